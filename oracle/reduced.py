@@ -1,0 +1,326 @@
+"""FP64 oracle of the reduced (slack-eliminated) IRLS + PCG method.
+
+TEST INFRASTRUCTURE ONLY -- never imported by the product path.
+
+What is computed (paper arXiv 2401.09961):
+
+* Wrapped gradients G^v, G^h of the observed phase X (Section 2, the
+  definitions before problem (prob:main)); the residue function W maps a
+  difference to [-pi, pi).
+* Edge weights C^v, C^h (Section 2 and the ``unwrap`` interface of Section
+  4.4): given per edge, else the smaller of the two endpoint pixel weights,
+  else 1.
+* The weighted L1 objective of problem (prob:main-matrix-form) and its
+  Huber smoothing H_eps = sum C h_eps(DU - G).  Eliminating the slacks of
+  problem (prob:soft-constraints) gives exactly this Huber form (Moreau
+  envelope of |.|), so H_eps is the objective IRLS decreases.
+* IRLS (structure of Algorithm 1): U^0 = 0; per iteration the weights
+  Omega = C / max(|DU - G|, eps), a preconditioned CG solve of
+  D^T Omega D U = D^T Omega G warm-started at the current U, then the mean
+  is removed (last step of Algorithm 1).
+* PCG as in Algorithm 2, matrix-free; stop when ||r|| <= tol ||b||.
+* Preconditioner: the U block of (eq:preconditioner-definition), the
+  unweighted Neumann Laplacian I (x) S^T S + T T^T (x) I, solved through its
+  eigendecomposition (eq:eigendecompositions) -- the eigenvectors are the
+  orthonormal DCT-II basis and the eigenvalues 2 - 2 cos(pi k / n) -- with
+  mode (0, 0) set to zero (the pseudo-inverse choice of Appendix B).  The
+  tau factor is dropped: CG iterates do not change when the preconditioner
+  is scaled by a positive constant.
+
+Pins (tests/test_oracle_pins.py): closed-form eigenpairs, dense matrix
+definitions of S, T and D^T Omega D, pseudo-inverse identities, one-step
+convergence for unit weights, dense least squares, the Itoh integration
+case, monotone decrease of H_eps, linear-programming brute force on small
+grids, the 2 x 2 single-loop closed form, and the paper-form cross-oracle.
+Parity unpinned: pointwise U when the L1 / Huber minimiser is not unique.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.fft
+
+TWO_PI = 2.0 * math.pi
+
+
+# ----------------------------------------------------------------------------
+# Problem data (Section 2)
+# ----------------------------------------------------------------------------
+def wrap(x):
+    """Residue of x modulo 2 pi in [-pi, pi): x - 2 pi floor((x + pi) / 2 pi)."""
+    x = np.asarray(x, dtype=np.float64)
+    return x - TWO_PI * np.floor((x + math.pi) / TWO_PI)
+
+
+def wrapped_gradients(X):
+    """G^v_{ij} = W(X_{i+1,j} - X_{ij}), G^h_{ij} = W(X_{i,j+1} - X_{ij})."""
+    X = np.asarray(X, dtype=np.float64)
+    return wrap(X[1:, :] - X[:-1, :]), wrap(X[:, 1:] - X[:, :-1])
+
+
+def edge_weights(N, M, w=None, Cv=None, Ch=None):
+    """Per-edge weights: explicit (Cv, Ch) win; else min of the endpoint
+    pixel weights; else unit weights."""
+    if Cv is not None or Ch is not None:
+        if Cv is None or Ch is None:
+            raise ValueError("Cv and Ch must be given together")
+        return np.asarray(Cv, np.float64), np.asarray(Ch, np.float64)
+    if w is not None:
+        w = np.asarray(w, dtype=np.float64)
+        return np.minimum(w[1:, :], w[:-1, :]), np.minimum(w[:, 1:], w[:, :-1])
+    return np.ones((N - 1, M)), np.ones((N, M - 1))
+
+
+# ----------------------------------------------------------------------------
+# Difference operators (matrices S and T of Section 2, Appendix A)
+# ----------------------------------------------------------------------------
+def diff_v(U):
+    """S U: vertical forward differences, (N-1) x M."""
+    return U[1:, :] - U[:-1, :]
+
+
+def diff_h(U):
+    """U T: horizontal forward differences, N x (M-1)."""
+    return U[:, 1:] - U[:, :-1]
+
+
+def div(Fv, Fh):
+    """D^T F = S^T F^v + F^h T^T (adjoint of the two difference maps)."""
+    N = Fv.shape[0] + 1
+    M = Fh.shape[1] + 1
+    q = np.zeros((N, M), dtype=np.float64)
+    q[:-1, :] -= Fv
+    q[1:, :] += Fv
+    q[:, :-1] -= Fh
+    q[:, 1:] += Fh
+    return q
+
+
+def apply_A(Ov, Oh, P):
+    """Weighted 5-point operator D^T Omega D applied to an N x M image."""
+    return div(Ov * diff_v(P), Oh * diff_h(P))
+
+
+def sparse_D(N, M):
+    """Explicit sparse D = [I_M kron S ; T^T kron I_N] acting on the
+    column-major vec of the paper's notation section."""
+    import scipy.sparse as sp
+    S = sp.diags([-np.ones(N - 1), np.ones(N - 1)], [0, 1], shape=(N - 1, N))
+    T = sp.diags([-np.ones(M - 1), np.ones(M - 1)], [0, -1], shape=(M, M - 1))
+    return sp.vstack([sp.kron(sp.identity(M), S), sp.kron(T.T, sp.identity(N))]).tocsr()
+
+
+def vec(A):
+    """Column-major vectorisation (the paper's vec)."""
+    return np.asarray(A).flatten(order="F")
+
+
+# ----------------------------------------------------------------------------
+# Objectives (problem (prob:main-matrix-form) and its Huber smoothing)
+# ----------------------------------------------------------------------------
+def residuals(U, Gv, Gh):
+    return diff_v(U) - Gv, diff_h(U) - Gh
+
+
+def l1_objective(U, Gv, Gh, Cv, Ch):
+    rv, rh = residuals(U, Gv, Gh)
+    return float(np.sum(Cv * np.abs(rv)) + np.sum(Ch * np.abs(rh)))
+
+
+def huber(r, eps):
+    a = np.abs(r)
+    return np.where(a <= eps, 0.5 * r * r / eps, a - 0.5 * eps)
+
+
+def huber_objective(U, Gv, Gh, Cv, Ch, eps):
+    rv, rh = residuals(U, Gv, Gh)
+    return float(np.sum(Cv * huber(rv, eps)) + np.sum(Ch * huber(rh, eps)))
+
+
+# ----------------------------------------------------------------------------
+# IRLS weight step: closed-form weights, right-hand side, objectives
+# ----------------------------------------------------------------------------
+def weight_step(U, Gv, Gh, Cv, Ch, eps):
+    """Omega = C / max(|DU - G|, eps); b = D^T Omega G; L1 and H_eps at U."""
+    rv, rh = residuals(U, Gv, Gh)
+    Ov = Cv / np.maximum(np.abs(rv), eps)
+    Oh = Ch / np.maximum(np.abs(rh), eps)
+    b = div(Ov * Gv, Oh * Gh)
+    L1 = float(np.sum(Cv * np.abs(rv)) + np.sum(Ch * np.abs(rh)))
+    H = float(np.sum(Cv * huber(rv, eps)) + np.sum(Ch * huber(rh, eps)))
+    return Ov, Oh, b, L1, H
+
+
+# ----------------------------------------------------------------------------
+# Preconditioner: eigendecomposition of the Neumann Laplacian (Section 3.3)
+# ----------------------------------------------------------------------------
+def laplacian_eigenvalues(n):
+    """Eigenvalues of S^T S (n x n): 2 - 2 cos(pi k / n), k = 0..n-1."""
+    k = np.arange(n, dtype=np.float64)
+    return 2.0 - 2.0 * np.cos(math.pi * k / n)
+
+
+def dct_basis(n):
+    """Orthonormal eigenvectors of S^T S: P[i, k] = c_k cos(pi k (2i+1) / 2n)."""
+    i = np.arange(n, dtype=np.float64)[:, None]
+    k = np.arange(n, dtype=np.float64)[None, :]
+    P = np.cos(math.pi * k * (2.0 * i + 1.0) / (2.0 * n)) * math.sqrt(2.0 / n)
+    P[:, 0] = math.sqrt(1.0 / n)
+    return P
+
+
+def _spectral_divide(Rh):
+    N, M = Rh.shape
+    lam = laplacian_eigenvalues(N)[:, None] + laplacian_eigenvalues(M)[None, :]
+    lam[0, 0] = np.inf  # pseudo-inverse: the constant mode maps to zero
+    return Rh / lam
+
+
+def apply_precond(R, workers=None):
+    """z = L^+ r for the unweighted Neumann Laplacian L, via the orthonormal
+    DCT-II (forward) and DCT-III (inverse) on both axes."""
+    Rh = scipy.fft.dctn(np.asarray(R, np.float64), type=2, norm="ortho",
+                        workers=workers)
+    return scipy.fft.idctn(_spectral_divide(Rh), type=2, norm="ortho",
+                           workers=workers)
+
+
+def apply_precond_explicit(R):
+    """Same map with the dense eigenbasis products P_N^T R P_M and
+    P_N Z' P_M^T written out (small grids only)."""
+    N, M = R.shape
+    PN, PM = dct_basis(N), dct_basis(M)
+    return PN @ _spectral_divide(PN.T @ R @ PM) @ PM.T
+
+
+# ----------------------------------------------------------------------------
+# Preconditioned conjugate gradient (Algorithm 2)
+# ----------------------------------------------------------------------------
+class Breakdown(RuntimeError):
+    pass
+
+
+def pcg(A, Minv, b, x0, tol, maxit):
+    """Algorithm 2 with a matrix-free A and preconditioner solve Minv.
+
+    Stops when ||r|| <= tol ||b|| (checked on the recursively updated
+    residual, before the preconditioner) or after maxit iterations.
+    Returns x and a dict with iterations, recursive and true relative
+    residuals.
+    """
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = b - A(x)
+    bnorm = math.sqrt(float(np.vdot(b, b)))
+    it = 0
+    if math.sqrt(float(np.vdot(r, r))) > tol * bnorm:
+        z = Minv(r)
+        p = z.copy()
+        rho = float(np.vdot(r, z))
+        while it < maxit:
+            q = A(p)
+            pq = float(np.vdot(p, q))
+            if not pq > 0.0:
+                raise Breakdown("p^T A p <= 0")
+            alpha = rho / pq
+            x += alpha * p
+            r -= alpha * q
+            it += 1
+            if math.sqrt(float(np.vdot(r, r))) <= tol * bnorm:
+                break
+            z = Minv(r)
+            rho_new = float(np.vdot(r, z))
+            beta = rho_new / rho
+            rho = rho_new
+            p = z + beta * p
+    rt = b - A(x)
+    denom = bnorm if bnorm > 0 else 1.0
+    return x, dict(iters=it,
+                   relres=math.sqrt(float(np.vdot(r, r))) / denom,
+                   true_relres=math.sqrt(float(np.vdot(rt, rt))) / denom)
+
+
+# ----------------------------------------------------------------------------
+# IRLS outer loop (Algorithm 1 structure, reduced form)
+# ----------------------------------------------------------------------------
+def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, eps=1e-3, iters=20,
+         tol=1e-8, maxit=100, U0=None, precond="dct", workers=None,
+         callback=None):
+    """Unwrap X (or given gradients G = (Gv, Gh)); return (U, history).
+
+    history[k] holds L1 and H_eps at U^k (before solve k) and the solve
+    statistics; history[iters] holds L1 and H_eps of the returned U.
+    """
+    if G is None:
+        Gv, Gh = wrapped_gradients(X)
+    else:
+        Gv, Gh = (np.asarray(g, np.float64) for g in G)
+    N, M = Gv.shape[0] + 1, Gh.shape[1] + 1
+    Cv, Ch = edge_weights(N, M, w, Cv, Ch)
+    if precond == "dct":
+        Minv = lambda r: apply_precond(r, workers=workers)  # noqa: E731
+    elif precond == "explicit":
+        Minv = apply_precond_explicit
+    elif precond == "none":
+        Minv = lambda r: r.copy()  # noqa: E731
+    else:
+        raise ValueError(precond)
+    U = np.zeros((N, M)) if U0 is None else np.array(U0, np.float64, copy=True)
+    hist = []
+    for k in range(iters):
+        Ov, Oh, b, L1, H = weight_step(U, Gv, Gh, Cv, Ch, eps)
+        U, info = pcg(lambda p: apply_A(Ov, Oh, p), Minv, b, U, tol, maxit)
+        U = U - U.mean()
+        rec = dict(k=k, L1=L1, H=H, **info)
+        hist.append(rec)
+        if callback is not None:
+            callback(rec, U)
+    hist.append(dict(k=iters, L1=l1_objective(U, Gv, Gh, Cv, Ch),
+                     H=huber_objective(U, Gv, Gh, Cv, Ch, eps)))
+    return U, hist
+
+
+# ----------------------------------------------------------------------------
+# Adjoint of the converged (frozen-weight) least-squares map
+# ----------------------------------------------------------------------------
+def frozen_weights(U, Gv, Gh, eps):
+    """omega_bar = 1 / max(|DU - G|, eps) at a converged U."""
+    rv, rh = residuals(U, Gv, Gh)
+    return 1.0 / np.maximum(np.abs(rv), eps), 1.0 / np.maximum(np.abs(rh), eps)
+
+
+def frozen_solve(Cv, Ch, Gv, Gh, wv, wh, tol=1e-14, maxit=5000, x0=None):
+    """U = argmin over mean-zero U of sum C omega_bar (DU - G)^2."""
+    Ov, Oh = Cv * wv, Ch * wh
+    b = div(Ov * Gv, Oh * Gh)
+    N, M = b.shape
+    x0 = np.zeros((N, M)) if x0 is None else x0
+    U, _ = pcg(lambda p: apply_A(Ov, Oh, p), apply_precond, b, x0, tol, maxit)
+    return U - U.mean()
+
+
+def adjoint(U, Gv, Gh, Cv, Ch, eps, gU, tol=1e-14, maxit=5000, weights=None):
+    """Gradients of a loss with dL/dU = gU through the frozen map.
+
+    U must solve the frozen system for the weights omega_bar, which are
+    ``weights`` = (wv, wh) if given, else 1 / max(|DU - G|, eps) at U (the
+    fixed point of converged IRLS).  lambda solves D^T Omega D lambda = gU - mean(gU); then per edge
+    g_Omega = -(D lambda) r, g_C = omega_bar g_Omega,
+    g_G = Omega (D lambda), and g_X = D^T g_G (the residue map W has
+    derivative 1 away from its jumps).
+    """
+    rv, rh = residuals(U, Gv, Gh)
+    wv, wh = frozen_weights(U, Gv, Gh, eps) if weights is None else weights
+    Ov, Oh = Cv * wv, Ch * wh
+    g = np.asarray(gU, np.float64)
+    g = g - g.mean()
+    lam, _ = pcg(lambda p: apply_A(Ov, Oh, p), apply_precond, g,
+                 np.zeros_like(g), tol, maxit)
+    lam -= lam.mean()
+    dv, dh = diff_v(lam), diff_h(lam)
+    gOv, gOh = -dv * rv, -dh * rh
+    gCv, gCh = wv * gOv, wh * gOh
+    gGv, gGh = Ov * dv, Oh * dh
+    gX = div(gGv, gGh)
+    return dict(lam=lam, gCv=gCv, gCh=gCh, gGv=gGv, gGh=gGh, gX=gX,
+                wv=wv, wh=wh)
