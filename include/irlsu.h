@@ -1,0 +1,218 @@
+/*
+ * irlsu -- IRLS + PCG weighted-L1 phase unwrapping on AMD Instinct MI355X.
+ *
+ * C ABI of the library.  Plain pointers and sizes only; every pointer named
+ * "device" is HIP device memory, every other pointer is host memory.  No
+ * function throws; every function returns an irlsu_status.  All work is
+ * enqueued on the caller's HIP stream (passed as void*, a hipStream_t; NULL
+ * is the default stream) and is asynchronous unless stated otherwise.
+ *
+ * The method (paper: Dubois-Taine, Akiki, d'Aspremont, "Iteratively
+ * Reweighted Least Squares for Phase Unwrapping", arXiv 2401.09961):
+ *
+ *   minimise over mean-zero U   sum C^v |S U - G^v| + sum C^h |U T - G^h|
+ *
+ * (Section 2, problem (prob:main-matrix-form)), with G the wrapped phase
+ * differences of the observed phase X and C > 0 per-edge weights.  The
+ * library runs the slack-eliminated form of the paper's IRLS (Algorithm 1):
+ * eliminating V^v, V^h from the linear system of Proposition 1 leaves the
+ * weighted 5-point system D^T Omega D U = D^T Omega G, here with IRLS weights
+ * Omega = C / max(|DU - G|, eps), which minimises sum C h_eps(DU - G) (the
+ * Huber function, the Moreau envelope that the paper's penalty produces).
+ * Each system is solved by preconditioned CG (Algorithm 2) with the U block
+ * of the block-diagonal preconditioner of Section 3.3: the Neumann
+ * Laplacian, inverted through its eigendecomposition -- the dense products
+ * P_S^T R P_T and P_S Z' P_T^T of Section 3.3, where P is the orthonormal
+ * DCT-II basis -- with the zero mode removed (Appendix B).
+ *
+ * Internal layout.  Step-level entry points take images in the plan's
+ * internal layout: Np rows by ld columns, row-major, columns contiguous,
+ * with Np >= N and ld >= M padded to the plan's tile size (irlsu_plan_info).
+ * Pixel (i, j) is element i * ld + j.  Vertical edge (i, j) joins pixels
+ * (i, j) and (i+1, j); horizontal edge (i, j) joins (i, j) and (i, j+1).
+ * Edge arrays use the same Np x ld shape; entries of edges that do not exist
+ * (row N-1 and below for vertical edges, column M-1 and beyond for
+ * horizontal edges) and all padding must be zero.  The element type is
+ * double for IRLSU_F64 plans and float for all other plans.
+ */
+#ifndef IRLSU_H
+#define IRLSU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum irlsu_status {
+  IRLSU_OK = 0,
+  IRLSU_NOT_CONVERGED = 1,     /* warning: a PCG solve hit pcg_max */
+  IRLSU_ERR_INVALID_ARG = -1,  /* null pointer, bad stride, bad parameter */
+  IRLSU_ERR_SHAPE = -2,        /* N < 2 or M < 2, or sizes do not match the plan */
+  IRLSU_ERR_NONFINITE = -3,    /* NaN or Inf in X or in the weights */
+  IRLSU_ERR_BAD_WEIGHTS = -4,  /* a weight is <= 0 */
+  IRLSU_ERR_BREAKDOWN = -5,    /* PCG breakdown: p^T A p <= 0 */
+  IRLSU_ERR_HIP = -6,          /* a HIP runtime call failed */
+  IRLSU_ERR_OOM = -7,          /* plan allocation failed (nothing leaked) */
+  IRLSU_ERR_UNSUPPORTED = -8,  /* precision not built into this library */
+  IRLSU_ERR_WORKSPACE = -9     /* workspace missing or smaller than required */
+} irlsu_status;
+
+typedef enum irlsu_precision {
+  IRLSU_F64 = 0,        /* FP64 vectors, FP64 MFMA preconditioner */
+  IRLSU_F32 = 1,        /* FP32 vectors, FP32 MFMA preconditioner */
+  IRLSU_MIXED_BF16 = 2, /* FP32 vectors, BF16 MFMA preconditioner (FP32 accumulate) */
+  IRLSU_MIXED_F16 = 3   /* FP32 vectors, FP16 MFMA preconditioner (FP32 accumulate) */
+} irlsu_precision;
+
+typedef struct irlsu_plan irlsu_plan;
+
+/* Solver parameters (Section 4.4 names in brackets). */
+typedef struct irlsu_params {
+  double eps;              /* IRLS weight floor; Omega = C / max(|r|, eps). 1e-3 */
+  double pcg_rtol;         /* stop PCG when ||r|| <= pcg_rtol ||b||. 1e-8 (F64), 1e-6 otherwise */
+  double l1_target;        /* > 0: stop IRLS at the first U^k with L1(U^k) <= l1_target */
+  int32_t irls_iters;      /* number of IRLS iterations. 20 */
+  int32_t pcg_max;         /* maximum PCG iterations per IRLS iteration. 100 */
+  int32_t true_res_every;  /* recompute r = b - A u every this many PCG iterations; 0 = never. 32 */
+  int32_t poll_every;      /* host reads the device convergence flag every this many PCG iterations. 4 */
+  int32_t flexible;        /* CG beta: 0 = rho_new / rho (Algorithm 2), 1 = flexible
+                              (z_new . (r_new - r_old) / rho), -1 = flexible for mixed plans */
+  int32_t reserved[7];
+} irlsu_params;
+
+#define IRLSU_MAX_IRLS 256
+
+typedef struct irlsu_iter_stats {
+  double L1;          /* weighted L1 objective at U^k (before solve k) */
+  double H;           /* Huber objective sum C h_eps(DU - G) at U^k */
+  double relres;      /* ||r|| / ||b|| of the recursive residual when solve k stopped */
+  int32_t pcg_iters;  /* PCG iterations of solve k */
+  int32_t status;     /* irlsu_status of solve k */
+} irlsu_iter_stats;
+
+typedef struct irlsu_stats {
+  int32_t irls_done;      /* IRLS iterations performed */
+  int32_t pcg_total;      /* PCG iterations over all solves */
+  int32_t target_hit;     /* 1 if l1_target was reached */
+  int32_t status;         /* overall status */
+  double L1_final;        /* L1 of the returned U */
+  double H_final;         /* Huber objective of the returned U */
+  irlsu_iter_stats iter[IRLSU_MAX_IRLS];
+} irlsu_stats;
+
+typedef struct irlsu_plan_desc {
+  int64_t N, M;           /* image rows, columns */
+  int64_t Np, ld;         /* padded rows, padded row stride (elements) */
+  int32_t precision;      /* irlsu_precision */
+  int32_t elem_bytes;     /* 8 for F64 plans, 4 otherwise */
+  size_t workspace_bytes; /* workspace needed by irlsu_unwrap and the step functions */
+  size_t plan_bytes;      /* device memory owned by the plan (basis, eigenvalues) */
+} irlsu_plan_desc;
+
+/* Human-readable name of a status code (static storage). */
+const char* irlsu_status_string(irlsu_status st);
+
+/* Fill *p with the defaults for precision prec. */
+irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec);
+
+/* Create a plan for N x M images.  Allocates and fills the orthonormal DCT-II
+ * bases P_N, P_M and the Laplacian eigenvalues 2 - 2 cos(pi k / n) on the
+ * current HIP device (Section 3.3, eq:eigendecompositions: computed once,
+ * reused by every PCG iteration).  Synchronises the stream before returning.
+ * Errors: ERR_INVALID_ARG (out null), ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM,
+ * ERR_HIP.  On error *out is NULL and nothing is leaked. */
+irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M,
+                               irlsu_precision prec, void* stream);
+
+/* Release a plan and its device memory.  NULL is accepted. */
+irlsu_status irlsu_plan_destroy(irlsu_plan* plan);
+
+/* Describe a plan (host struct). */
+irlsu_status irlsu_plan_info(const irlsu_plan* plan, irlsu_plan_desc* out);
+
+/* Workspace bytes needed by irlsu_unwrap and the step functions (0 on NULL). */
+size_t irlsu_workspace_bytes(const irlsu_plan* plan);
+
+/* Unwrap one image (the whole hot path: setup, IRLS weight updates, PCG with
+ * the DCT preconditioner, mean removal).  Section 2 problem, Algorithm 1.
+ *
+ *   X       device, N x M wrapped phase, row stride ldx >= M elements.
+ *   w       device or NULL: N x M per-pixel weights > 0 (stride ldx); edge
+ *           weight = min of its two pixel weights.
+ *   Cv, Ch  device or NULL (both or neither; override w): per-edge weights
+ *           > 0, Cv (N-1) x M with stride ldcv >= M, Ch N x (M-1) with
+ *           stride ldch >= M-1.  With no weights, C = 1.
+ *   U0      device or NULL: N x M warm start (stride ldu), e.g. to resume.
+ *   params  host or NULL (defaults for the plan's precision).
+ *   U       device out: N x M mean-zero unwrapped phase (stride ldu >= M).
+ *           May alias U0.
+ *   workspace, workspace_bytes: device scratch owned by the caller, at least
+ *           irlsu_workspace_bytes(plan); contents are overwritten.
+ *   stats   host or NULL.
+ *
+ * Element type of X, w, Cv, Ch, U0, U: double for F64 plans, float otherwise.
+ * The call synchronises the stream once after setup (input validation) and
+ * whenever it reads the device convergence flag (every poll_every PCG
+ * iterations) or the objectives (every IRLS iteration when stats or
+ * l1_target are given).  Returns OK, NOT_CONVERGED (a solve hit pcg_max;
+ * U is still valid), or an error: ERR_INVALID_ARG, ERR_SHAPE,
+ * ERR_NONFINITE, ERR_BAD_WEIGHTS, ERR_BREAKDOWN, ERR_WORKSPACE, ERR_HIP. */
+irlsu_status irlsu_unwrap(irlsu_plan* plan,
+                          const void* X, int64_t ldx,
+                          const void* w,
+                          const void* Cv, int64_t ldcv,
+                          const void* Ch, int64_t ldch,
+                          const void* U0,
+                          const irlsu_params* params,
+                          void* U, int64_t ldu,
+                          void* workspace, size_t workspace_bytes,
+                          irlsu_stats* stats, void* stream);
+
+/* ---- Step-level entry points (internal layout, see top of file) -------- */
+
+/* Setup (Section 2): Gv, Gh = wrapped differences W(d) = d - 2 pi
+ * floor((d + pi) / 2 pi) of X computed in FP64, stored in the plan's
+ * element type; CvI, ChI = per-edge weights by the irlsu_unwrap rules.  All
+ * four outputs are device, internal layout.  Input arguments as in
+ * irlsu_unwrap.  Also validates the inputs: *flags (device int32) gets bit 0
+ * for a non-finite value and bit 1 for a weight <= 0 (caller zeroes it). */
+irlsu_status irlsu_setup(const irlsu_plan* plan,
+                         const void* X, int64_t ldx, const void* w,
+                         const void* Cv, int64_t ldcv,
+                         const void* Ch, int64_t ldch,
+                         void* Gv, void* Gh, void* CvI, void* ChI,
+                         int32_t* flags, void* stream);
+
+/* IRLS weight step (closed-form weights, Section 3.1): with r = DU - G,
+ * Ov/Oh = C / max(|r|, eps), b = D^T (Omega G), and objectives[0..2] =
+ * {sum C |r|, sum C h_eps(r), ||b||^2} accumulated in FP64 (device doubles).
+ * All images device, internal layout.  workspace as for irlsu_unwrap. */
+irlsu_status irlsu_weights(const irlsu_plan* plan, double eps,
+                           const void* U, const void* Gv, const void* Gh,
+                           const void* CvI, const void* ChI,
+                           void* Ov, void* Oh, void* b, double* objectives,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* Weighted 5-point operator q = D^T Omega D p (the U block of the system of
+ * Proposition 1 after slack elimination; Appendix A gives S^T S and T T^T).
+ * p, q, Ov, Oh device, internal layout; q must not alias p.  pq (device
+ * double, nullable) receives sum p q accumulated in FP64. */
+irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* Oh,
+                            const void* p, void* q, double* pq,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Preconditioner z = L^+ r (Section 3.3, Appendix B): orthonormal DCT-II of
+ * both axes as dense products on MFMA, division by lambda_k + mu_l, mode
+ * (0,0) set to zero, DCT-III back.  r, z device, internal layout, may not
+ * alias.  rz (device double, nullable) receives sum r z in FP64.  For mixed
+ * plans the products run in BF16 / FP16 with FP32 accumulation. */
+irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRLSU_H */

@@ -1,0 +1,306 @@
+"""irlsu: IRLS + PCG weighted-L1 phase unwrapping on AMD MI355X (gfx950).
+
+Thin Python binding of the C ABI declared in ``include/irlsu.h``: argument
+marshalling only.  Every step of the computation runs in the HIP kernels of
+``lib/libirlsu.so``; PyTorch provides device memory and the stream.  There
+is no CPU fallback: if the library is missing, loading fails loudly.
+
+Method: Dubois-Taine, Akiki, d'Aspremont, "Iteratively Reweighted Least
+Squares for Phase Unwrapping", arXiv 2401.09961 (Section 2 problem,
+Algorithm 1 IRLS, Algorithm 2 PCG, Section 3.3 preconditioner).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+__all__ = [
+    "IrlsuError", "Params", "Stats", "Plan", "unwrap", "load_library",
+    "library_path", "PRECISIONS", "DECLARED_SYMBOLS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "lib", "libirlsu.so")
+
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+IRLSU_MAX_IRLS = 256
+
+# every function declared in include/irlsu.h
+DECLARED_SYMBOLS = (
+    "irlsu_status_string", "irlsu_params_default", "irlsu_plan_create",
+    "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
+    "irlsu_unwrap", "irlsu_setup", "irlsu_weights", "irlsu_operator",
+    "irlsu_precond",
+)
+
+STATUS = {
+    0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID_ARG", -2: "ERR_SHAPE",
+    -3: "ERR_NONFINITE", -4: "ERR_BAD_WEIGHTS", -5: "ERR_BREAKDOWN",
+    -6: "ERR_HIP", -7: "ERR_OOM", -8: "ERR_UNSUPPORTED", -9: "ERR_WORKSPACE",
+}
+
+
+class IrlsuError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"irlsu status {code} ({self.name}) {msg}".strip())
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double), ("pcg_rtol", ctypes.c_double),
+        ("l1_target", ctypes.c_double), ("irls_iters", ctypes.c_int32),
+        ("pcg_max", ctypes.c_int32), ("true_res_every", ctypes.c_int32),
+        ("poll_every", ctypes.c_int32), ("flexible", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [("L1", ctypes.c_double), ("H", ctypes.c_double),
+                ("relres", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("irls_done", ctypes.c_int32), ("pcg_total", ctypes.c_int32),
+        ("target_hit", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("L1_final", ctypes.c_double), ("H_final", ctypes.c_double),
+        ("iter", IterStats * IRLSU_MAX_IRLS),
+    ]
+
+    def to_dict(self):
+        n = self.irls_done
+        hist = [dict(k=k, L1=self.iter[k].L1, H=self.iter[k].H,
+                     relres=self.iter[k].relres, iters=self.iter[k].pcg_iters,
+                     status=self.iter[k].status) for k in range(min(n + 1, IRLSU_MAX_IRLS))]
+        return dict(irls_done=n, pcg_total=self.pcg_total,
+                    target_hit=bool(self.target_hit), status=self.status,
+                    L1_final=self.L1_final, H_final=self.H_final, history=hist)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64),
+                ("Np", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t), ("plan_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libirlsu.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I64, I32, D, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "irlsu_status_string": (ctypes.c_char_p, [I32]),
+        "irlsu_params_default": (I32, [ctypes.POINTER(Params), I32]),
+        "irlsu_plan_create": (I32, [ctypes.POINTER(P), I64, I64, I32, P]),
+        "irlsu_plan_destroy": (I32, [P]),
+        "irlsu_plan_info": (I32, [P, ctypes.POINTER(PlanDesc)]),
+        "irlsu_workspace_bytes": (SZ, [P]),
+        "irlsu_unwrap": (I32, [P, P, I64, P, P, I64, P, I64, P, ctypes.POINTER(Params),
+                               P, I64, P, SZ, ctypes.POINTER(Stats), P]),
+        "irlsu_setup": (I32, [P, P, I64, P, P, I64, P, I64, P, P, P, P, P, P]),
+        "irlsu_weights": (I32, [P, D, P, P, P, P, P, P, P, P, P, P, SZ, P]),
+        "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
+        "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code, what=""):
+    if code < 0:
+        raise IrlsuError(code, what)
+    return code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_params(precision="f32") -> Params:
+    p = Params()
+    _check(load_library().irlsu_params_default(ctypes.byref(p), PRECISIONS[precision]))
+    return p
+
+
+class Plan:
+    """A plan for N x M images at one precision, bound to a torch device.
+
+    Owns the device basis tables (through the library) and a workspace
+    tensor allocated by torch.
+    """
+
+    def __init__(self, N: int, M: int, precision: str = "f32", device=None):
+        import torch
+        self.lib = load_library()
+        self.precision = precision
+        self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
+                       else torch.device(device))
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _check(self.lib.irlsu_plan_create(ctypes.byref(h), int(N), int(M),
+                                              PRECISIONS[precision], _stream()), "plan_create")
+            self.handle = h
+            d = PlanDesc()
+            _check(self.lib.irlsu_plan_info(h, ctypes.byref(d)))
+            self.desc = d
+            self.workspace = torch.empty(int(d.workspace_bytes), dtype=torch.uint8, device=self.device)
+        self.N, self.M, self.Np, self.ld = d.N, d.M, d.Np, d.ld
+        self.dtype = torch.float64 if d.elem_bytes == 8 else torch.float32
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.irlsu_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- layout helpers (internal layout: Np x ld, zero padded) --------
+    def to_internal(self, A, rows=None, cols=None, dtype=None):
+        import torch
+        out = torch.zeros((self.Np, self.ld), dtype=dtype or self.dtype, device=self.device)
+        r = A.shape[0] if rows is None else rows
+        c = A.shape[1] if cols is None else cols
+        out[:r, :c] = A[:r, :c].to(out.dtype)
+        return out
+
+    def from_internal(self, A, rows=None, cols=None):
+        return A[: (rows or self.N), : (cols or self.M)]
+
+    # ---- whole path -----------------------------------------------------
+    def unwrap(self, X, weights=None, *, Cv=None, Ch=None, U0=None, params: Optional[Params] = None,
+               out=None, stats: bool = False):
+        import torch
+        X = _mat(X, self.dtype)
+        assert X.shape == (self.N, self.M), "X shape does not match the plan"
+        w = None if weights is None else _mat(weights, self.dtype, like=X)
+        Cv_t = None if Cv is None else _mat(Cv, self.dtype)
+        Ch_t = None if Ch is None else _mat(Ch, self.dtype)
+        U = out if out is not None else torch.empty((self.N, self.M), dtype=self.dtype, device=self.device)
+        U0_t = None if U0 is None else _mat(U0, self.dtype, like=U)
+        st = Stats() if stats else None
+        code = self.lib.irlsu_unwrap(
+            self.handle, _ptr(X), X.stride(0), _ptr(w),
+            _ptr(Cv_t), Cv_t.stride(0) if Cv_t is not None else 0,
+            _ptr(Ch_t), Ch_t.stride(0) if Ch_t is not None else 0,
+            _ptr(U0_t), ctypes.byref(params) if params is not None else None,
+            _ptr(U), U.stride(0), _ptr(self.workspace), self.workspace.numel(),
+            ctypes.byref(st) if st is not None else None, _stream())
+        _check(code, "unwrap")
+        if stats:
+            d = st.to_dict()
+            d["code"] = code
+            return U, d
+        return U
+
+    # ---- step-level entry points -----------------------------------------
+    def setup(self, X, weights=None, Cv=None, Ch=None):
+        import torch
+        X = _mat(X, self.dtype)
+        w = None if weights is None else _mat(weights, self.dtype, like=X)
+        Cv_t = None if Cv is None else _mat(Cv, self.dtype)
+        Ch_t = None if Ch is None else _mat(Ch, self.dtype)
+        outs = [torch.empty((self.Np, self.ld), dtype=self.dtype, device=self.device) for _ in range(4)]
+        flags = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _check(self.lib.irlsu_setup(
+            self.handle, _ptr(X), X.stride(0), _ptr(w),
+            _ptr(Cv_t), Cv_t.stride(0) if Cv_t is not None else 0,
+            _ptr(Ch_t), Ch_t.stride(0) if Ch_t is not None else 0,
+            *[_ptr(o) for o in outs], _ptr(flags), _stream()), "setup")
+        return (*outs, flags)
+
+    def weights(self, eps, U, Gv, Gh, Cv, Ch):
+        import torch
+        assert U.dtype == torch.float64 and U.shape == (self.Np, self.ld)
+        outs = [torch.empty((self.Np, self.ld), dtype=self.dtype, device=self.device) for _ in range(3)]
+        obj = torch.zeros(3, dtype=torch.float64, device=self.device)
+        _check(self.lib.irlsu_weights(
+            self.handle, float(eps), _ptr(U), _ptr(Gv), _ptr(Gh), _ptr(Cv), _ptr(Ch),
+            *[_ptr(o) for o in outs], _ptr(obj), _ptr(self.workspace), self.workspace.numel(),
+            _stream()), "weights")
+        return (*outs, obj)
+
+    def operator(self, Ov, Oh, p):
+        import torch
+        q = torch.empty_like(p)
+        pq = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(self.lib.irlsu_operator(self.handle, _ptr(Ov), _ptr(Oh), _ptr(p), _ptr(q), _ptr(pq),
+                                       _ptr(self.workspace), self.workspace.numel(), _stream()),
+               "operator")
+        return q, pq
+
+    def precond(self, r):
+        import torch
+        z = torch.empty_like(r)
+        rz = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(self.lib.irlsu_precond(self.handle, _ptr(r), _ptr(z), _ptr(rz),
+                                      _ptr(self.workspace), self.workspace.numel(), _stream()),
+               "precond")
+        return z, rz
+
+
+def _mat(A, dtype, like=None):
+    import torch
+    if not isinstance(A, torch.Tensor):
+        A = torch.as_tensor(A)
+    dev = like.device if like is not None else (A.device if A.is_cuda else torch.device("cuda"))
+    A = A.to(device=dev, dtype=dtype)
+    if A.dim() != 2 or A.stride(1) != 1:
+        A = A.contiguous()
+    if like is not None and A.stride(0) != like.stride(0):
+        A = A.contiguous()
+        assert A.stride(0) == like.stride(0), "weights must share the stride of X"
+    return A
+
+
+def unwrap(X, weights=None, *, Cv=None, Ch=None, precision: str = "f32", params=None,
+           stats=False, plan: Optional[Plan] = None):
+    """Unwrap a wrapped phase image on the current GPU.
+
+    X: N x M tensor (float64 for precision "f64", float32 otherwise);
+    weights: optional per-pixel weights; Cv, Ch: optional per-edge weights
+    ((N-1) x M and N x (M-1)).  Returns the mean-zero unwrapped U (and a stats
+    dict with ``stats=True``).
+    """
+    import torch
+    if not isinstance(X, torch.Tensor):
+        X = torch.as_tensor(X)
+    N, M = X.shape
+    own = plan is None
+    if own:
+        plan = Plan(N, M, precision)
+    try:
+        return plan.unwrap(X, weights, Cv=Cv, Ch=Ch, params=params, stats=stats)
+    finally:
+        if own:
+            plan.close()

@@ -1,0 +1,129 @@
+// Shared definitions of the irlsu HIP kernels (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "irlsu.h"
+
+namespace irlsu {
+
+constexpr int kThreads = 256;          // every kernel runs 4 wave64s per block
+constexpr int kMaxPartials = 16384;    // per-block partial sums per quantity
+constexpr int kTilePad = 128;          // internal rows / row stride multiple
+
+// Slots of the per-plan device scalar array (double).
+enum Scalar : int {
+  SC_RHO = 0,      // [2] rho_l = r_l . z_l, double-buffered by iteration parity
+  SC_ALPHA = 2,    // [2] alpha_l, double-buffered by parity
+  SC_BETA = 4,
+  SC_PQ = 5,
+  SC_RR = 6,       // ||r||^2 of the last reduced residual
+  SC_BB = 7,       // ||b||^2
+  SC_L1 = 8,
+  SC_H = 9,
+  SC_MEAN = 10,
+  SC_TOL2 = 11,    // pcg_rtol^2
+  SC_ZSUM = 12,
+  SC_COUNT = 32
+};
+
+// Slots of the per-plan device flag array (int32).
+enum Flag : int {
+  FL_DONE = 0,     // PCG of the current IRLS iteration has stopped
+  FL_ITERS = 1,    // PCG iterations performed
+  FL_STATUS = 2,   // bit 0: breakdown
+  FL_INPUT = 3,    // bit 0: non-finite input, bit 1: weight <= 0
+  FL_COUNT = 16
+};
+
+// Partial-sum slots: part[slot * kMaxPartials + block].
+enum Part : int {
+  PT_A = 0,        // first quantity of the producing kernel
+  PT_B = 1,
+  PT_C = 2,
+  PT_D = 3,
+  PT_COUNT = 4
+};
+
+// Quantities by slot for each producer:
+//   weights:  A = sum C|r|, B = sum C h_eps(r), C = ||b||^2
+//   residual/axpy: A = ||r||^2, B = sum r
+//   stencil:  C = p . q            (kept apart from the residual slots)
+//   precond:  D = z . r, and PT_Q_ZQ / PT_Q_ZS below
+enum PartRole : int {
+  PR_L1 = PT_A, PR_H = PT_B, PR_BB = PT_C,
+  PR_RR = PT_A, PR_RSUM = PT_B,
+  PR_PQ = PT_C,
+  PR_ZR = PT_D,
+};
+constexpr int kPartSlots = 7;   // A..D plus precond's z.q and sum z
+constexpr int PR_ZQ = 4;
+constexpr int PR_ZS = 5;
+constexpr int PR_AUX = 6;
+
+struct DevState {
+  double* sc;       // SC_COUNT doubles
+  int32_t* fl;      // FL_COUNT ints
+  double* part;     // kPartSlots * kMaxPartials doubles
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// Deterministic block sum of NV doubles; the result is returned in every
+// thread.  Fixed shuffle tree inside each wave, then waves summed in order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double red[NV][kThreads / 64];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = wave_sum(v[k]);
+    if (lane == 0) red[k][wid] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s += red[k][w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Reduce n partials of one slot in a fixed order; identical in every block.
+__device__ __forceinline__ double reduce_slot(const double* part, int slot, int n) {
+  const double* p = part + (size_t)slot * kMaxPartials;
+  double s[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += kThreads) s[0] += p[i];
+  block_sum<1>(s);
+  return s[0];
+}
+
+__device__ __forceinline__ int linear_block() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+__device__ __forceinline__ int nblocks() {
+  return gridDim.x * gridDim.y * gridDim.z;
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partials(double* part, const int (&slots)[NV], double (&v)[NV]) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+    const int b = linear_block();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[(size_t)slots[k] * kMaxPartials + b] = v[k];
+  }
+}
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace irlsu

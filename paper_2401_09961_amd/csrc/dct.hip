@@ -1,0 +1,429 @@
+// Preconditioner z = L^+ r of Section 3.3: with the eigendecompositions
+// S^T S = P_N Lambda_N P_N^T and T T^T = P_M Lambda_M P_M^T (P the orthonormal
+// DCT-II basis), z = P_N [ (P_N^T r P_M) ./ (lambda_k + mu_l) ] P_M^T, mode
+// (0,0) set to zero (the pseudo-inverse choice of Appendix B).  The paper
+// names the two dense products as the bottleneck; here they are four dense
+// GEMMs on the MFMA units, every one in "NT" form (both operands contiguous
+// along the contraction index), chaining transposed and direct stores:
+//
+//   G1  T1^T[l][i] = sum_j r[i][j]   P_M[j][l]      (A = r, B = P_M^T)
+//   G2  T2^T[l][k] = sum_i T1^T[l][i] P_N[i][k] / (lambda_k + mu_l)
+//   G3  T3[i][l]   = sum_k T2^T[l][k] P_N[i][k]     (B = P_N)
+//   G4  z[i][j]    = sum_l T3[i][l]  P_M[j][l]      (B = P_M), epilogue
+//                    partial sums z.r, z.q, sum z in FP64
+//
+// Operand precisions: FP64 (v_mfma_f64_16x16x4f64), FP32
+// (v_mfma_f32_32x32x2f32), BF16 / FP16 (v_mfma_f32_32x32x16_{bf16,f16}) with
+// FP32 accumulation; intermediates are stored in the operand type.
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace irlsu {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class OT>
+struct Mfma;
+
+// Result layout of the 32 x 32 instructions: accumulator e of lane l holds
+// row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32 (RS = 1: the four values
+// of a group are consecutive rows).  The FP64 16 x 16 x 4 instruction holds
+// row 4 e + l / 16, column l % 16 (RS = 4).
+template <>
+struct Mfma<__bf16> {
+  static constexpr int TM = 32, KPL = 8, TK = 16, NACC = 16, RS = 1;
+  __device__ static int row0(int g, int lane) { return 8 * g + 4 * (lane / 32); }
+  using frag_t = bf16x8;
+  using acc_t = f32x16;
+  using acc_e = float;
+  __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<_Float16> {
+  static constexpr int TM = 32, KPL = 8, TK = 16, NACC = 16, RS = 1;
+  __device__ static int row0(int g, int lane) { return 8 * g + 4 * (lane / 32); }
+  using frag_t = f16x8;
+  using acc_t = f32x16;
+  using acc_e = float;
+  __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  static constexpr int TM = 32, KPL = 1, TK = 2, NACC = 16, RS = 1;
+  __device__ static int row0(int g, int lane) { return 8 * g + 4 * (lane / 32); }
+  using frag_t = float;
+  using acc_t = f32x16;
+  using acc_e = float;
+  __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<double> {
+  static constexpr int TM = 16, KPL = 1, TK = 4, NACC = 4, RS = 4;
+  __device__ static int row0(int, int lane) { return lane / 16; }
+  using frag_t = double;
+  using acc_t = f64x4;
+  using acc_e = double;
+  __device__ static acc_t mma(frag_t a, frag_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// Tile shapes per operand type: block BM x BN, depth BK, 4 waves in 2 x 2.
+template <class OT>
+struct Tile {
+  static constexpr int BM = 128, BN = 128, BK = 64;
+};
+template <>
+struct Tile<float> {
+  static constexpr int BM = 128, BN = 128, BK = 32;
+};
+template <>
+struct Tile<double> {
+  static constexpr int BM = 64, BN = 64, BK = 16;
+};
+
+
+struct GemmCtl {
+  DevState st;
+  int check_done;   // return when the PCG done flag is set
+  int check_conv;   // G1: reduce ||r||^2 partials and stop on convergence
+  int nparts_rr;
+};
+
+// C[m][n] = sum_k A[m][k] B[n][k]; A is AT (converted to OT while staging),
+// B is OT.  M, N multiples of BM, BN; K a multiple of BK.
+template <class OT, class AT, class Epi>
+__global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict__ A, int64_t lda,
+                                                           const OT* __restrict__ B, int64_t ldb,
+                                                           int64_t K, float ascale, Epi epi,
+                                                           GemmCtl ctl) {
+  using F = Mfma<OT>;
+  constexpr int BM = Tile<OT>::BM, BN = Tile<OT>::BN, BK = Tile<OT>::BK;
+  constexpr int TM = F::TM;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / TM, FN = WN / TM;
+  constexpr int PAD = 16 / (int)sizeof(OT);
+  constexpr int LDS_LD = BK + PAD;
+  // staging: chunks of CH elements along K
+  constexpr int CH = (sizeof(OT) <= 2) ? 8 : (16 / (int)sizeof(OT));
+  constexpr int A_CHUNKS = BM * BK / CH / kThreads;
+  constexpr int B_CHUNKS = BN * BK / CH / kThreads;
+  static_assert(A_CHUNKS * CH * kThreads == BM * BK, "A tile staging");
+  static_assert(B_CHUNKS * CH * kThreads == BN * BK, "B tile staging");
+
+  if (ctl.check_done && ctl.st.fl[FL_DONE]) return;
+  if (ctl.check_conv) {
+    const double rr = reduce_slot(ctl.st.part, PR_RR, ctl.nparts_rr);
+    const double thr = ctl.st.sc[SC_TOL2] * ctl.st.sc[SC_BB];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctl.st.sc[SC_RR] = rr;
+    if (rr <= thr) {
+      if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctl.st.fl[FL_DONE] = 1;
+      return;
+    }
+  }
+
+  __shared__ __attribute__((aligned(16))) OT As[BM * LDS_LD];
+  __shared__ __attribute__((aligned(16))) OT Bs[BN * LDS_LD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+
+  typename F::acc_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int e = 0; e < F::NACC; ++e) acc[a][b][e] = 0;
+
+  AT ra[A_CHUNKS][CH];
+  OT rb[B_CHUNKS][CH];
+
+  auto load_tile = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < A_CHUNKS; ++c) {
+      const int idx = tid + c * kThreads;
+      const int row = idx / (BK / CH);
+      const int kc = (idx % (BK / CH)) * CH;
+      const AT* src = A + (m0 + row) * lda + k0 + kc;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) ra[c][e] = src[e];
+    }
+#pragma unroll
+    for (int c = 0; c < B_CHUNKS; ++c) {
+      const int idx = tid + c * kThreads;
+      const int row = idx / (BK / CH);
+      const int kc = (idx % (BK / CH)) * CH;
+      const OT* src = B + (n0 + row) * ldb + k0 + kc;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) rb[c][e] = src[e];
+    }
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int c = 0; c < A_CHUNKS; ++c) {
+      const int idx = tid + c * kThreads;
+      const int row = idx / (BK / CH);
+      const int kc = (idx % (BK / CH)) * CH;
+      OT tmp[CH];
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        if constexpr (std::is_same<OT, AT>::value)
+          tmp[e] = ra[c][e];
+        else
+          tmp[e] = (OT)((float)ra[c][e] * ascale);
+      }
+#pragma unroll
+      for (int e = 0; e < CH; ++e) As[row * LDS_LD + kc + e] = tmp[e];
+    }
+#pragma unroll
+    for (int c = 0; c < B_CHUNKS; ++c) {
+      const int idx = tid + c * kThreads;
+      const int row = idx / (BK / CH);
+      const int kc = (idx % (BK / CH)) * CH;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) Bs[row * LDS_LD + kc + e] = rb[c][e];
+    }
+  };
+
+  const int64_t nk = K / BK;
+  load_tile(0);
+  store_tile();
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / F::TK; ++ks) {
+      typename F::frag_t fa[FM], fb[FN];
+      const int kk = ks * F::TK + F::KPL * (lane / TM);
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const int row = wm * WM + a * TM + (lane % TM);
+        fa[a] = *reinterpret_cast<const typename F::frag_t*>(&As[row * LDS_LD + kk]);
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int row = wn * WN + b * TM + (lane % TM);
+        fb[b] = *reinterpret_cast<const typename F::frag_t*>(&Bs[row * LDS_LD + kk]);
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = F::mma(fa[a], fb[b], acc[a][b]);
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      store_tile();
+      __syncthreads();
+    }
+  }
+
+  // Epilogue: group g of lane l holds rows row0(g, l) + t RS (t = 0..3) of
+  // column l % TM of each MFMA tile.
+  typename Epi::Acc part;
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int g = 0; g < F::NACC / 4; ++g) {
+        const int64_t m = m0 + wm * WM + a * TM + F::row0(g, lane);
+        const int64_t n = n0 + wn * WN + b * TM + (lane % TM);
+        typename F::acc_e v[4] = {acc[a][b][4 * g], acc[a][b][4 * g + 1], acc[a][b][4 * g + 2],
+                                  acc[a][b][4 * g + 3]};
+        epi.template apply<F::RS>(m, n, v, part);
+      }
+  epi.finish(part, ctl.st);
+}
+
+// ---- epilogues ------------------------------------------------------------
+struct NoAcc {};
+
+// Transposed store: Ct[n][m + t RS] = v[t] (operand type).
+template <class OT>
+struct EpiStoreT {
+  OT* C;
+  int64_t ldc;
+  using Acc = NoAcc;
+  template <int RS, class V>
+  __device__ __forceinline__ void apply(int64_t m, int64_t n, const V (&v)[4], Acc&) const {
+    OT* d = C + n * ldc + m;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t * RS] = (OT)v[t];
+  }
+  __device__ __forceinline__ void finish(Acc&, DevState) const {}
+};
+
+// Direct store with the spectral division: C[m][n] = v / (eigM[m] + eigN[n]),
+// zero at (0,0) and on padding (tables hold +inf there).
+template <class OT>
+struct EpiScale {
+  OT* C;
+  int64_t ldc;
+  const double* eigM;  // rows of this product are the l (column) modes
+  const double* eigN;  // columns are the k (row) modes
+  using Acc = NoAcc;
+  template <int RS, class V>
+  __device__ __forceinline__ void apply(int64_t m, int64_t n, const V (&v)[4], Acc&) const {
+    const double en = eigN[n];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t mm = m + t * RS;
+      const double lam = eigM[mm] + en;
+      const double f = (mm == 0 && n == 0) ? 0.0 : 1.0 / lam;
+      C[mm * ldc + n] = (OT)((double)v[t] * f);
+    }
+  }
+  __device__ __forceinline__ void finish(Acc&, DevState) const {}
+};
+
+// Final product: z (vector type T), partial sums of z.r, z.q, sum z.
+template <class T>
+struct EpiFinal {
+  T* z;
+  const T* r;
+  const T* q;  // nullable
+  int64_t ldc;
+  double zscale;
+  struct Acc {
+    double zr = 0.0, zq = 0.0, zs = 0.0;
+  };
+  template <int RS, class V>
+  __device__ __forceinline__ void apply(int64_t m, int64_t n, const V (&v)[4], Acc& acc) const {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t o = (m + t * RS) * ldc + n;
+      const T zt = (T)((double)v[t] * zscale);
+      z[o] = zt;
+      const double zd = (double)zt;
+      acc.zr += zd * (double)r[o];
+      if (q) acc.zq += zd * (double)q[o];
+      acc.zs += zd;
+    }
+  }
+  __device__ __forceinline__ void finish(Acc& acc, DevState st) const {
+    double v[3] = {acc.zr, acc.zq, acc.zs};
+    const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
+    write_partials<3>(st.part, slots, v);
+  }
+};
+
+template <class OT, class AT, class Epi>
+static void gemm(const AT* A, int64_t lda, const OT* B, int64_t ldb, int64_t Mg, int64_t Ng,
+                 int64_t K, float ascale, const Epi& epi, const GemmCtl& ctl, hipStream_t s) {
+  constexpr int BM = Tile<OT>::BM, BN = Tile<OT>::BN;
+  const dim3 grid((unsigned)(Ng / BN), (unsigned)(Mg / BM));
+  hipLaunchKernelGGL((gemm_nt_kernel<OT, AT, Epi>), grid, dim3(kThreads), 0, s, A, lda, B, ldb, K,
+                     ascale, epi, ctl);
+}
+
+template <class OT, class T>
+static int precond_impl(const PrecondArgs& a, hipStream_t s) {
+  const int64_t Np = a.Np, Mp = a.Mp;
+  const OT* PN = static_cast<const OT*>(a.PN);
+  const OT* PNt = static_cast<const OT*>(a.PNt);
+  const OT* PM = static_cast<const OT*>(a.PM);
+  const OT* PMt = static_cast<const OT*>(a.PMt);
+  OT* T1 = static_cast<OT*>(a.T1);
+  OT* T2 = static_cast<OT*>(a.T2);
+  OT* T3 = static_cast<OT*>(a.T3);
+  const T* r = static_cast<const T*>(a.r);
+  GemmCtl c1{a.st, 1, a.check_conv, a.nparts_rr};
+  GemmCtl cn{a.st, 1, 0, 0};
+  // G1: T1^T = (r P_M)^T
+  gemm<OT, T>(r, Mp, PMt, Mp, Np, Mp, Mp, (float)a.scale, EpiStoreT<OT>{T1, Np}, c1, s);
+  // G2: T2^T = (P_N^T T1)^T ./ lambda
+  gemm<OT, OT>(T1, Np, PNt, Np, Mp, Np, Np, 1.0f,
+               EpiScale<OT>{T2, Np, static_cast<const double*>(a.eigM),
+                            static_cast<const double*>(a.eigN)},
+               cn, s);
+  // G3: T3 = (T2^T P_N^T)^T = P_N T2
+  gemm<OT, OT>(T2, Np, PN, Np, Mp, Np, Np, 1.0f, EpiStoreT<OT>{T3, Mp}, cn, s);
+  // G4: z = T3 P_M^T
+  gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
+               EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
+                           1.0 / a.scale},
+               cn, s);
+  return (int)((Mp / Tile<OT>::BN) * (Np / Tile<OT>::BM));
+}
+
+int launch_precond(const PrecondArgs& a, hipStream_t s) {
+  switch (a.kind) {
+    case OK_F64: return precond_impl<double, double>(a, s);
+    case OK_F32: return precond_impl<float, float>(a, s);
+    case OK_BF16: return precond_impl<__bf16, float>(a, s);
+    case OK_F16: return precond_impl<_Float16, float>(a, s);
+  }
+  return 0;
+}
+
+// ---- basis tables ------------------------------------------------------
+// P[i][k] = c_k cos(pi k (2i+1) / (2n)), c_0 = sqrt(1/n), c_k = sqrt(2/n);
+// the angle index k (2i+1) is reduced modulo 4n exactly in integers.
+// eig[k] = 2 - 2 cos(pi k / n) = 4 sin^2(pi k / 2n) (no cancellation), +inf
+// on padding so that the spectral division yields zero there.
+template <class OT>
+__global__ __launch_bounds__(kThreads) void basis_kernel(int64_t n, int64_t npad, OT* P, OT* Pt,
+                                                        double* eig) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (k >= npad) return;
+  double v = 0.0;
+  if (i < n && k < n) {
+    const int64_t idx = (k * (2 * i + 1)) % (4 * n);
+    const double ang = 3.141592653589793 * (double)idx / (double)(2 * n);
+    v = cos(ang) * (k == 0 ? sqrt(1.0 / (double)n) : sqrt(2.0 / (double)n));
+  }
+  P[i * npad + k] = (OT)v;
+  Pt[k * npad + i] = (OT)v;
+  if (i == 0) {
+    if (k < n) {
+      const double sn = sin(3.141592653589793 * (double)k / (double)(2 * n));
+      eig[k] = 4.0 * sn * sn;
+    } else {
+      eig[k] = __builtin_inf();
+    }
+  }
+}
+
+void launch_basis(int kind, int64_t n, int64_t npad, void* P, void* Pt, void* eig, hipStream_t s) {
+  const dim3 grid((unsigned)((npad + kThreads - 1) / kThreads), (unsigned)npad);
+  double* e = static_cast<double*>(eig);
+  switch (kind) {
+    case OK_F64:
+      hipLaunchKernelGGL(basis_kernel<double>, grid, dim3(kThreads), 0, s, n, npad,
+                         static_cast<double*>(P), static_cast<double*>(Pt), e);
+      break;
+    case OK_F32:
+      hipLaunchKernelGGL(basis_kernel<float>, grid, dim3(kThreads), 0, s, n, npad,
+                         static_cast<float*>(P), static_cast<float*>(Pt), e);
+      break;
+    case OK_BF16:
+      hipLaunchKernelGGL(basis_kernel<__bf16>, grid, dim3(kThreads), 0, s, n, npad,
+                         static_cast<__bf16*>(P), static_cast<__bf16*>(Pt), e);
+      break;
+    case OK_F16:
+      hipLaunchKernelGGL(basis_kernel<_Float16>, grid, dim3(kThreads), 0, s, n, npad,
+                         static_cast<_Float16*>(P), static_cast<_Float16*>(Pt), e);
+      break;
+  }
+}
+
+}  // namespace irlsu

@@ -1,0 +1,105 @@
+// Kernel argument blocks and launchers of the irlsu library.
+#pragma once
+
+#include "common.hpp"
+
+namespace irlsu {
+
+template <class T>
+struct SetupArgs {
+  const T* X; int64_t ldx;
+  const T* w;                       // nullable per-pixel weights (stride ldx)
+  const T* Cv; int64_t ldcv;        // nullable per-edge weights
+  const T* Ch; int64_t ldch;
+  const T* U0; int64_t ldu0;        // nullable warm start
+  int64_t N, M, Np, ld;
+  T* Gv; T* Gh; T* Cv_out; T* Ch_out;
+  double* U;                        // nullable: internal U to initialise
+  int32_t* flags;                   // input-validation bits
+};
+
+template <class T>
+struct WeightsArgs {
+  const double* U;
+  const T* Gv; const T* Gh; const T* Cv; const T* Ch;
+  T* Ov; T* Oh; T* b;
+  double eps;
+  int64_t Np, ld;
+  DevState st;
+};
+
+template <class T>
+struct AxpyArgs {
+  double* u; T* r; const T* p; const T* q;
+  int64_t n;          // Np * ld, a multiple of 4
+  int nparts_pq;      // number of p.q partials written by the stencil
+  int iter;
+  DevState st;
+};
+
+// Weighted 5-point stencil modes.
+enum StencilMode : int {
+  ST_FUSED = 0,   // p = (z - zc) + beta p_old;  q = A p;  partial p.q
+  ST_APPLY = 1,   // q = A p;  partial p.q
+  ST_RESID = 2,   // r = b - A u (u in FP64);  partial ||r||^2, sum r
+};
+
+template <class T>
+struct StencilArgs {
+  const T* Ov; const T* Oh;
+  const T* z;          // FUSED: preconditioned residual
+  const T* p_in;       // FUSED: previous direction; APPLY: p
+  T* p_out;            // FUSED: new direction (must not alias p_in)
+  T* q;                // FUSED / APPLY output
+  const double* u;     // RESID input
+  const T* b;          // RESID input
+  T* r;                // RESID output
+  int64_t N, M, Np, ld;
+  int iter;            // FUSED: PCG iteration l (l == 0 -> beta = 0)
+  int flexible;        // FUSED: flexible beta
+  int nparts_prec;     // FUSED: partials of the preconditioner epilogue
+  int nparts_res;      // FUSED: partials of sum r (axpy or residual kernel)
+  int check_done;      // skip when the PCG done flag is set
+  DevState st;
+};
+
+template <class T> void launch_setup(const SetupArgs<T>& a, hipStream_t s);
+template <class T> int launch_weights(const WeightsArgs<T>& a, hipStream_t s);
+void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s);
+template <class T> int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks);
+void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s);
+template <class T>
+void launch_copy_out(const double* u, int64_t ld, T* out, int64_t ldo, int64_t N, int64_t M,
+                     hipStream_t s);
+void launch_finalize_rr(DevState st, int nparts, hipStream_t s);
+void launch_reduce_to(DevState st, int slot, int nparts, double* out, hipStream_t s);
+int elementwise_blocks(int64_t n);
+
+template <class T> int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s);
+// Grid of the stencil (and of the axpy, which must write as many partials).
+dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out);
+
+// ---- DCT preconditioner (dense cosine-basis products on MFMA) ----------
+enum OperandKind : int { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2, OK_F16 = 3 };
+
+struct PrecondArgs {
+  int kind;                 // OperandKind
+  int64_t N, M, Np, Mp;     // Mp == ld
+  const void* PN;  const void* PNt;   // Np x Np basis and its transpose (operand type)
+  const void* PM;  const void* PMt;   // Mp x Mp
+  const void* eigN; const void* eigM; // inverse-eigenvalue tables (see dct.hip)
+  void* T1; void* T2; void* T3;       // intermediates (operand type), Np * Mp each
+  const void* r;            // residual (T)
+  void* z;                  // output (T)
+  const void* q;            // nullable: previous A p for the flexible beta (T)
+  double scale;             // r is multiplied by scale on load, z by 1/scale
+  int check_conv;           // first product checks ||r|| <= tol ||b|| and stops
+  int nparts_rr;            // partials of ||r||^2 for the convergence check
+  DevState st;
+};
+// Returns the number of partials written by the last product (z.r etc.).
+int launch_precond(const PrecondArgs& a, hipStream_t s);
+void launch_basis(int kind, int64_t n, int64_t npad, void* P, void* Pt, void* eig_inv,
+                  hipStream_t s);
+
+}  // namespace irlsu

@@ -1,0 +1,325 @@
+// Point-wise and reduction kernels of the IRLS + PCG path: setup of the
+// wrapped gradients and edge weights, the IRLS weight step, the CG axpy,
+// mean removal and the scalar finalisers.  All HBM-bound: one pass each,
+// FP64 accumulation of every reduction through deterministic block sums.
+#include "kernels.hpp"
+
+namespace irlsu {
+
+// ----------------------------------------------------------------------------
+// Setup (Section 2): G = W(X_{i+1,j} - X_{ij}) etc. with W the residue in
+// [-pi, pi), computed in FP64 with explicitly rounded operations so that the
+// branch taken by floor() is the one the FP64 definition takes.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_residue(double d) {
+  const double kPi = 3.141592653589793;
+  const double kTwoPi = 6.283185307179586;
+  const double k = floor(__ddiv_rn(__dadd_rn(d, kPi), kTwoPi));
+  return __dsub_rn(d, __dmul_rn(kTwoPi, k));
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void setup_kernel(
+    SetupArgs<T> a) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= a.ld) return;
+  const int64_t N = a.N, M = a.M;
+  const int64_t o = i * a.ld + j;
+  T gv = 0, gh = 0, cv = 0, ch = 0;
+  int bad = 0;
+  if (i < N && j < M) {
+    const double x0 = (double)a.X[i * a.ldx + j];
+    if (!isfinite(x0)) bad |= 1;
+    if (a.w) {
+      const double w0 = (double)a.w[i * a.ldx + j];
+      if (!isfinite(w0)) bad |= 1;
+      else if (!(w0 > 0.0)) bad |= 2;
+    }
+    if (i + 1 < N) {
+      const double x1 = (double)a.X[(i + 1) * a.ldx + j];
+      gv = (T)wrap_residue(x1 - x0);
+      if (a.Cv) {
+        const T c = a.Cv[i * a.ldcv + j];
+        if (!isfinite((double)c)) bad |= 1;
+        else if (!((double)c > 0.0)) bad |= 2;
+        cv = c;
+      } else if (a.w) {
+        const T w0 = a.w[i * a.ldx + j], w1 = a.w[(i + 1) * a.ldx + j];
+        cv = w0 < w1 ? w0 : w1;
+      } else {
+        cv = (T)1;
+      }
+    }
+    if (j + 1 < M) {
+      const double x1 = (double)a.X[i * a.ldx + j + 1];
+      gh = (T)wrap_residue(x1 - x0);
+      if (a.Ch) {
+        const T c = a.Ch[i * a.ldch + j];
+        if (!isfinite((double)c)) bad |= 1;
+        else if (!((double)c > 0.0)) bad |= 2;
+        ch = c;
+      } else if (a.w) {
+        const T w0 = a.w[i * a.ldx + j], w1 = a.w[i * a.ldx + j + 1];
+        ch = w0 < w1 ? w0 : w1;
+      } else {
+        ch = (T)1;
+      }
+    }
+  }
+  a.Gv[o] = gv;
+  a.Gh[o] = gh;
+  a.Cv_out[o] = cv;
+  a.Ch_out[o] = ch;
+  if (a.U) {
+    double u = 0.0;
+    if (a.U0 && i < N && j < M) {
+      u = (double)a.U0[i * a.ldu0 + j];
+      if (!isfinite(u)) bad |= 1;
+    }
+    a.U[o] = u;
+  }
+  if (bad) atomicOr(a.flags, bad);
+}
+
+// ----------------------------------------------------------------------------
+// IRLS weight step: r = DU - G, Omega = C / max(|r|, eps), b = D^T (Omega G),
+// partial sums of C|r|, C h_eps(r) and b^2.  One thread per pixel; the edges
+// above and to the left are recomputed from cached neighbours.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double edge_omega(double c, double r, double eps) {
+  const double a = fabs(r);
+  return c / (a > eps ? a : eps);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void weights_kernel(WeightsArgs<T> a, int rows_per_block) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int64_t i0 = (int64_t)blockIdx.y * rows_per_block;
+  int64_t i1 = i0 + rows_per_block;
+  if (i1 > a.Np) i1 = a.Np;
+  if (j < a.ld) {
+    const int64_t ld = a.ld;
+    const double eps = a.eps;
+    for (int64_t i = i0; i < i1; ++i) {
+      const int64_t o = i * ld + j;
+      const double u = a.U[o];
+      const double ud = (i + 1 < a.Np) ? a.U[o + ld] : 0.0;
+      const double ur = (j + 1 < ld) ? a.U[o + 1] : 0.0;
+      const double gv = (double)a.Gv[o], gh = (double)a.Gh[o];
+      const double cv = (double)a.Cv[o], ch = (double)a.Ch[o];
+      const double rv = ud - u - gv;
+      const double rh = ur - u - gh;
+      const double ov = edge_omega(cv, rv, eps);
+      const double oh = edge_omega(ch, rh, eps);
+      double bsum = -ov * gv - oh * gh;
+      if (i > 0) {
+        const double gvu = (double)a.Gv[o - ld], cvu = (double)a.Cv[o - ld];
+        bsum += edge_omega(cvu, u - a.U[o - ld] - gvu, eps) * gvu;
+      }
+      if (j > 0) {
+        const double ghl = (double)a.Gh[o - 1], chl = (double)a.Ch[o - 1];
+        bsum += edge_omega(chl, u - a.U[o - 1] - ghl, eps) * ghl;
+      }
+      a.Ov[o] = (T)ov;
+      a.Oh[o] = (T)oh;
+      a.b[o] = (T)bsum;
+      const double arv = fabs(rv), arh = fabs(rh);
+      acc[0] += cv * arv + ch * arh;
+      acc[1] += cv * (arv <= eps ? 0.5 * arv * arv / eps : arv - 0.5 * eps) +
+                ch * (arh <= eps ? 0.5 * arh * arh / eps : arh - 0.5 * eps);
+      const double bt = (double)(T)bsum;
+      acc[2] += bt * bt;
+    }
+  }
+  const int slots[3] = {PR_L1, PR_H, PR_BB};
+  write_partials<3>(a.st.part, slots, acc);
+}
+
+// Finalise the weight step: objectives and ||b||^2 into scalars (and an
+// optional user array), reset the PCG flags for the next solve.
+__global__ __launch_bounds__(kThreads) void finalize_weights_kernel(
+    DevState st, int nparts, double* out, double tol2) {
+  const double l1 = reduce_slot(st.part, PR_L1, nparts);
+  const double h = reduce_slot(st.part, PR_H, nparts);
+  const double bb = reduce_slot(st.part, PR_BB, nparts);
+  if (threadIdx.x == 0) {
+    st.sc[SC_L1] = l1;
+    st.sc[SC_H] = h;
+    st.sc[SC_BB] = bb;
+    st.sc[SC_TOL2] = tol2;
+    st.fl[FL_DONE] = 0;
+    st.fl[FL_ITERS] = 0;
+    if (out) {
+      out[0] = l1;
+      out[1] = h;
+      out[2] = bb;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// CG update (Algorithm 2): alpha = rho / p.q, u += alpha p, r -= alpha q,
+// partial ||r||^2 and sum r.  The prologue reduces the stencil's p.q partials
+// (identically in every block) and stops on breakdown.
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kThreads) void axpy_kernel(AxpyArgs<T> a) {
+  if (a.st.fl[FL_DONE]) return;
+  const double pq = reduce_slot(a.st.part, PR_PQ, a.nparts_pq);
+  const double rho = a.st.sc[SC_RHO + (a.iter & 1)];
+  if (!(pq > 0.0) || !(rho >= 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.st.fl[FL_STATUS] |= 1;
+      a.st.fl[FL_DONE] = 1;
+    }
+    return;
+  }
+  const double alpha = rho / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.st.sc[SC_ALPHA + (a.iter & 1)] = alpha;
+    a.st.sc[SC_PQ] = pq;
+    a.st.fl[FL_ITERS] = a.iter + 1;
+  }
+  const T al = (T)alpha;
+  double acc[2] = {0.0, 0.0};
+  const int64_t n4 = a.n / 4;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n4;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t o = k * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const T p = a.p[o + e];
+      const T q = a.q[o + e];
+      a.u[o + e] += alpha * (double)p;
+      const T r = a.r[o + e] - al * q;
+      a.r[o + e] = r;
+      acc[0] += (double)r * (double)r;
+      acc[1] += (double)r;
+    }
+  }
+  const int slots[2] = {PR_RR, PR_RSUM};
+  write_partials<2>(a.st.part, slots, acc);
+}
+
+// ----------------------------------------------------------------------------
+// Mean removal (last step of Algorithm 1): sum over the valid pixels, then
+// subtract.  The padding stays zero.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void sum_kernel(const double* u, int64_t N, int64_t M,
+                                                      int64_t ld, DevState st) {
+  double acc[1] = {0.0};
+  const int64_t n = N * ld;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t j = k % ld;
+    if (j < M) acc[0] += (double)u[k];
+  }
+  const int slots[1] = {PR_AUX};
+  write_partials<1>(st.part, slots, acc);
+}
+
+__global__ __launch_bounds__(kThreads) void sub_mean_kernel(double* u, int64_t N, int64_t M,
+                                                           int64_t ld, DevState st,
+                                                           int nparts) {
+  const double s = reduce_slot(st.part, PR_AUX, nparts);
+  const double mean = s / ((double)N * (double)M);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st.sc[SC_MEAN] = mean;
+  const int64_t n = N * ld;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t j = k % ld;
+    if (j < M) u[k] -= mean;
+  }
+}
+
+// Copy the (mean-zero) internal U to the caller's N x M buffer.
+template <class T>
+__global__ __launch_bounds__(kThreads) void copy_out_kernel(const double* u, int64_t ld, T* out,
+                                                           int64_t ldo, int64_t N, int64_t M) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (i < N && j < M) out[i * ldo + j] = (T)u[i * ld + j];
+}
+
+// Reduce the residual partials after a solve: ||r||^2 into SC_RR.
+__global__ __launch_bounds__(kThreads) void finalize_rr_kernel(DevState st, int nparts) {
+  const double rr = reduce_slot(st.part, PR_RR, nparts);
+  if (threadIdx.x == 0) st.sc[SC_RR] = rr;
+}
+
+// Reduce one partial slot into a device double (step-level entry points).
+__global__ __launch_bounds__(kThreads) void reduce_to_kernel(DevState st, int slot, int nparts,
+                                                            double* out) {
+  const double v = reduce_slot(st.part, slot, nparts);
+  if (threadIdx.x == 0) *out = v;
+}
+
+// ----------------------------------------------------------------------------
+// Launchers
+// ----------------------------------------------------------------------------
+template <class T>
+void launch_setup(const SetupArgs<T>& a, hipStream_t s) {
+  dim3 grid((unsigned)((a.ld + kThreads - 1) / kThreads), (unsigned)a.Np);
+  hipLaunchKernelGGL(setup_kernel<T>, grid, dim3(kThreads), 0, s, a);
+}
+
+template <class T>
+int launch_weights(const WeightsArgs<T>& a, hipStream_t s) {
+  const int64_t bx = (a.ld + kThreads - 1) / kThreads;
+  int64_t rows = 1;
+  while (bx * ((a.Np + rows - 1) / rows) > kMaxPartials / 2) rows *= 2;
+  const dim3 grid((unsigned)bx, (unsigned)((a.Np + rows - 1) / rows));
+  hipLaunchKernelGGL(weights_kernel<T>, grid, dim3(kThreads), 0, s, a, (int)rows);
+  return (int)(grid.x * grid.y);
+}
+
+void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_weights_kernel, dim3(1), dim3(kThreads), 0, s, st, nparts, out, tol2);
+}
+
+int elementwise_blocks(int64_t n) {
+  int64_t b = (n / 4 + kThreads - 1) / kThreads;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <class T>
+int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks) {
+  hipLaunchKernelGGL((axpy_kernel<T>), dim3(nblocks), dim3(kThreads), 0, s, a);
+  return nblocks;
+}
+
+void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s) {
+  const int nb = elementwise_blocks(N * ld);
+  hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(kThreads), 0, s, u, N, M, ld, st);
+  hipLaunchKernelGGL(sub_mean_kernel, dim3(nb), dim3(kThreads), 0, s, u, N, M, ld, st, nb);
+}
+
+template <class T>
+void launch_copy_out(const double* u, int64_t ld, T* out, int64_t ldo, int64_t N, int64_t M,
+                     hipStream_t s) {
+  dim3 grid((unsigned)((M + kThreads - 1) / kThreads), (unsigned)N);
+  hipLaunchKernelGGL((copy_out_kernel<T>), grid, dim3(kThreads), 0, s, u, ld, out, ldo, N, M);
+}
+
+void launch_finalize_rr(DevState st, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_rr_kernel, dim3(1), dim3(kThreads), 0, s, st, nparts);
+}
+
+void launch_reduce_to(DevState st, int slot, int nparts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_to_kernel, dim3(1), dim3(kThreads), 0, s, st, slot, nparts, out);
+}
+
+template void launch_setup<float>(const SetupArgs<float>&, hipStream_t);
+template void launch_setup<double>(const SetupArgs<double>&, hipStream_t);
+template int launch_weights<float>(const WeightsArgs<float>&, hipStream_t);
+template int launch_weights<double>(const WeightsArgs<double>&, hipStream_t);
+template int launch_axpy<float>(const AxpyArgs<float>&, hipStream_t, int);
+template int launch_axpy<double>(const AxpyArgs<double>&, hipStream_t, int);
+template void launch_copy_out<float>(const double*, int64_t, float*, int64_t, int64_t, int64_t, hipStream_t);
+template void launch_copy_out<double>(const double*, int64_t, double*, int64_t, int64_t, int64_t, hipStream_t);
+
+}  // namespace irlsu

@@ -1,0 +1,277 @@
+// Weighted 5-point operator q = D^T Omega D p on the image (the U block of the
+// linear system of Proposition 1 after slack elimination; S^T S and T T^T of
+// Appendix A are its unweighted form), fused with the CG direction update
+// p = z + beta p (Algorithm 2) and the FP64 partial sum of p . q.
+//
+// Layout: row-major, ld columns.  A block owns 1024 columns (4 per thread,
+// one 16-byte access per array per row for FP32) and a band of rows that it
+// walks top to bottom, keeping the rows above / at / below the current one
+// in registers.  Horizontal neighbours across thread boundaries (the column
+// halo) go through LDS: each thread publishes its first and last column of
+// p and its last horizontal weight, double-buffered by row parity so one
+// barrier per row suffices.  HBM traffic per pixel: z, p_old, Omega^v,
+// Omega^h in, p, q out = 24 bytes (FP32), plus the two halo rows per band.
+#include "kernels.hpp"
+
+namespace irlsu {
+
+template <class T>
+struct V4 {
+  T v[4];
+};
+
+template <class T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+  V4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  }
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ void st4(T* p, const V4<T>& r) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(r.v[2], r.v[3]);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ V4<T> zero4() {
+  V4<T> r;
+  r.v[0] = r.v[1] = r.v[2] = r.v[3] = (T)0;
+  return r;
+}
+
+// CT: compute type (double in the residual mode, where u is FP64).
+template <class T, int MODE>
+struct StencilIO {
+  using CT = typename std::conditional<MODE == ST_RESID, double, T>::type;
+  const StencilArgs<T>& a;
+  CT beta, zc;
+
+  __device__ StencilIO(const StencilArgs<T>& a_, CT beta_, CT zc_) : a(a_), beta(beta_), zc(zc_) {}
+
+  // p value of one pixel (scalar; used for the column halo).
+  __device__ __forceinline__ CT p1(int64_t i, int64_t j) const {
+    if (i < 0 || i >= a.Np || j < 0 || j >= a.ld) return (CT)0;
+    const int64_t o = i * a.ld + j;
+    if constexpr (MODE == ST_FUSED) {
+      if (i >= a.N || j >= a.M) return (CT)0;
+      return ((CT)a.z[o] - zc) + beta * (CT)a.p_in[o];
+    } else if constexpr (MODE == ST_APPLY) {
+      return (CT)a.p_in[o];
+    } else {
+      return (CT)a.u[o];
+    }
+  }
+
+  // p values of 4 consecutive pixels (j multiple of 4, j < ld).
+  __device__ __forceinline__ V4<CT> p4(int64_t i, int64_t j) const {
+    V4<CT> r;
+    if (i < 0 || i >= a.Np) {
+      r.v[0] = r.v[1] = r.v[2] = r.v[3] = (CT)0;
+      return r;
+    }
+    const int64_t o = i * a.ld + j;
+    if constexpr (MODE == ST_FUSED) {
+      const V4<T> z = ld4(a.z + o);
+      const V4<T> p = ld4(a.p_in + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool valid = (i < a.N) && (j + e < a.M);
+        r.v[e] = valid ? ((CT)z.v[e] - zc) + beta * (CT)p.v[e] : (CT)0;
+      }
+    } else if constexpr (MODE == ST_APPLY) {
+      const V4<T> p = ld4(a.p_in + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) r.v[e] = (CT)p.v[e];
+    } else {
+      const V4<double> u = ld4(a.u + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) r.v[e] = (CT)u.v[e];
+    }
+    return r;
+  }
+};
+
+template <class T, int MODE>
+__global__ __launch_bounds__(kThreads) void stencil_kernel(StencilArgs<T> a, int rows_per_block) {
+  using IO = StencilIO<T, MODE>;
+  using CT = typename IO::CT;
+  if (a.check_done && a.st.fl[FL_DONE]) return;
+
+  CT beta = 0, zc = 0;
+  if constexpr (MODE == ST_FUSED) {
+    const double zr = reduce_slot(a.st.part, PR_ZR, a.nparts_prec);
+    const double zs = reduce_slot(a.st.part, PR_ZS, a.nparts_prec);
+    const double zq = reduce_slot(a.st.part, PR_ZQ, a.nparts_prec);
+    const double rsum = reduce_slot(a.st.part, PR_RSUM, a.nparts_res);
+    const double zcd = zs / ((double)a.N * (double)a.M);
+    const double rho = zr - zcd * rsum;
+    double b = 0.0;
+    if (a.iter > 0) {
+      const double rho_old = a.st.sc[SC_RHO + ((a.iter - 1) & 1)];
+      if (a.flexible) {
+        const double alpha_old = a.st.sc[SC_ALPHA + ((a.iter - 1) & 1)];
+        b = -alpha_old * zq / rho_old;
+      } else {
+        b = rho / rho_old;
+      }
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      a.st.sc[SC_RHO + (a.iter & 1)] = rho;
+      a.st.sc[SC_BETA] = b;
+      a.st.sc[SC_ZSUM] = zs;
+    }
+    beta = (CT)b;
+    zc = (CT)zcd;
+  }
+  const IO io(a, beta, zc);
+
+  __shared__ CT s_first[2][kThreads + 2];
+  __shared__ CT s_last[2][kThreads + 2];
+  __shared__ CT s_ohl[2][kThreads + 2];
+
+  const int t = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * (kThreads * 4);
+  const int64_t j0 = c0 + 4 * t;
+  const bool active = j0 < a.ld;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+  int64_t r1 = r0 + rows_per_block;
+  if (r1 > a.Np) r1 = a.Np;
+  const int64_t ld = a.ld;
+
+  V4<CT> pu = zero4<CT>(), pc = zero4<CT>(), pd = zero4<CT>(), ovu = zero4<CT>();
+  if (active) {
+    pu = io.p4(r0 - 1, j0);
+    pc = io.p4(r0, j0);
+    pd = io.p4(r0 + 1, j0);
+    if (r0 > 0) {
+      const V4<T> o = ld4(a.Ov + (r0 - 1) * ld + j0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ovu.v[e] = (CT)o.v[e];
+    }
+  }
+
+  double acc0 = 0.0, acc1 = 0.0;
+  int buf = 0;
+  for (int64_t i = r0; i < r1; ++i) {
+    V4<CT> ov = zero4<CT>(), oh = zero4<CT>(), pn = zero4<CT>();
+    if (active) {
+      const V4<T> ovt = ld4(a.Ov + i * ld + j0);
+      const V4<T> oht = ld4(a.Oh + i * ld + j0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ov.v[e] = (CT)ovt.v[e];
+        oh.v[e] = (CT)oht.v[e];
+      }
+      pn = io.p4(i + 2, j0);  // look-ahead row, used after this row
+    }
+    s_first[buf][t + 1] = pc.v[0];
+    s_last[buf][t + 1] = pc.v[3];
+    s_ohl[buf][t + 1] = oh.v[3];
+    if (t == 0) {
+      s_last[buf][0] = io.p1(i, c0 - 1);
+      s_ohl[buf][0] = (c0 > 0) ? (CT)a.Oh[i * ld + c0 - 1] : (CT)0;
+    }
+    if (t == kThreads - 1) s_first[buf][kThreads + 1] = io.p1(i, c0 + 4 * kThreads);
+    __syncthreads();
+    if (active) {
+      const CT pl = s_last[buf][t];
+      const CT pr = s_first[buf][t + 2];
+      const CT ohl = s_ohl[buf][t];
+      V4<CT> q;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const CT right = e < 3 ? pc.v[e + 1] : pr;
+        const CT left = e > 0 ? pc.v[e - 1] : pl;
+        const CT wl = e > 0 ? oh.v[e - 1] : ohl;
+        q.v[e] = ov.v[e] * (pc.v[e] - pd.v[e]) + ovu.v[e] * (pc.v[e] - pu.v[e]) +
+                 oh.v[e] * (pc.v[e] - right) + wl * (pc.v[e] - left);
+      }
+      const int64_t o = i * ld + j0;
+      if constexpr (MODE == ST_RESID) {
+        const V4<T> bt = ld4(a.b + o);
+        V4<T> rt;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          rt.v[e] = (T)((double)bt.v[e] - q.v[e]);
+          acc0 += (double)rt.v[e] * (double)rt.v[e];
+          acc1 += (double)rt.v[e];
+        }
+        st4(a.r + o, rt);
+      } else {
+        V4<T> qt;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          qt.v[e] = (T)q.v[e];
+          acc0 += (double)pc.v[e] * (double)qt.v[e];
+        }
+        st4(a.q + o, qt);
+        if constexpr (MODE == ST_FUSED) {
+          V4<T> pt;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pt.v[e] = (T)pc.v[e];
+          st4(a.p_out + o, pt);
+        }
+      }
+    }
+    pu = pc;
+    pc = pd;
+    pd = pn;
+    ovu = ov;
+    buf ^= 1;
+  }
+
+  if constexpr (MODE == ST_RESID) {
+    double v[2] = {acc0, acc1};
+    const int slots[2] = {PR_RR, PR_RSUM};
+    write_partials<2>(a.st.part, slots, v);
+  } else {
+    double v[1] = {acc0};
+    const int slots[1] = {PR_PQ};
+    write_partials<1>(a.st.part, slots, v);
+  }
+}
+
+// Enough blocks to fill 256 CUs several times over, within the partials table.
+dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out) {
+  const int64_t bx = (ld + 4 * kThreads - 1) / (4 * kThreads);
+  int64_t rows = 64;
+  while (rows > 4 && bx * ((Np + rows - 1) / rows) < 2048) rows /= 2;
+  while (bx * ((Np + rows - 1) / rows) > kMaxPartials) rows *= 2;
+  *rows_out = (int)rows;
+  return dim3((unsigned)bx, (unsigned)((Np + rows - 1) / rows));
+}
+
+template <class T>
+int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s) {
+  int rows = 0;
+  const dim3 grid = stencil_grid(a.Np, a.ld, &rows);
+  switch (mode) {
+    case ST_FUSED:
+      hipLaunchKernelGGL((stencil_kernel<T, ST_FUSED>), grid, dim3(kThreads), 0, s, a, rows);
+      break;
+    case ST_APPLY:
+      hipLaunchKernelGGL((stencil_kernel<T, ST_APPLY>), grid, dim3(kThreads), 0, s, a, rows);
+      break;
+    default:
+      hipLaunchKernelGGL((stencil_kernel<T, ST_RESID>), grid, dim3(kThreads), 0, s, a, rows);
+      break;
+  }
+  return (int)(grid.x * grid.y);
+}
+
+template int launch_stencil<float>(int, const StencilArgs<float>&, hipStream_t);
+template int launch_stencil<double>(int, const StencilArgs<double>&, hipStream_t);
+
+}  // namespace irlsu

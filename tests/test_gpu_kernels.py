@@ -1,0 +1,180 @@
+"""Kernel-level parity of the HIP path against the FP64 oracle, through the
+C ABI (step entry points), on seeded inputs that span several tiles and a
+ragged tail.
+
+Tolerances (derived from the arithmetic, per precision of the plan):
+* setup: bit-exact -- both sides difference and wrap in FP64 with the same
+  rounded operations, the FP32 plan then rounds to nearest.
+* weights / operator: element-wise bound 8 u sum_e Omega_e (|p_i| + |p_j|)
+  (u the unit roundoff of the vector type; each output sums four terms).
+* preconditioner: norm-wise relative error; FP64 1e-11, FP32 2e-5, BF16
+  3e-2 (operands rounded to 8 mantissa bits in four chained products).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2401_09961_amd as pkg
+from oracle import reduced as R
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(96, 80), (131, 257), (256, 256)]
+UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24}
+PRECOND_RTOL = {"f64": 1e-11, "f32": 2e-5, "bf16": 3e-2}
+
+
+def npdt(prec):
+    return np.float64 if prec == "f64" else np.float32
+
+
+def internal(plan, A, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    return plan.to_internal(t, dtype=dtype)
+
+
+def edge_v(plan, Ev, dtype=None):
+    return internal(plan, Ev, dtype)  # (N-1) x M in the top-left corner
+
+
+@pytest.fixture(scope="module", params=["f64", "f32", "bf16"])
+def prec(request):
+    return request.param
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_setup_bit_exact(prec, shape):
+    N, M = shape
+    f = synth.field_c2(1, N, M)
+    dt = npdt(prec)
+    X, w = f.X.astype(dt), f.w.astype(dt)
+    plan = pkg.Plan(N, M, prec)
+    Gv, Gh, Cv, Ch, flags = plan.setup(torch.from_numpy(X).cuda(), torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0
+    Gv_o, Gh_o = R.wrapped_gradients(X.astype(np.float64))
+    Cv_o, Ch_o = R.edge_weights(N, M, w=w.astype(np.float64))
+    Gv_g, Gh_g = Gv.cpu().numpy(), Gh.cpu().numpy()
+    assert np.array_equal(Gv_g[: N - 1, :M], Gv_o.astype(dt))
+    assert np.array_equal(Gh_g[:N, : M - 1], Gh_o.astype(dt))
+    assert np.array_equal(Cv.cpu().numpy()[: N - 1, :M], Cv_o.astype(dt))
+    assert np.array_equal(Ch.cpu().numpy()[:N, : M - 1], Ch_o.astype(dt))
+    # padding and missing edges are zero
+    for A, r, c in ((Gv_g, N - 1, M), (Gh_g, N, M - 1)):
+        Z = A.copy()
+        Z[:r, :c] = 0
+        assert not Z.any()
+    plan.close()
+
+
+def test_setup_flags_bad_inputs():
+    plan = pkg.Plan(40, 33, "f32")
+    X = torch.zeros((40, 33), dtype=torch.float32, device="cuda")
+    w = torch.ones_like(X)
+    X[3, 4] = float("nan")
+    *_, flags = plan.setup(X, w)
+    assert int(flags.item()) & 1
+    X[3, 4] = 0.0
+    w[5, 6] = 0.0
+    *_, flags = plan.setup(X, w)
+    assert int(flags.item()) & 2
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_weights_step(prec, shape):
+    N, M = shape
+    f = synth.field_c3(2, N, M)
+    dt = npdt(prec)
+    plan = pkg.Plan(N, M, prec)
+    Gv, Gh, Cv, Ch, _ = plan.setup(torch.from_numpy(f.X.astype(dt)).cuda(),
+                                   torch.from_numpy(f.w.astype(dt)).cuda())
+    rng = np.random.default_rng(3)
+    U = f.phi - f.phi.mean() + rng.normal(0, 0.3, (N, M))
+    Ui = internal(plan, U, torch.float64)
+    eps = 1e-3
+    Ov, Oh, b, obj = plan.weights(eps, Ui, Gv, Gh, Cv, Ch)
+    torch.cuda.synchronize()
+    Gv_o = Gv.cpu().numpy()[: N - 1, :M].astype(np.float64)
+    Gh_o = Gh.cpu().numpy()[:N, : M - 1].astype(np.float64)
+    Cv_o = Cv.cpu().numpy()[: N - 1, :M].astype(np.float64)
+    Ch_o = Ch.cpu().numpy()[:N, : M - 1].astype(np.float64)
+    Ov_o, Oh_o, b_o, L1, H = R.weight_step(U, Gv_o, Gh_o, Cv_o, Ch_o, eps)
+    u = UNIT[prec]
+    Ov_g = Ov.cpu().numpy()
+    Oh_g = Oh.cpu().numpy()
+    assert np.all(np.abs(Ov_g[: N - 1, :M] - Ov_o) <= 2 * u * np.abs(Ov_o))
+    assert np.all(np.abs(Oh_g[:N, : M - 1] - Oh_o) <= 2 * u * np.abs(Oh_o))
+    assert not Ov_g[N - 1:, :].any() and not Oh_g[:, M - 1:].any()
+    fv, fh = np.abs(Ov_o * Gv_o), np.abs(Oh_o * Gh_o)
+    bound = (np.pad(fv, ((0, 1), (0, 0))) + np.pad(fv, ((1, 0), (0, 0)))
+             + np.pad(fh, ((0, 0), (0, 1))) + np.pad(fh, ((0, 0), (1, 0))))
+    err = np.abs(b.cpu().numpy()[:N, :M] - b_o)
+    assert np.all(err <= 8 * u * bound + 1e-300)
+    o = obj.cpu().numpy()
+    assert abs(o[0] - L1) <= 1e-12 * L1
+    assert abs(o[1] - H) <= 1e-12 * H
+    bb = float(np.sum(b.cpu().numpy().astype(np.float64) ** 2))
+    assert abs(o[2] - bb) <= 1e-12 * bb
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_operator_and_dot(prec, shape):
+    N, M = shape
+    dt = npdt(prec)
+    rng = np.random.default_rng(4)
+    Ov = rng.uniform(0.0, 50.0, (N - 1, M)).astype(dt)
+    Oh = rng.uniform(0.0, 50.0, (N, M - 1)).astype(dt)
+    p = rng.standard_normal((N, M)).astype(dt)
+    plan = pkg.Plan(N, M, prec)
+    q, pq = plan.operator(internal(plan, Ov), internal(plan, Oh), internal(plan, p))
+    torch.cuda.synchronize()
+    Ovd, Ohd, pd = Ov.astype(np.float64), Oh.astype(np.float64), p.astype(np.float64)
+    q_o = R.apply_A(Ovd, Ohd, pd)
+    absd_v = np.abs(Ovd) * (np.abs(pd[1:, :]) + np.abs(pd[:-1, :]))
+    absd_h = np.abs(Ohd) * (np.abs(pd[:, 1:]) + np.abs(pd[:, :-1]))
+    bound = (np.pad(absd_v, ((0, 1), (0, 0))) + np.pad(absd_v, ((1, 0), (0, 0)))
+             + np.pad(absd_h, ((0, 0), (0, 1))) + np.pad(absd_h, ((0, 0), (1, 0))))
+    qg = q.cpu().numpy()
+    assert np.all(np.abs(qg[:N, :M] - q_o) <= 8 * UNIT[prec] * bound)
+    assert not qg[N:, :].any() and not qg[:, M:].any()
+    ref = float(np.sum(pd * qg[:N, :M].astype(np.float64)))
+    assert abs(pq.item() - ref) <= 1e-12 * np.sum(np.abs(pd * q_o)) + 1e-300
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_precond_matches_dct_oracle(prec, shape):
+    N, M = shape
+    dt = npdt(prec)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal((N, M)).astype(dt)
+    plan = pkg.Plan(N, M, prec)
+    z, rz = plan.precond(internal(plan, r))
+    torch.cuda.synchronize()
+    z_o = R.apply_precond(r.astype(np.float64))
+    zg = z.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
+    print(f"precond {prec} {shape}: rel err {rel:.3e}")
+    assert rel <= PRECOND_RTOL[prec]
+    assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
+    ref = float(np.sum(r.astype(np.float64) * z_o))
+    assert abs(rz.item() - ref) <= 2 * PRECOND_RTOL[prec] * abs(ref)
+    plan.close()
+
+
+def test_precond_is_pseudo_inverse_property_f64():
+    """L z = r - mean(r) with L the unweighted Neumann Laplacian (applied by
+    the oracle's plain stencil), at a size with several GEMM tiles."""
+    N, M = 384, 200
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal((N, M))
+    plan = pkg.Plan(N, M, "f64")
+    z, _ = plan.precond(internal(plan, r))
+    zg = z.cpu().numpy()[:N, :M]
+    Lz = R.apply_A(np.ones((N - 1, M)), np.ones((N, M - 1)), zg)
+    assert np.abs(Lz - (r - r.mean())).max() < 1e-10
+    assert abs(zg.mean()) < 1e-12
+    plan.close()
