@@ -170,6 +170,62 @@ irlsu_status irlsu_unwrap(irlsu_plan* plan,
                           void* workspace, size_t workspace_bytes,
                           irlsu_stats* stats, void* stream);
 
+/* ---- Batched uneven tiles ---------------------------------------------- */
+
+typedef struct irlsu_batch irlsu_batch;
+
+/* One independent problem of a batch (each tile is its own Section 2
+ * problem with its own mean-zero constraint; tiles are not coupled).  Same
+ * argument meaning and layout as irlsu_unwrap, element type float. */
+typedef struct irlsu_tile {
+  const void* X; int64_t ldx;
+  const void* w;
+  const void* Cv; int64_t ldcv;
+  const void* Ch; int64_t ldch;
+  void* U; int64_t ldu;
+} irlsu_tile;
+
+/* Create a batch for ntiles tiles of shapes[2t] x shapes[2t+1] (host array).
+ * Builds one DCT-II basis per distinct side length (Section 3.3 precompute)
+ * in the mixed precisions only (IRLSU_MIXED_BF16 or IRLSU_MIXED_F16; other
+ * precisions return ERR_UNSUPPORTED).  Tiles are padded to multiples of 256.
+ * Errors as irlsu_plan_create; ERR_SHAPE also when the batch is too large
+ * for the partial-sum table. */
+irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_t ntiles,
+                                irlsu_precision prec, void* stream);
+irlsu_status irlsu_batch_destroy(irlsu_batch* batch);
+size_t irlsu_batch_workspace_bytes(const irlsu_batch* batch);
+
+/* Unwrap all tiles of a batch.  Every PCG phase (stencil, update,
+ * preconditioner products) is one grouped launch over all tiles, with
+ * per-tile scalars and convergence flags; converged tiles drop out.
+ * tiles: host array of ntiles descriptors; stats: host array of ntiles or
+ * NULL.  Returns the worst per-tile status. */
+irlsu_status irlsu_unwrap_batched(irlsu_batch* batch, const irlsu_tile* tiles,
+                                  const irlsu_params* params, void* workspace,
+                                  size_t workspace_bytes, irlsu_stats* stats, void* stream);
+
+/* Adjoint of the converged system (frozen weights).  For a loss L(U) with
+ * gU = dL/dU (device, N x M, stride ldg), differentiates the map
+ * (C, X) -> U = argmin over mean-zero U of sum C omega (DU - G(X))^2 with
+ * omega = 1 / max(|DU* - G|, eps) frozen at the U* that the last
+ * irlsu_unwrap on this plan and workspace returned (the fixed point of
+ * Algorithm 1).  One extra PCG solve D^T Omega D lambda = gU - mean(gU) with
+ * the forward kernels, then per edge gC = -omega (D lambda) (DU* - G) and
+ * gX = D^T (Omega D lambda).
+ *   gCv (N-1) x M (stride ldgcv), gCh N x (M-1) (stride ldgch): device out.
+ *   gX  N x M (stride ldgx): device out, nullable.
+ *   workspace: the one passed to the preceding irlsu_unwrap, unmodified since.
+ *   params: solver parameters of the adjoint solve (NULL: defaults).
+ * Returns OK, NOT_CONVERGED or an error as irlsu_unwrap; stats (nullable)
+ * gets the solve's iteration count and relative residual in iter[0]. */
+irlsu_status irlsu_adjoint(irlsu_plan* plan, const void* gU, int64_t ldg,
+                           const irlsu_params* params,
+                           void* gCv, int64_t ldgcv, void* gCh, int64_t ldgch,
+                           void* gX, int64_t ldgx,
+                           void* workspace, size_t workspace_bytes,
+                           irlsu_stats* stats, void* stream);
+
 /* ---- Step-level entry points (internal layout, see top of file) -------- */
 
 /* Setup (Section 2): Gv, Gh = wrapped differences W(d) = d - 2 pi

@@ -17,7 +17,7 @@ from typing import Optional
 
 __all__ = [
     "IrlsuError", "Params", "Stats", "Plan", "unwrap", "load_library",
-    "library_path", "PRECISIONS", "DECLARED_SYMBOLS",
+    "library_path", "PRECISIONS", "DECLARED_SYMBOLS", "UnwrapFn", "Batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,8 +30,9 @@ IRLSU_MAX_IRLS = 256
 DECLARED_SYMBOLS = (
     "irlsu_status_string", "irlsu_params_default", "irlsu_plan_create",
     "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
-    "irlsu_unwrap", "irlsu_setup", "irlsu_weights", "irlsu_operator",
-    "irlsu_precond",
+    "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
+    "irlsu_operator", "irlsu_precond", "irlsu_batch_create", "irlsu_batch_destroy",
+    "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
 )
 
 STATUS = {
@@ -82,6 +83,13 @@ class Stats(ctypes.Structure):
                     L1_final=self.L1_final, H_final=self.H_final, history=hist)
 
 
+class Tile(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("w", ctypes.c_void_p),
+                ("Cv", ctypes.c_void_p), ("ldcv", ctypes.c_int64),
+                ("Ch", ctypes.c_void_p), ("ldch", ctypes.c_int64),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64)]
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64),
                 ("Np", ctypes.c_int64), ("ld", ctypes.c_int64),
@@ -115,7 +123,14 @@ def load_library():
         "irlsu_workspace_bytes": (SZ, [P]),
         "irlsu_unwrap": (I32, [P, P, I64, P, P, I64, P, I64, P, ctypes.POINTER(Params),
                                P, I64, P, SZ, ctypes.POINTER(Stats), P]),
+        "irlsu_adjoint": (I32, [P, P, I64, ctypes.POINTER(Params), P, I64, P, I64, P, I64,
+                                P, SZ, ctypes.POINTER(Stats), P]),
         "irlsu_setup": (I32, [P, P, I64, P, P, I64, P, I64, P, P, P, P, P, P]),
+        "irlsu_batch_create": (I32, [ctypes.POINTER(P), ctypes.POINTER(I64), I32, I32, P]),
+        "irlsu_batch_destroy": (I32, [P]),
+        "irlsu_batch_workspace_bytes": (SZ, [P]),
+        "irlsu_unwrap_batched": (I32, [P, ctypes.POINTER(Tile), ctypes.POINTER(Params), P, SZ,
+                                       ctypes.POINTER(Stats), P]),
         "irlsu_weights": (I32, [P, D, P, P, P, P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
@@ -198,9 +213,14 @@ class Plan:
         return A[: (rows or self.N), : (cols or self.M)]
 
     # ---- whole path -----------------------------------------------------
-    def unwrap(self, X, weights=None, *, Cv=None, Ch=None, U0=None, params: Optional[Params] = None,
-               out=None, stats: bool = False):
+    def new_workspace(self):
         import torch
+        return torch.empty(int(self.desc.workspace_bytes), dtype=torch.uint8, device=self.device)
+
+    def unwrap(self, X, weights=None, *, Cv=None, Ch=None, U0=None, params: Optional[Params] = None,
+               out=None, stats: bool = False, workspace=None):
+        import torch
+        ws = self.workspace if workspace is None else workspace
         X = _mat(X, self.dtype)
         assert X.shape == (self.N, self.M), "X shape does not match the plan"
         w = None if weights is None else _mat(weights, self.dtype, like=X)
@@ -214,7 +234,7 @@ class Plan:
             _ptr(Cv_t), Cv_t.stride(0) if Cv_t is not None else 0,
             _ptr(Ch_t), Ch_t.stride(0) if Ch_t is not None else 0,
             _ptr(U0_t), ctypes.byref(params) if params is not None else None,
-            _ptr(U), U.stride(0), _ptr(self.workspace), self.workspace.numel(),
+            _ptr(U), U.stride(0), _ptr(ws), ws.numel(),
             ctypes.byref(st) if st is not None else None, _stream())
         _check(code, "unwrap")
         if stats:
@@ -222,6 +242,27 @@ class Plan:
             d["code"] = code
             return U, d
         return U
+
+    def adjoint(self, gU, *, params: Optional[Params] = None, workspace=None, stats: bool = False):
+        """Gradients (gCv, gCh, gX) of a loss with dL/dU = gU through the
+        frozen-weight map at the U of the last unwrap that used `workspace`."""
+        import torch
+        ws = self.workspace if workspace is None else workspace
+        g = _mat(gU, self.dtype)
+        gCv = torch.empty((self.N - 1, self.M), dtype=self.dtype, device=self.device)
+        gCh = torch.empty((self.N, self.M - 1), dtype=self.dtype, device=self.device)
+        gX = torch.empty((self.N, self.M), dtype=self.dtype, device=self.device)
+        st = Stats() if stats else None
+        code = self.lib.irlsu_adjoint(
+            self.handle, _ptr(g), g.stride(0), ctypes.byref(params) if params is not None else None,
+            _ptr(gCv), gCv.stride(0), _ptr(gCh), gCh.stride(0), _ptr(gX), gX.stride(0),
+            _ptr(ws), ws.numel(), ctypes.byref(st) if st is not None else None, _stream())
+        _check(code, "adjoint")
+        if stats:
+            d = st.to_dict()
+            d["code"] = code
+            return gCv, gCh, gX, d
+        return gCv, gCh, gX
 
     # ---- step-level entry points -----------------------------------------
     def setup(self, X, weights=None, Cv=None, Ch=None):
@@ -269,6 +310,58 @@ class Plan:
         return z, rz
 
 
+class Batch:
+    """Uneven tiles unwrapped together: one grouped launch per PCG phase."""
+
+    def __init__(self, shapes, precision: str = "bf16", device=None):
+        import torch
+        self.lib = load_library()
+        self.shapes = [(int(n), int(m)) for n, m in shapes]
+        self.precision = precision
+        self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
+                       else torch.device(device))
+        flat = (ctypes.c_int64 * (2 * len(self.shapes)))(*[v for nm in self.shapes for v in nm])
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _check(self.lib.irlsu_batch_create(ctypes.byref(h), flat, len(self.shapes),
+                                               PRECISIONS[precision], _stream()), "batch_create")
+            self.handle = h
+            nbytes = self.lib.irlsu_batch_workspace_bytes(h)
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.irlsu_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def unwrap(self, Xs, weights=None, *, params: Optional[Params] = None, stats: bool = False):
+        import torch
+        n = len(self.shapes)
+        keep, outs = [], []
+        tiles = (Tile * n)()
+        for t, (N, M) in enumerate(self.shapes):
+            X = _mat(Xs[t], torch.float32)
+            w = None if weights is None or weights[t] is None else _mat(weights[t], torch.float32, like=X)
+            U = torch.empty((N, M), dtype=torch.float32, device=self.device)
+            keep += [X, w]
+            outs.append(U)
+            tiles[t] = Tile(X.data_ptr(), X.stride(0), None if w is None else w.data_ptr(),
+                            None, 0, None, 0, U.data_ptr(), U.stride(0))
+        st = (Stats * n)() if stats else None
+        code = self.lib.irlsu_unwrap_batched(self.handle, tiles, ctypes.byref(params) if params else None,
+                                             _ptr(self.workspace), self.workspace.numel(), st, _stream())
+        _check(code, "unwrap_batched")
+        if stats:
+            return outs, [st[t].to_dict() for t in range(n)]
+        return outs
+
+
 def _mat(A, dtype, like=None):
     import torch
     if not isinstance(A, torch.Tensor):
@@ -304,3 +397,43 @@ def unwrap(X, weights=None, *, Cv=None, Ch=None, precision: str = "f32", params=
     finally:
         if own:
             plan.close()
+
+
+def _autograd_function():
+    import torch
+
+    class UnwrapFn(torch.autograd.Function):
+        """U = unwrap(X, Cv, Ch) with a hand-written adjoint.
+
+        forward runs the IRLS + PCG path on a workspace of its own; backward
+        runs one extra PCG solve on the converged system with the weights
+        frozen (irlsu_adjoint) and returns gradients for X and the per-edge
+        weights Cv, Ch.
+        """
+
+        @staticmethod
+        def forward(ctx, X, Cv, Ch, plan, params=None, adj_params=None):
+            ws = plan.new_workspace()
+            U = plan.unwrap(X, Cv=Cv, Ch=Ch, params=params, workspace=ws)
+            ctx.plan, ctx.ws, ctx.adj_params = plan, ws, adj_params if adj_params is not None else params
+            return U
+
+        @staticmethod
+        def backward(ctx, gU):
+            gCv, gCh, gX = ctx.plan.adjoint(gU.contiguous(), params=ctx.adj_params, workspace=ctx.ws)
+            ctx.ws = None
+            return gX, gCv, gCh, None, None, None
+
+    return UnwrapFn
+
+
+class _LazyFn:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _autograd_function()
+        return _LazyFn._fn.apply(*args)
+
+
+UnwrapFn = _LazyFn()

@@ -9,7 +9,7 @@
 namespace irlsu {
 
 constexpr int kThreads = 256;          // every kernel runs 4 wave64s per block
-constexpr int kMaxPartials = 16384;    // per-block partial sums per quantity
+constexpr int kMaxPartials = 65536;    // per-block partial sums per quantity (all tiles)
 constexpr int kTilePad = 128;          // internal rows / row stride multiple
 
 // Slots of the per-plan device scalar array (double).
@@ -62,10 +62,15 @@ constexpr int PR_ZQ = 4;
 constexpr int PR_ZS = 5;
 constexpr int PR_AUX = 6;
 
+// Device state of one problem (one image, or one tile of a batch): its
+// scalars and flags, and its range [off, off + blocks) of every row of the
+// shared partial-sum table.
 struct DevState {
   double* sc;       // SC_COUNT doubles
   int32_t* fl;      // FL_COUNT ints
-  double* part;     // kPartSlots * kMaxPartials doubles
+  double* part;     // kPartSlots * kMaxPartials doubles (shared by all problems)
+  int32_t off;      // first partial index of this problem
+  int32_t pad_;
 };
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -74,11 +79,12 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// Deterministic block sum of NV doubles; the result is returned in every
-// thread.  Fixed shuffle tree inside each wave, then waves summed in order.
-template <int NV>
+// Deterministic block sum of NV doubles over NT threads; the result is
+// returned in every thread.  Fixed shuffle tree inside each wave, then the
+// waves summed in order.
+template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_sum(double (&v)[NV]) {
-  __shared__ double red[NV][kThreads / 64];
+  __shared__ double red[NV][NT / 64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
 #pragma unroll
@@ -91,18 +97,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) s += red[k][w];
+    for (int w = 0; w < NT / 64; ++w) s += red[k][w];
     v[k] = s;
   }
   __syncthreads();
 }
 
 // Reduce n partials of one slot in a fixed order; identical in every block.
-__device__ __forceinline__ double reduce_slot(const double* part, int slot, int n) {
-  const double* p = part + (size_t)slot * kMaxPartials;
+template <int NT = kThreads>
+__device__ __forceinline__ double reduce_slot(const DevState& st, int slot, int n) {
+  const double* p = st.part + (size_t)slot * kMaxPartials + st.off;
   double s[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += kThreads) s[0] += p[i];
-  block_sum<1>(s);
+  for (int i = threadIdx.x; i < n; i += NT) s[0] += p[i];
+  block_sum<1, NT>(s);
   return s[0];
 }
 
@@ -114,13 +121,15 @@ __device__ __forceinline__ int nblocks() {
   return gridDim.x * gridDim.y * gridDim.z;
 }
 
-template <int NV>
-__device__ __forceinline__ void write_partials(double* part, const int (&slots)[NV], double (&v)[NV]) {
-  block_sum<NV>(v);
+// Block-reduce NV quantities and store them as partial number lb (the
+// block's index within its problem).
+template <int NV, int NT = kThreads>
+__device__ __forceinline__ void write_partials(const DevState& st, const int (&slots)[NV],
+                                               double (&v)[NV], int lb) {
+  block_sum<NV, NT>(v);
   if (threadIdx.x == 0) {
-    const int b = linear_block();
 #pragma unroll
-    for (int k = 0; k < NV; ++k) part[(size_t)slots[k] * kMaxPartials + b] = v[k];
+    for (int k = 0; k < NV; ++k) st.part[(size_t)slots[k] * kMaxPartials + st.off + lb] = v[k];
   }
 }
 

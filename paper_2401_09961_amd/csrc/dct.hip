@@ -81,20 +81,18 @@ struct Mfma<double> {
   }
 };
 
-// Tile shapes per operand type: block BM x BN, depth BK, 4 waves in 2 x 2.
-template <class OT>
-struct Tile {
-  static constexpr int BM = 128, BN = 128, BK = 64;
+// Tile configurations: block BM x BN, depth BK, WGM x WGN waves.
+template <int BM_, int BN_, int BK_, int WGM_, int WGN_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WGM = WGM_, WGN = WGN_;
+  static constexpr int THREADS = 64 * WGM * WGN;
 };
-template <>
-struct Tile<float> {
-  static constexpr int BM = 128, BN = 128, BK = 32;
-};
-template <>
-struct Tile<double> {
-  static constexpr int BM = 64, BN = 64, BK = 16;
-};
-
+// 256 x 256 x 64 with 8 waves of 128 x 64 (8 MFMA tiles, 128 accumulators
+// each): a 64 KB k-tile per block fetched by 512 threads.
+using CfgBig16 = Cfg<256, 256, 64, 2, 4>;
+using CfgSmall16 = Cfg<128, 128, 64, 2, 2>;
+using CfgF32 = Cfg<128, 128, 32, 2, 2>;
+using CfgF64 = Cfg<64, 64, 16, 2, 2>;
 
 struct GemmCtl {
   DevState st;
@@ -103,47 +101,69 @@ struct GemmCtl {
   int nparts_rr;
 };
 
+// Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
+// with its own L2: block b runs on XCD b % 8.  Blocks are renumbered so that
+// each XCD owns a contiguous range of tiles, and that range is walked in
+// groups of GM tile-rows so the tiles resident on one XCD at a time share a
+// few A row-panels and B column-panels in that XCD's L2.
+__device__ __forceinline__ void tile_coords(int bid, int ntm, int ntn, int GM, int& tm, int& tn) {
+  const int total = ntm * ntn;
+  int t = bid;
+  if (total % 8 == 0) t = (bid % 8) * (total / 8) + bid / 8;
+  const int per_group = GM * ntn;
+  const int group = t / per_group;
+  const int first = group * GM;
+  const int gsz = (ntm - first) < GM ? (ntm - first) : GM;
+  const int in = t % per_group;
+  tm = first + in % gsz;
+  tn = in / gsz;
+}
+
 // C[m][n] = sum_k A[m][k] B[n][k]; A is AT (converted to OT while staging),
-// B is OT.  M, N multiples of BM, BN; K a multiple of BK.
-template <class OT, class AT, class Epi>
-__global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict__ A, int64_t lda,
-                                                           const OT* __restrict__ B, int64_t ldb,
-                                                           int64_t K, float ascale, Epi epi,
-                                                           GemmCtl ctl) {
+// B is OT.  M, N multiples of BM, BN; K a multiple of BK.  LDS is
+// double-buffered: the next k-tile is fetched into registers while the
+// current one feeds the MFMAs, then written to the other buffer; one barrier
+// per k-tile.
+template <class OT, class AT, class C, class Epi>
+__device__ __forceinline__ void gemm_body(const AT* __restrict__ A, int64_t lda,
+                                          const OT* __restrict__ B, int64_t ldb, int64_t K, int ntm,
+                                          int ntn, int GM, int bid, float ascale, const Epi& epi,
+                                          const GemmCtl& ctl) {
   using F = Mfma<OT>;
-  constexpr int BM = Tile<OT>::BM, BN = Tile<OT>::BN, BK = Tile<OT>::BK;
+  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, NT = C::THREADS;
   constexpr int TM = F::TM;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WM = BM / C::WGM, WN = BN / C::WGN;
   constexpr int FM = WM / TM, FN = WN / TM;
   constexpr int PAD = 16 / (int)sizeof(OT);
   constexpr int LDS_LD = BK + PAD;
-  // staging: chunks of CH elements along K
-  constexpr int CH = (sizeof(OT) <= 2) ? 8 : (16 / (int)sizeof(OT));
-  constexpr int A_CHUNKS = BM * BK / CH / kThreads;
-  constexpr int B_CHUNKS = BN * BK / CH / kThreads;
-  static_assert(A_CHUNKS * CH * kThreads == BM * BK, "A tile staging");
-  static_assert(B_CHUNKS * CH * kThreads == BN * BK, "B tile staging");
+  constexpr int CH = (sizeof(OT) <= 2) ? 8 : (16 / (int)sizeof(OT));  // staging chunk along K
+  constexpr int A_CHUNKS = BM * BK / CH / NT;
+  constexpr int B_CHUNKS = BN * BK / CH / NT;
+  static_assert(A_CHUNKS * CH * NT == BM * BK, "A tile staging");
+  static_assert(B_CHUNKS * CH * NT == BN * BK, "B tile staging");
 
   if (ctl.check_done && ctl.st.fl[FL_DONE]) return;
   if (ctl.check_conv) {
-    const double rr = reduce_slot(ctl.st.part, PR_RR, ctl.nparts_rr);
+    const double rr = reduce_slot<NT>(ctl.st, PR_RR, ctl.nparts_rr);
     const double thr = ctl.st.sc[SC_TOL2] * ctl.st.sc[SC_BB];
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctl.st.sc[SC_RR] = rr;
+    if (bid == 0 && threadIdx.x == 0) ctl.st.sc[SC_RR] = rr;
     if (rr <= thr) {
-      if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctl.st.fl[FL_DONE] = 1;
+      if (bid == 0 && threadIdx.x == 0) ctl.st.fl[FL_DONE] = 1;
       return;
     }
   }
 
-  __shared__ __attribute__((aligned(16))) OT As[BM * LDS_LD];
-  __shared__ __attribute__((aligned(16))) OT Bs[BN * LDS_LD];
+  __shared__ __attribute__((aligned(16))) OT As[2][BM * LDS_LD];
+  __shared__ __attribute__((aligned(16))) OT Bs[2][BN * LDS_LD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int wm = wave / C::WGN, wn = wave % C::WGN;
+  int tm, tn;
+  tile_coords(bid, ntm, ntn, GM, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM;
+  const int64_t n0 = (int64_t)tn * BN;
 
   typename F::acc_t acc[FM][FN];
 #pragma unroll
@@ -159,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict_
   auto load_tile = [&](int64_t k0) {
 #pragma unroll
     for (int c = 0; c < A_CHUNKS; ++c) {
-      const int idx = tid + c * kThreads;
+      const int idx = tid + c * NT;
       const int row = idx / (BK / CH);
       const int kc = (idx % (BK / CH)) * CH;
       const AT* src = A + (m0 + row) * lda + k0 + kc;
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict_
     }
 #pragma unroll
     for (int c = 0; c < B_CHUNKS; ++c) {
-      const int idx = tid + c * kThreads;
+      const int idx = tid + c * NT;
       const int row = idx / (BK / CH);
       const int kc = (idx % (BK / CH)) * CH;
       const OT* src = B + (n0 + row) * ldb + k0 + kc;
@@ -176,10 +196,10 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict_
       for (int e = 0; e < CH; ++e) rb[c][e] = src[e];
     }
   };
-  auto store_tile = [&]() {
+  auto store_tile = [&](int buf) {
 #pragma unroll
     for (int c = 0; c < A_CHUNKS; ++c) {
-      const int idx = tid + c * kThreads;
+      const int idx = tid + c * NT;
       const int row = idx / (BK / CH);
       const int kc = (idx % (BK / CH)) * CH;
       OT tmp[CH];
@@ -191,24 +211,27 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict_
           tmp[e] = (OT)((float)ra[c][e] * ascale);
       }
 #pragma unroll
-      for (int e = 0; e < CH; ++e) As[row * LDS_LD + kc + e] = tmp[e];
+      for (int e = 0; e < CH; ++e) As[buf][row * LDS_LD + kc + e] = tmp[e];
     }
 #pragma unroll
     for (int c = 0; c < B_CHUNKS; ++c) {
-      const int idx = tid + c * kThreads;
+      const int idx = tid + c * NT;
       const int row = idx / (BK / CH);
       const int kc = (idx % (BK / CH)) * CH;
 #pragma unroll
-      for (int e = 0; e < CH; ++e) Bs[row * LDS_LD + kc + e] = rb[c][e];
+      for (int e = 0; e < CH; ++e) Bs[buf][row * LDS_LD + kc + e] = rb[c][e];
     }
   };
 
   const int64_t nk = K / BK;
   load_tile(0);
-  store_tile();
+  store_tile(0);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
+    const OT* as = As[buf];
+    const OT* bs = Bs[buf];
 #pragma unroll
     for (int ks = 0; ks < BK / F::TK; ++ks) {
       typename F::frag_t fa[FM], fb[FN];
@@ -216,23 +239,20 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict_
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
         const int row = wm * WM + a * TM + (lane % TM);
-        fa[a] = *reinterpret_cast<const typename F::frag_t*>(&As[row * LDS_LD + kk]);
+        fa[a] = *reinterpret_cast<const typename F::frag_t*>(&as[row * LDS_LD + kk]);
       }
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
         const int row = wn * WN + b * TM + (lane % TM);
-        fb[b] = *reinterpret_cast<const typename F::frag_t*>(&Bs[row * LDS_LD + kk]);
+        fb[b] = *reinterpret_cast<const typename F::frag_t*>(&bs[row * LDS_LD + kk]);
       }
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = F::mma(fa[a], fb[b], acc[a][b]);
     }
+    if (kt + 1 < nk) store_tile(buf ^ 1);
     __syncthreads();
-    if (kt + 1 < nk) {
-      store_tile();
-      __syncthreads();
-    }
   }
 
   // Epilogue: group g of lane l holds rows row0(g, l) + t RS (t = 0..3) of
@@ -249,8 +269,18 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(const AT* __restrict_
         typename F::acc_e v[4] = {acc[a][b][4 * g], acc[a][b][4 * g + 1], acc[a][b][4 * g + 2],
                                   acc[a][b][4 * g + 3]};
         epi.template apply<F::RS>(m, n, v, part);
+        // keep the epilogue's loads from being hoisted across tiles
+        __builtin_amdgcn_sched_barrier(0);
       }
-  epi.finish(part, ctl.st);
+  epi.template finish<NT>(part, ctl.st, bid);
+}
+
+template <class OT, class AT, class C, class Epi>
+__global__ __launch_bounds__(C::THREADS) void gemm_nt_kernel(const AT* __restrict__ A, int64_t lda,
+                                                             const OT* __restrict__ B, int64_t ldb,
+                                                             int64_t K, int ntm, int ntn, int GM,
+                                                             float ascale, Epi epi, GemmCtl ctl) {
+  gemm_body<OT, AT, C, Epi>(A, lda, B, ldb, K, ntm, ntn, GM, (int)blockIdx.x, ascale, epi, ctl);
 }
 
 // ---- epilogues ------------------------------------------------------------
@@ -268,7 +298,8 @@ struct EpiStoreT {
 #pragma unroll
     for (int t = 0; t < 4; ++t) d[t * RS] = (OT)v[t];
   }
-  __device__ __forceinline__ void finish(Acc&, DevState) const {}
+  template <int NT>
+  __device__ __forceinline__ void finish(Acc&, const DevState&, int) const {}
 };
 
 // Direct store with the spectral division: C[m][n] = v / (eigM[m] + eigN[n]),
@@ -291,7 +322,8 @@ struct EpiScale {
       C[mm * ldc + n] = (OT)((double)v[t] * f);
     }
   }
-  __device__ __forceinline__ void finish(Acc&, DevState) const {}
+  template <int NT>
+  __device__ __forceinline__ void finish(Acc&, const DevState&, int) const {}
 };
 
 // Final product: z (vector type T), partial sums of z.r, z.q, sum z.
@@ -318,20 +350,46 @@ struct EpiFinal {
       acc.zs += zd;
     }
   }
-  __device__ __forceinline__ void finish(Acc& acc, DevState st) const {
+  template <int NT>
+  __device__ __forceinline__ void finish(Acc& acc, const DevState& st, int lb) const {
     double v[3] = {acc.zr, acc.zq, acc.zs};
     const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
-    write_partials<3>(st.part, slots, v);
+    write_partials<3, NT>(st, slots, v, lb);
   }
 };
 
-template <class OT, class AT, class Epi>
-static void gemm(const AT* A, int64_t lda, const OT* B, int64_t ldb, int64_t Mg, int64_t Ng,
-                 int64_t K, float ascale, const Epi& epi, const GemmCtl& ctl, hipStream_t s) {
-  constexpr int BM = Tile<OT>::BM, BN = Tile<OT>::BN;
-  const dim3 grid((unsigned)(Ng / BN), (unsigned)(Mg / BM));
-  hipLaunchKernelGGL((gemm_nt_kernel<OT, AT, Epi>), grid, dim3(kThreads), 0, s, A, lda, B, ldb, K,
-                     ascale, epi, ctl);
+template <class OT>
+struct CfgFor {
+  using type = CfgSmall16;
+};
+template <>
+struct CfgFor<float> {
+  using type = CfgF32;
+};
+template <>
+struct CfgFor<double> {
+  using type = CfgF64;
+};
+
+// Launch one product with the largest configuration whose tiles divide the
+// problem; returns the number of blocks (partials of the final epilogue).
+template <class OT, class AT, class Epi, bool kBig = true>
+static int gemm(const AT* A, int64_t lda, const OT* B, int64_t ldb, int64_t Mg, int64_t Ng,
+                int64_t K, float ascale, const Epi& epi, const GemmCtl& ctl, hipStream_t s) {
+  if constexpr (sizeof(OT) == 2 && kBig) {
+    using CB = CfgBig16;
+    if (Mg % CB::BM == 0 && Ng % CB::BN == 0 && K % CB::BK == 0) {
+      const int ntm = (int)(Mg / CB::BM), ntn = (int)(Ng / CB::BN);
+      hipLaunchKernelGGL((gemm_nt_kernel<OT, AT, CB, Epi>), dim3(ntm * ntn), dim3(CB::THREADS), 0,
+                         s, A, lda, B, ldb, K, ntm, ntn, 4, ascale, epi, ctl);
+      return ntm * ntn;
+    }
+  }
+  using CS = typename CfgFor<OT>::type;
+  const int ntm = (int)(Mg / CS::BM), ntn = (int)(Ng / CS::BN);
+  hipLaunchKernelGGL((gemm_nt_kernel<OT, AT, CS, Epi>), dim3(ntm * ntn), dim3(CS::THREADS), 0, s,
+                     A, lda, B, ldb, K, ntm, ntn, 8, ascale, epi, ctl);
+  return ntm * ntn;
 }
 
 template <class OT, class T>
@@ -356,12 +414,13 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
                cn, s);
   // G3: T3 = (T2^T P_N^T)^T = P_N T2
   gemm<OT, OT>(T2, Np, PN, Np, Mp, Np, Np, 1.0f, EpiStoreT<OT>{T3, Mp}, cn, s);
-  // G4: z = T3 P_M^T
-  gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
-               EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
-                           1.0 / a.scale},
-               cn, s);
-  return (int)((Mp / Tile<OT>::BN) * (Np / Tile<OT>::BM));
+  // G4: z = T3 P_M^T (the 128 x 128 tile: its epilogue reads r and q and
+  // accumulates three FP64 sums, which does not fit beside the 256 x 256
+  // tile's registers)
+  return gemm<OT, OT, EpiFinal<T>, false>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
+                      EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
+                                  1.0 / a.scale},
+                      cn, s);
 }
 
 int launch_precond(const PrecondArgs& a, hipStream_t s) {
@@ -372,6 +431,87 @@ int launch_precond(const PrecondArgs& a, hipStream_t s) {
     case OK_F16: return precond_impl<_Float16, float>(a, s);
   }
   return 0;
+}
+
+// ---- grouped products over the tiles of a batch ------------------------
+// The configuration of each product is fixed per launch: tiles are padded to
+// multiples of 256 so that G1..G3 use the 256 x 256 tile, G4 the 128 x 128.
+template <class OT, int G>
+struct BatchCfg {
+  using type = typename std::conditional<G == 4, CfgSmall16, CfgBig16>::type;
+};
+
+template <int G>
+constexpr int batch_threads() {
+  return G == 4 ? CfgSmall16::THREADS : CfgBig16::THREADS;
+}
+
+template <class OT, class T, int G>
+__global__ __launch_bounds__(batch_threads<G>()) void gemm_batched_kernel(
+    const BatchTile<T>* tiles, const int32_t* start, int ntiles, int check_conv) {
+  using C = typename BatchCfg<OT, G>::type;
+  const int t = find_tile(start, ntiles, (int)blockIdx.x);
+  const BatchTile<T>& bt = tiles[t];
+  const int bid = (int)blockIdx.x - start[t];
+  const int64_t Np = bt.Np, Mp = bt.ld;
+  GemmCtl ctl{bt.st, 1, G == 1 ? check_conv : 0, bt.st_nblk};
+  if constexpr (G == 1) {
+    gemm_body<OT, T, C>(bt.r, Mp, static_cast<const OT*>(bt.PMt), Mp, Mp, (int)(Np / C::BM),
+                        (int)(Mp / C::BN), 4, bid, 1.0f,
+                        EpiStoreT<OT>{static_cast<OT*>(bt.T1), Np}, ctl);
+  } else if constexpr (G == 2) {
+    gemm_body<OT, OT, C>(static_cast<const OT*>(bt.T1), Np, static_cast<const OT*>(bt.PNt), Np, Np,
+                         (int)(Mp / C::BM), (int)(Np / C::BN), 4, bid, 1.0f,
+                         EpiScale<OT>{static_cast<OT*>(bt.T2), Np, bt.eigM, bt.eigN}, ctl);
+  } else if constexpr (G == 3) {
+    gemm_body<OT, OT, C>(static_cast<const OT*>(bt.T2), Np, static_cast<const OT*>(bt.PN), Np, Np,
+                         (int)(Mp / C::BM), (int)(Np / C::BN), 4, bid, 1.0f,
+                         EpiStoreT<OT>{static_cast<OT*>(bt.T3), Mp}, ctl);
+  } else {
+    gemm_body<OT, OT, C>(static_cast<const OT*>(bt.T3), Mp, static_cast<const OT*>(bt.PM), Mp, Mp,
+                         (int)(Np / C::BM), (int)(Mp / C::BN), 8, bid, 1.0f,
+                         EpiFinal<T>{bt.z, bt.r, bt.flexible_q ? bt.q : nullptr, Mp, 1.0}, ctl);
+  }
+}
+
+void precond_blocks(int kind, int64_t Np, int64_t Mp, int out[4]) {
+  (void)kind;
+  const int64_t B = CfgBig16::BM, S = CfgSmall16::BM;
+  out[0] = (int)((Np / B) * (Mp / B));
+  out[1] = (int)((Mp / B) * (Np / B));
+  out[2] = out[1];
+  out[3] = (int)((Np / S) * (Mp / S));
+}
+
+template <class OT>
+static void precond_batched_impl(const BatchTile<float>* tiles, const int32_t* starts, int ntiles,
+                                 const int* totals, int check_conv, hipStream_t s) {
+  const int n1 = ntiles + 1;
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 1>), dim3(totals[0]),
+                     dim3(BatchCfg<OT, 1>::type::THREADS), 0, s, tiles, starts, ntiles, check_conv);
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 2>), dim3(totals[1]),
+                     dim3(BatchCfg<OT, 2>::type::THREADS), 0, s, tiles, starts + n1, ntiles, 0);
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 3>), dim3(totals[2]),
+                     dim3(BatchCfg<OT, 3>::type::THREADS), 0, s, tiles, starts + 2 * n1, ntiles, 0);
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 4>), dim3(totals[3]),
+                     dim3(BatchCfg<OT, 4>::type::THREADS), 0, s, tiles, starts + 3 * n1, ntiles, 0);
+}
+
+void launch_precond_batched(int kind, const void* tiles, const int32_t* starts, int ntiles,
+                            const int* totals, int check_conv, hipStream_t s) {
+  const BatchTile<float>* t = static_cast<const BatchTile<float>*>(tiles);
+  if (kind == OK_F16)
+    precond_batched_impl<_Float16>(t, starts, ntiles, totals, check_conv, s);
+  else
+    precond_batched_impl<__bf16>(t, starts, ntiles, totals, check_conv, s);
+}
+
+int precond_nparts(int kind, int64_t Np, int64_t Mp) {
+  switch (kind) {
+    case OK_F64: return (int)((Np / CfgF64::BM) * (Mp / CfgF64::BN));
+    case OK_F32: return (int)((Np / CfgF32::BM) * (Mp / CfgF32::BN));
+    default: return (int)((Np / CfgSmall16::BM) * (Mp / CfgSmall16::BN));
+  }
 }
 
 // ---- basis tables ------------------------------------------------------

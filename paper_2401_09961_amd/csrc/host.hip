@@ -9,10 +9,13 @@
 // Every scalar (rho, alpha, beta, norms) lives on the device and is reduced in
 // a fixed order inside the consuming kernel's prologue; the host only reads
 // the convergence flag every poll_every iterations.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -37,6 +40,30 @@ struct irlsu_plan {
   int device = 0;
 };
 
+struct irlsu_batch {
+  int32_t ntiles = 0;
+  irlsu_precision prec = IRLSU_MIXED_BF16;
+  int kind = OK_BF16;
+  std::vector<int64_t> N, M, Np, Mp;
+  // basis tables per distinct side length
+  std::map<int64_t, int> side_index;
+  std::vector<void*> P, Pt;
+  std::vector<double*> eig;
+  // per-tile grids and partial ranges
+  std::vector<int32_t> st_gx, st_rows, st_nblk, g4_nparts, part_off;
+  int32_t st_total = 0;
+  int g_total[4] = {0, 0, 0, 0};
+  int32_t* d_st_start = nullptr;   // ntiles + 1
+  int32_t* d_g_start = nullptr;    // 4 (ntiles + 1)
+  void* d_tiles = nullptr;         // BatchTile<float>[ntiles]
+  void* h_tiles = nullptr;         // pinned staging of the table
+  int32_t* h_flags = nullptr;      // pinned, ntiles * FL_COUNT
+  double* h_sc = nullptr;          // pinned, ntiles * SC_COUNT
+  size_t ws_bytes = 0;
+  std::vector<size_t> tile_off;    // workspace offset of each tile's vectors
+  size_t part_off_bytes = 0, sc_off = 0, fl_off = 0;
+};
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -46,7 +73,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 enum VecId { V_R, V_Z, V_P0, V_P1, V_Q, V_B, V_GV, V_GH, V_CV, V_CH, V_OV, V_OH, V_COUNT };
 
 struct Layout {
-  size_t u, vec[V_COUNT], t1, t2, t3, part, sc, fl, total;
+  size_t u, lam, vec[V_COUNT], t1, t2, t3, part, sc, fl, total;
 };
 
 Layout layout(const irlsu_plan* p) {
@@ -54,6 +81,8 @@ Layout layout(const irlsu_plan* p) {
   const size_t npx = (size_t)p->Np * (size_t)p->Mp;
   size_t off = 0;
   L.u = off;
+  off = align_up(off + npx * sizeof(double));
+  L.lam = off;
   off = align_up(off + npx * sizeof(double));
   for (int v = 0; v < V_COUNT; ++v) {
     L.vec[v] = off;
@@ -78,6 +107,7 @@ Layout layout(const irlsu_plan* p) {
 template <class T>
 struct Ws {
   double* U;
+  double* lam;
   T* v[V_COUNT];
   void *T1, *T2, *T3;
   DevState st;
@@ -89,6 +119,7 @@ Ws<T> carve(const irlsu_plan* p, void* base) {
   char* b = static_cast<char*>(base);
   Ws<T> w;
   w.U = reinterpret_cast<double*>(b + L.u);
+  w.lam = reinterpret_cast<double*>(b + L.lam);
   for (int v = 0; v < V_COUNT; ++v) w.v[v] = reinterpret_cast<T*>(b + L.vec[v]);
   w.T1 = b + L.t1;
   w.T2 = b + L.t2;
@@ -168,6 +199,73 @@ irlsu_status read_back(irlsu_plan* pl, const Ws<T>& W, hipStream_t s) {
   return IRLSU_OK;
 }
 
+// PCG (Algorithm 2) on D^T Omega D x = rhs with the Omega currently in the
+// workspace, warm-started at x (FP64).  ||rhs||^2 and tol^2 must already be in
+// SC_BB / SC_TOL2 and the flags cleared (finalize_weights / adjoint rhs).
+template <class T>
+irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
+                       const irlsu_params& prm, int flexible, int* iters_out, double* relres_out,
+                       irlsu_status* solve_st, hipStream_t s) {
+  DevState st = W.st;
+  const size_t npx = (size_t)pl->Np * (size_t)pl->Mp;
+  const int nvec = stencil_blocks(pl);
+  T* P[2] = {W.v[V_P0], W.v[V_P1]};
+  StencilArgs<T> ra = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
+  ra.u = x;
+  ra.b = rhs;
+  ra.r = W.v[V_R];
+  ra.check_done = 0;
+  launch_stencil<T>(ST_RESID, ra, s);
+  PrecondArgs pa = precond_args<T>(pl, W, W.v[V_R], W.v[V_Z], flexible ? W.v[V_Q] : nullptr, 1,
+                                   nvec);
+  const int nprec = launch_precond(pa, s);
+  for (int l = 0; l < prm.pcg_max; ++l) {
+    StencilArgs<T> fa = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
+    fa.z = W.v[V_Z];
+    fa.p_in = P[(l + 1) & 1];
+    fa.p_out = P[l & 1];
+    fa.q = W.v[V_Q];
+    fa.iter = l;
+    fa.flexible = flexible;
+    fa.nparts_prec = nprec;
+    fa.nparts_res = nvec;
+    fa.check_done = 1;
+    const int npq = launch_stencil<T>(ST_FUSED, fa, s);
+    AxpyArgs<T> xa;
+    xa.u = x;
+    xa.r = W.v[V_R];
+    xa.p = P[l & 1];
+    xa.q = W.v[V_Q];
+    xa.n = (int64_t)npx;
+    xa.nparts_pq = npq;
+    xa.iter = l;
+    xa.st = st;
+    launch_axpy<T>(xa, s, nvec);
+    if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max) {
+      ra.check_done = 1;
+      launch_stencil<T>(ST_RESID, ra, s);
+    }
+    if (l + 1 < prm.pcg_max) launch_precond(pa, s);
+    if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+    if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
+      HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            s));
+      HIP_OK(hipStreamSynchronize(s));
+      if (pl->h_flags[FL_DONE]) break;
+    }
+  }
+  launch_finalize_rr(st, nvec, s);
+  irlsu_status rs = read_back(pl, W, s);
+  if (rs != IRLSU_OK) return rs;
+  *iters_out = pl->h_flags[FL_ITERS];
+  *solve_st = IRLSU_OK;
+  if (pl->h_flags[FL_STATUS] & 1) *solve_st = IRLSU_ERR_BREAKDOWN;
+  else if (!pl->h_flags[FL_DONE] && *iters_out >= prm.pcg_max) *solve_st = IRLSU_NOT_CONVERGED;
+  const double bb = pl->h_sc[SC_BB];
+  *relres_out = bb > 0 ? std::sqrt(pl->h_sc[SC_RR] / bb) : 0.0;
+  return IRLSU_OK;
+}
+
 template <class T>
 irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, const T* Cv,
                          int64_t ldcv, const T* Ch, int64_t ldch, const T* U0,
@@ -211,9 +309,7 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
 
   const int flexible = prm.flexible < 0 ? (is_mixed(pl->prec) ? 1 : 0) : prm.flexible;
   const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
-  const int nvec = stencil_blocks(pl);
   const bool want_obj = stats != nullptr || prm.l1_target > 0.0;
-  T* P[2] = {W.v[V_P0], W.v[V_P1]};
 
   WeightsArgs<T> wa;
   wa.U = W.U;
@@ -248,63 +344,15 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
       }
     }
     // ---- PCG (Algorithm 2), warm start from the current U ----
-    StencilArgs<T> ra = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
-    ra.u = W.U;
-    ra.b = W.v[V_B];
-    ra.r = W.v[V_R];
-    ra.check_done = 0;
-    launch_stencil<T>(ST_RESID, ra, s);
-    PrecondArgs pa = precond_args<T>(pl, W, W.v[V_R], W.v[V_Z], flexible ? W.v[V_Q] : nullptr, 1,
-                                     nvec);
-    const int nprec = launch_precond(pa, s);
-    int l = 0;
-    for (l = 0; l < prm.pcg_max; ++l) {
-      StencilArgs<T> fa = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
-      fa.z = W.v[V_Z];
-      fa.p_in = P[(l + 1) & 1];
-      fa.p_out = P[l & 1];
-      fa.q = W.v[V_Q];
-      fa.iter = l;
-      fa.flexible = flexible;
-      fa.nparts_prec = nprec;
-      fa.nparts_res = nvec;
-      fa.check_done = 1;
-      const int npq = launch_stencil<T>(ST_FUSED, fa, s);
-      AxpyArgs<T> xa;
-      xa.u = W.U;
-      xa.r = W.v[V_R];
-      xa.p = P[l & 1];
-      xa.q = W.v[V_Q];
-      xa.n = (int64_t)npx;
-      xa.nparts_pq = npq;
-      xa.iter = l;
-      xa.st = st;
-      launch_axpy<T>(xa, s, nvec);
-      if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max) {
-        ra.check_done = 1;
-        launch_stencil<T>(ST_RESID, ra, s);
-      }
-      if (l + 1 < prm.pcg_max) launch_precond(pa, s);
-      if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
-      if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
-        HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        if (pl->h_flags[FL_DONE]) break;
-      }
-    }
-    launch_finalize_rr(st, nvec, s);
-    rs = read_back(pl, W, s);
-    if (rs != IRLSU_OK) return rs;
-    const int iters = pl->h_flags[FL_ITERS];
+    int iters = 0;
+    double relres = 0.0;
     irlsu_status solve_st = IRLSU_OK;
-    if (pl->h_flags[FL_STATUS] & 1) solve_st = IRLSU_ERR_BREAKDOWN;
-    else if (!pl->h_flags[FL_DONE] && iters >= prm.pcg_max) solve_st = IRLSU_NOT_CONVERGED;
+    rs = pcg_solve<T>(pl, W, W.U, W.v[V_B], prm, flexible, &iters, &relres, &solve_st, s);
+    if (rs != IRLSU_OK) return rs;
     if (stats && k < IRLSU_MAX_IRLS) {
       stats->iter[k].pcg_iters = iters;
       stats->iter[k].status = solve_st;
-      const double bb = pl->h_sc[SC_BB];
-      stats->iter[k].relres = bb > 0 ? std::sqrt(pl->h_sc[SC_RR] / bb) : 0.0;
+      stats->iter[k].relres = relres;
     }
     pcg_total += iters;
     done_iters = k + 1;
@@ -335,6 +383,311 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
   if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
   if (stats) HIP_OK(hipStreamSynchronize(s));
   return overall;
+}
+
+// Adjoint solve on the state an irlsu_unwrap call left in the workspace:
+// frozen weights at the final U, one PCG solve, edge gradients.
+template <class T>
+irlsu_status adjoint_impl(irlsu_plan* pl, const T* gU, int64_t ldg, const irlsu_params& prm,
+                          T* gCv, int64_t ldgcv, T* gCh, int64_t ldgch, T* gX, int64_t ldgx,
+                          void* ws, irlsu_stats* stats, hipStream_t s) {
+  const Ws<T> W = carve<T>(pl, ws);
+  const int64_t N = pl->N, M = pl->M, Np = pl->Np, ld = pl->Mp;
+  const size_t npx = (size_t)Np * (size_t)ld;
+  DevState st = W.st;
+  WeightsArgs<T> wa;
+  wa.U = W.U;
+  wa.Gv = W.v[V_GV];
+  wa.Gh = W.v[V_GH];
+  wa.Cv = W.v[V_CV];
+  wa.Ch = W.v[V_CH];
+  wa.Ov = W.v[V_OV];
+  wa.Oh = W.v[V_OH];
+  wa.b = W.v[V_B];
+  wa.eps = prm.eps;
+  wa.Np = Np;
+  wa.ld = ld;
+  wa.st = st;
+  launch_weights<T>(wa, s);
+  launch_adjoint_rhs<T>(gU, ldg, N, M, Np, ld, W.v[V_B], st, prm.pcg_rtol * prm.pcg_rtol, s);
+  HIP_OK(hipMemsetAsync(W.lam, 0, npx * sizeof(double), s));
+  const int flexible = prm.flexible < 0 ? (is_mixed(pl->prec) ? 1 : 0) : prm.flexible;
+  int iters = 0;
+  double relres = 0.0;
+  irlsu_status solve_st = IRLSU_OK;
+  irlsu_status rs = pcg_solve<T>(pl, W, W.lam, W.v[V_B], prm, flexible, &iters, &relres,
+                                 &solve_st, s);
+  if (rs != IRLSU_OK) return rs;
+  if (solve_st == IRLSU_ERR_BREAKDOWN) return solve_st;
+  AdjEdgeArgs<T> ea;
+  ea.U = W.U;
+  ea.lam = W.lam;
+  ea.Gv = W.v[V_GV];
+  ea.Gh = W.v[V_GH];
+  ea.Cv = W.v[V_CV];
+  ea.Ch = W.v[V_CH];
+  ea.eps = prm.eps;
+  ea.N = N;
+  ea.M = M;
+  ea.ld = ld;
+  ea.gCv = gCv;
+  ea.ldgcv = ldgcv;
+  ea.gCh = gCh;
+  ea.ldgch = ldgch;
+  ea.gX = gX;
+  ea.ldgx = ldgx;
+  launch_adjoint_edges<T>(ea, s);
+  if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->irls_done = 0;
+    stats->pcg_total = iters;
+    stats->status = solve_st;
+    stats->iter[0].pcg_iters = iters;
+    stats->iter[0].relres = relres;
+    stats->iter[0].status = solve_st;
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  return solve_st;
+}
+
+// ---------------------------------------------------------------------------
+// Batched tiles: every PCG phase is one grouped launch over all tiles.
+// ---------------------------------------------------------------------------
+constexpr int64_t kBatchPad = 256;
+constexpr int kBatchVecs = 12;  // r z p0 p1 q b Gv Gh Cv Ch Ov Oh
+
+size_t batch_tile_bytes(int64_t Np, int64_t Mp) {
+  const size_t npx = (size_t)Np * (size_t)Mp;
+  return align_up(npx * sizeof(double)) + kBatchVecs * align_up(npx * sizeof(float)) +
+         3 * align_up(npx * 2);
+}
+
+struct TileWs {
+  double* U;
+  float* v[kBatchVecs];
+  void *T1, *T2, *T3;
+};
+
+TileWs carve_tile(const irlsu_batch* b, void* base, int t) {
+  const size_t npx = (size_t)b->Np[t] * (size_t)b->Mp[t];
+  char* p = static_cast<char*>(base) + b->tile_off[t];
+  TileWs w;
+  w.U = reinterpret_cast<double*>(p);
+  p += align_up(npx * sizeof(double));
+  for (int v = 0; v < kBatchVecs; ++v) {
+    w.v[v] = reinterpret_cast<float*>(p);
+    p += align_up(npx * sizeof(float));
+  }
+  w.T1 = p;
+  p += align_up(npx * 2);
+  w.T2 = p;
+  p += align_up(npx * 2);
+  w.T3 = p;
+  return w;
+}
+
+DevState tile_state(const irlsu_batch* b, void* base, int t) {
+  char* p = static_cast<char*>(base);
+  DevState st;
+  st.part = reinterpret_cast<double*>(p + b->part_off_bytes);
+  st.sc = reinterpret_cast<double*>(p + b->sc_off) + (size_t)t * SC_COUNT;
+  st.fl = reinterpret_cast<int32_t*>(p + b->fl_off) + (size_t)t * FL_COUNT;
+  st.off = b->part_off[t];
+  st.pad_ = 0;
+  return st;
+}
+
+irlsu_status batch_read_back(irlsu_batch* b, void* ws, hipStream_t s) {
+  char* p = static_cast<char*>(ws);
+  HIP_OK(hipMemcpyAsync(b->h_flags, p + b->fl_off, (size_t)b->ntiles * FL_COUNT * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(b->h_sc, p + b->sc_off, (size_t)b->ntiles * SC_COUNT * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return IRLSU_OK;
+}
+
+irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const irlsu_params& prm,
+                                 void* ws, irlsu_stats* stats, hipStream_t s) {
+  const int nt = b->ntiles;
+  char* base = static_cast<char*>(ws);
+  HIP_OK(hipMemsetAsync(base + b->sc_off, 0, (size_t)nt * SC_COUNT * sizeof(double), s));
+  HIP_OK(hipMemsetAsync(base + b->fl_off, 0, (size_t)nt * FL_COUNT * sizeof(int32_t), s));
+  BatchTile<float>* ht = static_cast<BatchTile<float>*>(b->h_tiles);
+  for (int t = 0; t < nt; ++t) {
+    const TileWs w = carve_tile(b, ws, t);
+    const size_t npx = (size_t)b->Np[t] * (size_t)b->Mp[t];
+    for (int v = 0; v < kBatchVecs; ++v) HIP_OK(hipMemsetAsync(w.v[v], 0, npx * sizeof(float), s));
+    const DevState st = tile_state(b, ws, t);
+    SetupArgs<float> sa;
+    sa.X = static_cast<const float*>(tiles[t].X);
+    sa.ldx = tiles[t].ldx;
+    sa.w = static_cast<const float*>(tiles[t].w);
+    sa.Cv = static_cast<const float*>(tiles[t].Cv);
+    sa.ldcv = tiles[t].ldcv;
+    sa.Ch = static_cast<const float*>(tiles[t].Ch);
+    sa.ldch = tiles[t].ldch;
+    sa.U0 = nullptr;
+    sa.ldu0 = 0;
+    sa.N = b->N[t];
+    sa.M = b->M[t];
+    sa.Np = b->Np[t];
+    sa.ld = b->Mp[t];
+    sa.Gv = w.v[6];
+    sa.Gh = w.v[7];
+    sa.Cv_out = w.v[8];
+    sa.Ch_out = w.v[9];
+    sa.U = w.U;
+    sa.flags = st.fl + FL_INPUT;
+    launch_setup<float>(sa, s);
+    BatchTile<float>& bt = ht[t];
+    bt.N = b->N[t];
+    bt.M = b->M[t];
+    bt.Np = b->Np[t];
+    bt.ld = b->Mp[t];
+    bt.U = w.U;
+    bt.r = w.v[0];
+    bt.z = w.v[1];
+    bt.p0 = w.v[2];
+    bt.p1 = w.v[3];
+    bt.q = w.v[4];
+    bt.b = w.v[5];
+    bt.Ov = w.v[10];
+    bt.Oh = w.v[11];
+    bt.st = st;
+    bt.st_gx = b->st_gx[t];
+    bt.st_rows = b->st_rows[t];
+    bt.st_nblk = b->st_nblk[t];
+    bt.g4_nparts = b->g4_nparts[t];
+    bt.flexible_q = 0;
+    bt.pad_ = 0;
+    bt.T1 = w.T1;
+    bt.T2 = w.T2;
+    bt.T3 = w.T3;
+    const int in = b->side_index.at(b->N[t]), im = b->side_index.at(b->M[t]);
+    bt.PN = b->P[in];
+    bt.PNt = b->Pt[in];
+    bt.PM = b->P[im];
+    bt.PMt = b->Pt[im];
+    bt.eigN = b->eig[in];
+    bt.eigM = b->eig[im];
+  }
+  if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+  irlsu_status rs = batch_read_back(b, ws, s);
+  if (rs != IRLSU_OK) return rs;
+  for (int t = 0; t < nt; ++t) {
+    if (b->h_flags[t * FL_COUNT + FL_INPUT] & 1) return IRLSU_ERR_NONFINITE;
+    if (b->h_flags[t * FL_COUNT + FL_INPUT] & 2) return IRLSU_ERR_BAD_WEIGHTS;
+  }
+  const int flexible = prm.flexible < 0 ? 1 : prm.flexible;
+  for (int t = 0; t < nt; ++t) ht[t].flexible_q = flexible;
+  HIP_OK(hipMemcpyAsync(b->d_tiles, b->h_tiles, (size_t)nt * sizeof(BatchTile<float>),
+                        hipMemcpyHostToDevice, s));
+  const BatchTile<float>* dt = static_cast<const BatchTile<float>*>(b->d_tiles);
+  const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
+  std::vector<int> pcg_total(nt, 0);
+  std::vector<irlsu_status> overall(nt, IRLSU_OK);
+  if (stats) std::memset(stats, 0, (size_t)nt * sizeof(irlsu_stats));
+
+  auto weights_all = [&]() {
+    for (int t = 0; t < nt; ++t) {
+      const BatchTile<float>& bt = ht[t];
+      const TileWs w = carve_tile(b, ws, t);
+      WeightsArgs<float> wa;
+      wa.U = w.U;
+      wa.Gv = w.v[6];
+      wa.Gh = w.v[7];
+      wa.Cv = w.v[8];
+      wa.Ch = w.v[9];
+      wa.Ov = w.v[10];
+      wa.Oh = w.v[11];
+      wa.b = w.v[5];
+      wa.eps = prm.eps;
+      wa.Np = bt.Np;
+      wa.ld = bt.ld;
+      wa.st = bt.st;
+      const int nw = launch_weights<float>(wa, s);
+      launch_finalize_weights(bt.st, nw, nullptr, tol2, s);
+    }
+  };
+
+  for (int k = 0; k < prm.irls_iters; ++k) {
+    weights_all();
+    if (stats) {
+      rs = batch_read_back(b, ws, s);
+      if (rs != IRLSU_OK) return rs;
+      for (int t = 0; t < nt && k < IRLSU_MAX_IRLS; ++t) {
+        stats[t].iter[k].L1 = b->h_sc[t * SC_COUNT + SC_L1];
+        stats[t].iter[k].H = b->h_sc[t * SC_COUNT + SC_H];
+      }
+    }
+    launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, 0, flexible, 0, s);
+    launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, s);
+    for (int l = 0; l < prm.pcg_max; ++l) {
+      launch_stencil_batched<float>(ST_FUSED, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
+                                    s);
+      launch_axpy_batched<float>(dt, b->d_st_start, nt, b->st_total, l, s);
+      if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max)
+        launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
+                                      s);
+      if (l + 1 < prm.pcg_max) launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, s);
+      if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+      if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
+        HIP_OK(hipMemcpyAsync(b->h_flags, base + b->fl_off, (size_t)nt * FL_COUNT * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int t = 0; t < nt; ++t) all = all && b->h_flags[t * FL_COUNT + FL_DONE];
+        if (all) break;
+      }
+    }
+    for (int t = 0; t < nt; ++t) launch_finalize_rr(ht[t].st, ht[t].st_nblk, s);
+    rs = batch_read_back(b, ws, s);
+    if (rs != IRLSU_OK) return rs;
+    for (int t = 0; t < nt; ++t) {
+      const int32_t* f = b->h_flags + t * FL_COUNT;
+      const int iters = f[FL_ITERS];
+      irlsu_status st = IRLSU_OK;
+      if (f[FL_STATUS] & 1) st = IRLSU_ERR_BREAKDOWN;
+      else if (!f[FL_DONE] && iters >= prm.pcg_max) st = IRLSU_NOT_CONVERGED;
+      if (st == IRLSU_ERR_BREAKDOWN) return st;
+      if (st == IRLSU_NOT_CONVERGED) overall[t] = st;
+      pcg_total[t] += iters;
+      if (stats && k < IRLSU_MAX_IRLS) {
+        stats[t].iter[k].pcg_iters = iters;
+        stats[t].iter[k].status = st;
+        const double bb = b->h_sc[t * SC_COUNT + SC_BB];
+        stats[t].iter[k].relres = bb > 0 ? std::sqrt(b->h_sc[t * SC_COUNT + SC_RR] / bb) : 0.0;
+      }
+    }
+    for (int t = 0; t < nt; ++t) launch_mean_removal(ht[t].U, ht[t].N, ht[t].M, ht[t].ld, ht[t].st, s);
+  }
+  if (stats) {
+    weights_all();
+    rs = batch_read_back(b, ws, s);
+    if (rs != IRLSU_OK) return rs;
+  }
+  irlsu_status worst = IRLSU_OK;
+  for (int t = 0; t < nt; ++t) {
+    launch_copy_out<float>(ht[t].U, ht[t].ld, static_cast<float*>(tiles[t].U), tiles[t].ldu,
+                           ht[t].N, ht[t].M, s);
+    if (overall[t] == IRLSU_NOT_CONVERGED) worst = IRLSU_NOT_CONVERGED;
+    if (stats) {
+      stats[t].irls_done = prm.irls_iters;
+      stats[t].pcg_total = pcg_total[t];
+      stats[t].status = overall[t];
+      stats[t].L1_final = b->h_sc[t * SC_COUNT + SC_L1];
+      stats[t].H_final = b->h_sc[t * SC_COUNT + SC_H];
+      if (prm.irls_iters < IRLSU_MAX_IRLS) {
+        stats[t].iter[prm.irls_iters].L1 = stats[t].L1_final;
+        stats[t].iter[prm.irls_iters].H = stats[t].H_final;
+      }
+    }
+  }
+  if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+  if (stats) HIP_OK(hipStreamSynchronize(s));
+  return worst;
 }
 
 irlsu_status check_ws(const irlsu_plan* pl, const void* ws, size_t bytes) {
@@ -505,6 +858,30 @@ irlsu_status irlsu_unwrap(irlsu_plan* plan, const void* X, int64_t ldx, const vo
                             prm, static_cast<float*>(U), ldu, workspace, stats, s);
 }
 
+irlsu_status irlsu_adjoint(irlsu_plan* plan, const void* gU, int64_t ldg,
+                           const irlsu_params* params, void* gCv, int64_t ldgcv, void* gCh,
+                           int64_t ldgch, void* gX, int64_t ldgx, void* workspace,
+                           size_t workspace_bytes, irlsu_stats* stats, void* stream) {
+  if (!plan || !gU || !gCv || !gCh) return IRLSU_ERR_INVALID_ARG;
+  if (ldg < plan->M || ldgcv < plan->M || ldgch < plan->M - 1) return IRLSU_ERR_INVALID_ARG;
+  if (gX && ldgx < plan->M) return IRLSU_ERR_INVALID_ARG;
+  irlsu_status st = check_ws(plan, workspace, workspace_bytes);
+  if (st != IRLSU_OK) return st;
+  irlsu_params prm;
+  if (params) prm = *params;
+  else irlsu_params_default(&prm, plan->prec);
+  if (!(prm.eps > 0.0) || prm.pcg_max < 1 || prm.poll_every < 0 || prm.true_res_every < 0)
+    return IRLSU_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->elem == 8)
+    return adjoint_impl<double>(plan, static_cast<const double*>(gU), ldg, prm,
+                                static_cast<double*>(gCv), ldgcv, static_cast<double*>(gCh), ldgch,
+                                static_cast<double*>(gX), ldgx, workspace, stats, s);
+  return adjoint_impl<float>(plan, static_cast<const float*>(gU), ldg, prm,
+                             static_cast<float*>(gCv), ldgcv, static_cast<float*>(gCh), ldgch,
+                             static_cast<float*>(gX), ldgx, workspace, stats, s);
+}
+
 irlsu_status irlsu_setup(const irlsu_plan* plan, const void* X, int64_t ldx, const void* w,
                          const void* Cv, int64_t ldcv, const void* Ch, int64_t ldch, void* Gv,
                          void* Gh, void* CvI, void* ChI, int32_t* flags, void* stream) {
@@ -615,6 +992,145 @@ irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, doubl
   st = plan->elem == 8 ? go(double{}) : go(float{});
   if (st != IRLSU_OK) return st;
   return last_launch();
+}
+
+irlsu_status irlsu_batch_destroy(irlsu_batch* b) {
+  if (!b) return IRLSU_OK;
+  for (void* p : b->P) if (p) (void)hipFree(p);
+  for (void* p : b->Pt) if (p) (void)hipFree(p);
+  for (double* p : b->eig) if (p) (void)hipFree(p);
+  if (b->d_st_start) (void)hipFree(b->d_st_start);
+  if (b->d_g_start) (void)hipFree(b->d_g_start);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+  if (b->h_flags) (void)hipHostFree(b->h_flags);
+  if (b->h_sc) (void)hipHostFree(b->h_sc);
+  delete b;
+  return IRLSU_OK;
+}
+
+irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_t ntiles,
+                                irlsu_precision prec, void* stream) {
+  if (!out || !shapes || ntiles < 1) return IRLSU_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (prec != IRLSU_MIXED_BF16 && prec != IRLSU_MIXED_F16) return IRLSU_ERR_UNSUPPORTED;
+  for (int t = 0; t < ntiles; ++t)
+    if (shapes[2 * t] < 2 || shapes[2 * t + 1] < 2 || shapes[2 * t] > 65536 ||
+        shapes[2 * t + 1] > 65536)
+      return IRLSU_ERR_SHAPE;
+  irlsu_batch* b = new (std::nothrow) irlsu_batch;
+  if (!b) return IRLSU_ERR_OOM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  b->ntiles = ntiles;
+  b->prec = prec;
+  b->kind = prec == IRLSU_MIXED_F16 ? OK_F16 : OK_BF16;
+  std::vector<int32_t> st_start(ntiles + 1, 0), g_start(4 * (ntiles + 1), 0);
+  int32_t part = 0;
+  size_t off = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int64_t N = shapes[2 * t], M = shapes[2 * t + 1];
+    const int64_t Np = round_up(N, kBatchPad), Mp = round_up(M, kBatchPad);
+    b->N.push_back(N);
+    b->M.push_back(M);
+    b->Np.push_back(Np);
+    b->Mp.push_back(Mp);
+    int rows = 0;
+    const dim3 g = stencil_grid(Np, Mp, &rows);
+    b->st_gx.push_back((int32_t)g.x);
+    b->st_rows.push_back(rows);
+    b->st_nblk.push_back((int32_t)(g.x * g.y));
+    int gb[4];
+    precond_blocks(b->kind, Np, Mp, gb);
+    b->g4_nparts.push_back(gb[3]);
+    const int64_t bw = ((Mp + kThreads - 1) / kThreads);
+    int64_t wrows = 1;
+    while (bw * ((Np + wrows - 1) / wrows) > kMaxPartials / 2) wrows *= 2;
+    const int32_t wblocks = (int32_t)(bw * ((Np + wrows - 1) / wrows));
+    const int32_t need = std::max({(int32_t)(g.x * g.y), gb[3], wblocks,
+                                   (int32_t)elementwise_blocks(Np * Mp)});
+    b->part_off.push_back(part);
+    part += need;
+    st_start[t + 1] = st_start[t] + (int32_t)(g.x * g.y);
+    for (int q = 0; q < 4; ++q) g_start[q * (ntiles + 1) + t + 1] = g_start[q * (ntiles + 1) + t] + gb[q];
+    b->tile_off.push_back(off);
+    off += align_up(batch_tile_bytes(Np, Mp));
+    b->side_index.emplace(N, 0);
+    b->side_index.emplace(M, 0);
+  }
+  if (part > kMaxPartials) {
+    irlsu_batch_destroy(b);
+    return IRLSU_ERR_SHAPE;
+  }
+  b->st_total = st_start[ntiles];
+  for (int q = 0; q < 4; ++q) b->g_total[q] = g_start[q * (ntiles + 1) + ntiles];
+  b->part_off_bytes = off;
+  off = align_up(off + (size_t)kPartSlots * kMaxPartials * sizeof(double));
+  b->sc_off = off;
+  off = align_up(off + (size_t)ntiles * SC_COUNT * sizeof(double));
+  b->fl_off = off;
+  off = align_up(off + (size_t)ntiles * FL_COUNT * sizeof(int32_t));
+  b->ws_bytes = off;
+  bool ok = true;
+  int idx = 0;
+  for (auto& kv : b->side_index) {
+    kv.second = idx++;
+    const int64_t n = kv.first, npad = round_up(n, kBatchPad);
+    void *P = nullptr, *Pt = nullptr;
+    double* e = nullptr;
+    ok = ok && hipMalloc(&P, (size_t)npad * npad * 2) == hipSuccess;
+    ok = ok && hipMalloc(&Pt, (size_t)npad * npad * 2) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&e), npad * sizeof(double)) == hipSuccess;
+    b->P.push_back(P);
+    b->Pt.push_back(Pt);
+    b->eig.push_back(e);
+    if (ok) launch_basis(b->kind, n, npad, P, Pt, e, s);
+  }
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_st_start), st_start.size() * 4) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_g_start), g_start.size() * 4) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_tiles, (size_t)ntiles * sizeof(BatchTile<float>)) == hipSuccess;
+  ok = ok && hipHostMalloc(&b->h_tiles, (size_t)ntiles * sizeof(BatchTile<float>),
+                           hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_flags), (size_t)ntiles * FL_COUNT * 4,
+                           hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_sc), (size_t)ntiles * SC_COUNT * 8,
+                           hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    irlsu_batch_destroy(b);
+    return IRLSU_ERR_OOM;
+  }
+  if (hipMemcpy(b->d_st_start, st_start.data(), st_start.size() * 4, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->d_g_start, g_start.data(), g_start.size() * 4, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    irlsu_batch_destroy(b);
+    return IRLSU_ERR_HIP;
+  }
+  *out = b;
+  return IRLSU_OK;
+}
+
+size_t irlsu_batch_workspace_bytes(const irlsu_batch* b) { return b ? b->ws_bytes : 0; }
+
+irlsu_status irlsu_unwrap_batched(irlsu_batch* b, const irlsu_tile* tiles,
+                                  const irlsu_params* params, void* workspace,
+                                  size_t workspace_bytes, irlsu_stats* stats, void* stream) {
+  if (!b || !tiles) return IRLSU_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < b->ws_bytes) return IRLSU_ERR_WORKSPACE;
+  for (int t = 0; t < b->ntiles; ++t) {
+    const irlsu_tile& x = tiles[t];
+    if (!x.X || !x.U || x.ldx < b->M[t] || x.ldu < b->M[t]) return IRLSU_ERR_INVALID_ARG;
+    if ((x.Cv == nullptr) != (x.Ch == nullptr)) return IRLSU_ERR_INVALID_ARG;
+    if (x.Cv && (x.ldcv < b->M[t] || x.ldch < b->M[t] - 1)) return IRLSU_ERR_INVALID_ARG;
+  }
+  irlsu_params prm;
+  if (params) prm = *params;
+  else irlsu_params_default(&prm, b->prec);
+  if (!(prm.eps > 0.0) || !(prm.pcg_rtol >= 0.0) || prm.irls_iters < 0 || prm.pcg_max < 1 ||
+      prm.true_res_every < 0 || prm.poll_every < 0 || prm.irls_iters >= IRLSU_MAX_IRLS)
+    return IRLSU_ERR_INVALID_ARG;
+  return unwrap_batched_impl(b, tiles, prm, workspace, stats, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

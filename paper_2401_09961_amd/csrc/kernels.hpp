@@ -63,6 +63,39 @@ struct StencilArgs {
   DevState st;
 };
 
+// ---- batched tiles ------------------------------------------------------
+// Device-resident description of one tile of a batch: its sizes, its
+// vectors in the internal layout, its scalars and partial range, its grids
+// and its preconditioner (basis tables of its side lengths).
+template <class T>
+struct BatchTile {
+  int64_t N, M, Np, ld;
+  double* U;
+  T* r; T* z; T* p0; T* p1; T* q; T* b; T* Ov; T* Oh;
+  DevState st;
+  int32_t st_gx, st_rows, st_nblk;   // stencil grid: column blocks, rows per band, blocks
+  int32_t g4_nparts;                 // partials of the last preconditioner product
+  int32_t flexible_q;                // pass q to the preconditioner epilogue
+  int32_t pad_;
+  void* T1; void* T2; void* T3;
+  const void* PN; const void* PNt; const void* PM; const void* PMt;
+  const double* eigN; const double* eigM;
+};
+
+// Index t with start[t] <= b < start[t + 1] (start has ntiles + 1 entries).
+__device__ __forceinline__ int find_tile(const int32_t* start, int ntiles, int b) {
+  int lo = 0, hi = ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T>
+struct StencilArgs;
+
 template <class T> void launch_setup(const SetupArgs<T>& a, hipStream_t s);
 template <class T> int launch_weights(const WeightsArgs<T>& a, hipStream_t s);
 void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s);
@@ -76,8 +109,58 @@ void launch_reduce_to(DevState st, int slot, int nparts, double* out, hipStream_
 int elementwise_blocks(int64_t n);
 
 template <class T> int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s);
+
+template <class T>
+__device__ __forceinline__ StencilArgs<T> batch_stencil_args(const BatchTile<T>& bt, int mode,
+                                                            int iter, int flexible, int check_done) {
+  StencilArgs<T> a;
+  a.Ov = bt.Ov;
+  a.Oh = bt.Oh;
+  a.z = bt.z;
+  a.p_in = (iter & 1) ? bt.p0 : bt.p1;
+  a.p_out = (iter & 1) ? bt.p1 : bt.p0;
+  a.q = bt.q;
+  a.u = bt.U;
+  a.b = bt.b;
+  a.r = bt.r;
+  a.N = bt.N;
+  a.M = bt.M;
+  a.Np = bt.Np;
+  a.ld = bt.ld;
+  a.iter = iter;
+  a.flexible = flexible;
+  a.nparts_prec = bt.g4_nparts;
+  a.nparts_res = bt.st_nblk;
+  a.check_done = check_done;
+  a.st = bt.st;
+  (void)mode;
+  return a;
+}
+template <class T>
+void launch_stencil_batched(int mode, const BatchTile<T>* tiles, const int32_t* start, int ntiles,
+                            int total_blocks, int iter, int flexible, int check_done,
+                            hipStream_t s);
+template <class T>
+void launch_axpy_batched(const BatchTile<T>* tiles, const int32_t* start, int ntiles,
+                         int total_blocks, int iter, hipStream_t s);
 // Grid of the stencil (and of the axpy, which must write as many partials).
 dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out);
+
+// ---- adjoint (frozen-weight) -------------------------------------------
+template <class T>
+struct AdjEdgeArgs {
+  const double* U; const double* lam;
+  const T* Gv; const T* Gh; const T* Cv; const T* Ch;   // internal layout
+  double eps;
+  int64_t N, M, ld;
+  T* gCv; int64_t ldgcv;    // (N-1) x M, caller layout
+  T* gCh; int64_t ldgch;    // N x (M-1)
+  T* gX; int64_t ldgx;      // N x M, nullable
+};
+template <class T>
+void launch_adjoint_rhs(const T* g, int64_t ldg, int64_t N, int64_t M, int64_t Np, int64_t ld,
+                        T* b, DevState st, double tol2, hipStream_t s);
+template <class T> void launch_adjoint_edges(const AdjEdgeArgs<T>& a, hipStream_t s);
 
 // ---- DCT preconditioner (dense cosine-basis products on MFMA) ----------
 enum OperandKind : int { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2, OK_F16 = 3 };
@@ -99,6 +182,15 @@ struct PrecondArgs {
 };
 // Returns the number of partials written by the last product (z.r etc.).
 int launch_precond(const PrecondArgs& a, hipStream_t s);
+// Number of partials the preconditioner's last product writes for a problem.
+int precond_nparts(int kind, int64_t Np, int64_t Mp);
+// Grouped preconditioner over the tiles of a batch (operand kind of the
+// batch); starts[g] are the per-tile block prefixes of product g (4 x
+// (ntiles + 1) entries, device), totals[g] the grid sizes.
+void launch_precond_batched(int kind, const void* tiles, const int32_t* starts, int ntiles,
+                            const int* totals, int check_conv, hipStream_t s);
+// Per-tile block counts of the four products (host side, for the prefixes).
+void precond_blocks(int kind, int64_t Np, int64_t Mp, int out[4]);
 void launch_basis(int kind, int64_t n, int64_t npad, void* P, void* Pt, void* eig_inv,
                   hipStream_t s);
 

@@ -134,16 +134,16 @@ __global__ __launch_bounds__(kThreads) void weights_kernel(WeightsArgs<T> a, int
     }
   }
   const int slots[3] = {PR_L1, PR_H, PR_BB};
-  write_partials<3>(a.st.part, slots, acc);
+  write_partials<3>(a.st, slots, acc, linear_block());
 }
 
 // Finalise the weight step: objectives and ||b||^2 into scalars (and an
 // optional user array), reset the PCG flags for the next solve.
 __global__ __launch_bounds__(kThreads) void finalize_weights_kernel(
     DevState st, int nparts, double* out, double tol2) {
-  const double l1 = reduce_slot(st.part, PR_L1, nparts);
-  const double h = reduce_slot(st.part, PR_H, nparts);
-  const double bb = reduce_slot(st.part, PR_BB, nparts);
+  const double l1 = reduce_slot(st, PR_L1, nparts);
+  const double h = reduce_slot(st, PR_H, nparts);
+  const double bb = reduce_slot(st, PR_BB, nparts);
   if (threadIdx.x == 0) {
     st.sc[SC_L1] = l1;
     st.sc[SC_H] = h;
@@ -164,20 +164,22 @@ __global__ __launch_bounds__(kThreads) void finalize_weights_kernel(
 // partial ||r||^2 and sum r.  The prologue reduces the stencil's p.q partials
 // (identically in every block) and stops on breakdown.
 // ----------------------------------------------------------------------------
+// Body shared by the single-image and the grouped (batched) launch: block lb
+// of nb blocks working on one problem.
 template <class T>
-__global__ __launch_bounds__(kThreads) void axpy_kernel(AxpyArgs<T> a) {
+__device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) {
   if (a.st.fl[FL_DONE]) return;
-  const double pq = reduce_slot(a.st.part, PR_PQ, a.nparts_pq);
+  const double pq = reduce_slot(a.st, PR_PQ, a.nparts_pq);
   const double rho = a.st.sc[SC_RHO + (a.iter & 1)];
   if (!(pq > 0.0) || !(rho >= 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
       a.st.fl[FL_STATUS] |= 1;
       a.st.fl[FL_DONE] = 1;
     }
     return;
   }
   const double alpha = rho / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (lb == 0 && threadIdx.x == 0) {
     a.st.sc[SC_ALPHA + (a.iter & 1)] = alpha;
     a.st.sc[SC_PQ] = pq;
     a.st.fl[FL_ITERS] = a.iter + 1;
@@ -185,8 +187,7 @@ __global__ __launch_bounds__(kThreads) void axpy_kernel(AxpyArgs<T> a) {
   const T al = (T)alpha;
   double acc[2] = {0.0, 0.0};
   const int64_t n4 = a.n / 4;
-  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n4;
-       k += (int64_t)gridDim.x * kThreads) {
+  for (int64_t k = (int64_t)lb * kThreads + threadIdx.x; k < n4; k += (int64_t)nb * kThreads) {
     const int64_t o = k * 4;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -200,7 +201,32 @@ __global__ __launch_bounds__(kThreads) void axpy_kernel(AxpyArgs<T> a) {
     }
   }
   const int slots[2] = {PR_RR, PR_RSUM};
-  write_partials<2>(a.st.part, slots, acc);
+  write_partials<2>(a.st, slots, acc, lb);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void axpy_kernel(AxpyArgs<T> a) {
+  axpy_body<T>(a, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Grouped launch over a batch: each tile gets as many blocks as its stencil
+// grid (so both producers of ||r||^2 write the same partial count).
+template <class T>
+__global__ __launch_bounds__(kThreads) void axpy_batched_kernel(const BatchTile<T>* tiles,
+                                                                const int32_t* start, int ntiles,
+                                                                int iter) {
+  const int t = find_tile(start, ntiles, (int)blockIdx.x);
+  const BatchTile<T>& bt = tiles[t];
+  AxpyArgs<T> a;
+  a.u = bt.U;
+  a.r = bt.r;
+  a.p = (iter & 1) ? bt.p1 : bt.p0;
+  a.q = bt.q;
+  a.n = bt.Np * bt.ld;
+  a.nparts_pq = bt.st_nblk;
+  a.iter = iter;
+  a.st = bt.st;
+  axpy_body<T>(a, (int)blockIdx.x - start[t], bt.st_nblk);
 }
 
 // ----------------------------------------------------------------------------
@@ -217,13 +243,13 @@ __global__ __launch_bounds__(kThreads) void sum_kernel(const double* u, int64_t 
     if (j < M) acc[0] += (double)u[k];
   }
   const int slots[1] = {PR_AUX};
-  write_partials<1>(st.part, slots, acc);
+  write_partials<1>(st, slots, acc, linear_block());
 }
 
 __global__ __launch_bounds__(kThreads) void sub_mean_kernel(double* u, int64_t N, int64_t M,
                                                            int64_t ld, DevState st,
                                                            int nparts) {
-  const double s = reduce_slot(st.part, PR_AUX, nparts);
+  const double s = reduce_slot(st, PR_AUX, nparts);
   const double mean = s / ((double)N * (double)M);
   if (blockIdx.x == 0 && threadIdx.x == 0) st.sc[SC_MEAN] = mean;
   const int64_t n = N * ld;
@@ -245,14 +271,14 @@ __global__ __launch_bounds__(kThreads) void copy_out_kernel(const double* u, int
 
 // Reduce the residual partials after a solve: ||r||^2 into SC_RR.
 __global__ __launch_bounds__(kThreads) void finalize_rr_kernel(DevState st, int nparts) {
-  const double rr = reduce_slot(st.part, PR_RR, nparts);
+  const double rr = reduce_slot(st, PR_RR, nparts);
   if (threadIdx.x == 0) st.sc[SC_RR] = rr;
 }
 
 // Reduce one partial slot into a device double (step-level entry points).
 __global__ __launch_bounds__(kThreads) void reduce_to_kernel(DevState st, int slot, int nparts,
                                                             double* out) {
-  const double v = reduce_slot(st.part, slot, nparts);
+  const double v = reduce_slot(st, slot, nparts);
   if (threadIdx.x == 0) *out = v;
 }
 
@@ -318,6 +344,15 @@ template void launch_setup<double>(const SetupArgs<double>&, hipStream_t);
 template int launch_weights<float>(const WeightsArgs<float>&, hipStream_t);
 template int launch_weights<double>(const WeightsArgs<double>&, hipStream_t);
 template int launch_axpy<float>(const AxpyArgs<float>&, hipStream_t, int);
+
+template <class T>
+void launch_axpy_batched(const BatchTile<T>* tiles, const int32_t* start, int ntiles,
+                         int total_blocks, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_batched_kernel<T>, dim3(total_blocks), dim3(kThreads), 0, s, tiles, start,
+                     ntiles, iter);
+}
+template void launch_axpy_batched<float>(const BatchTile<float>*, const int32_t*, int, int, int,
+                                         hipStream_t);
 template int launch_axpy<double>(const AxpyArgs<double>&, hipStream_t, int);
 template void launch_copy_out<float>(const double*, int64_t, float*, int64_t, int64_t, int64_t, hipStream_t);
 template void launch_copy_out<double>(const double*, int64_t, double*, int64_t, int64_t, int64_t, hipStream_t);

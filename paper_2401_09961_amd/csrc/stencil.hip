@@ -103,18 +103,21 @@ struct StencilIO {
   }
 };
 
+// Body shared by the single-image and the grouped (batched) launch: column
+// block bx, row band by, block lb of its problem.
 template <class T, int MODE>
-__global__ __launch_bounds__(kThreads) void stencil_kernel(StencilArgs<T> a, int rows_per_block) {
+__device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, int by,
+                                             int rows_per_block, int lb) {
   using IO = StencilIO<T, MODE>;
   using CT = typename IO::CT;
   if (a.check_done && a.st.fl[FL_DONE]) return;
 
   CT beta = 0, zc = 0;
   if constexpr (MODE == ST_FUSED) {
-    const double zr = reduce_slot(a.st.part, PR_ZR, a.nparts_prec);
-    const double zs = reduce_slot(a.st.part, PR_ZS, a.nparts_prec);
-    const double zq = reduce_slot(a.st.part, PR_ZQ, a.nparts_prec);
-    const double rsum = reduce_slot(a.st.part, PR_RSUM, a.nparts_res);
+    const double zr = reduce_slot(a.st, PR_ZR, a.nparts_prec);
+    const double zs = reduce_slot(a.st, PR_ZS, a.nparts_prec);
+    const double zq = reduce_slot(a.st, PR_ZQ, a.nparts_prec);
+    const double rsum = reduce_slot(a.st, PR_RSUM, a.nparts_res);
     const double zcd = zs / ((double)a.N * (double)a.M);
     const double rho = zr - zcd * rsum;
     double b = 0.0;
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(StencilArgs<T> a, int
         b = rho / rho_old;
       }
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
       a.st.sc[SC_RHO + (a.iter & 1)] = rho;
       a.st.sc[SC_BETA] = b;
       a.st.sc[SC_ZSUM] = zs;
@@ -142,10 +145,10 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(StencilArgs<T> a, int
   __shared__ CT s_ohl[2][kThreads + 2];
 
   const int t = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * (kThreads * 4);
+  const int64_t c0 = (int64_t)bx * (kThreads * 4);
   const int64_t j0 = c0 + 4 * t;
   const bool active = j0 < a.ld;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_block;
+  const int64_t r0 = (int64_t)by * rows_per_block;
   int64_t r1 = r0 + rows_per_block;
   if (r1 > a.Np) r1 = a.Np;
   const int64_t ld = a.ld;
@@ -235,12 +238,32 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(StencilArgs<T> a, int
   if constexpr (MODE == ST_RESID) {
     double v[2] = {acc0, acc1};
     const int slots[2] = {PR_RR, PR_RSUM};
-    write_partials<2>(a.st.part, slots, v);
+    write_partials<2>(a.st, slots, v, lb);
   } else {
     double v[1] = {acc0};
     const int slots[1] = {PR_PQ};
-    write_partials<1>(a.st.part, slots, v);
+    write_partials<1>(a.st, slots, v, lb);
   }
+}
+
+template <class T, int MODE>
+__global__ __launch_bounds__(kThreads) void stencil_kernel(StencilArgs<T> a, int rows_per_block) {
+  stencil_body<T, MODE>(a, (int)blockIdx.x, (int)blockIdx.y, rows_per_block,
+                        (int)(blockIdx.x + gridDim.x * blockIdx.y));
+}
+
+// Grouped launch over the tiles of a batch: block -> tile by binary search
+// over the per-tile block prefix, then the tile's own arguments.
+template <class T, int MODE>
+__global__ __launch_bounds__(kThreads) void stencil_batched_kernel(const BatchTile<T>* tiles,
+                                                                   const int32_t* start, int ntiles,
+                                                                   int iter, int flexible,
+                                                                   int check_done) {
+  const int t = find_tile(start, ntiles, (int)blockIdx.x);
+  const BatchTile<T>& bt = tiles[t];
+  const int lb = (int)blockIdx.x - start[t];
+  StencilArgs<T> a = batch_stencil_args<T>(bt, MODE, iter, flexible, check_done);
+  stencil_body<T, MODE>(a, lb % bt.st_gx, lb / bt.st_gx, bt.st_rows, lb);
 }
 
 // Enough blocks to fill 256 CUs several times over, within the partials table.
@@ -273,5 +296,25 @@ int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s) {
 
 template int launch_stencil<float>(int, const StencilArgs<float>&, hipStream_t);
 template int launch_stencil<double>(int, const StencilArgs<double>&, hipStream_t);
+
+template <class T>
+void launch_stencil_batched(int mode, const BatchTile<T>* tiles, const int32_t* start, int ntiles,
+                            int total_blocks, int iter, int flexible, int check_done,
+                            hipStream_t s) {
+  const dim3 grid((unsigned)total_blocks);
+  switch (mode) {
+    case ST_FUSED:
+      hipLaunchKernelGGL((stencil_batched_kernel<T, ST_FUSED>), grid, dim3(kThreads), 0, s, tiles,
+                         start, ntiles, iter, flexible, check_done);
+      break;
+    default:
+      hipLaunchKernelGGL((stencil_batched_kernel<T, ST_RESID>), grid, dim3(kThreads), 0, s, tiles,
+                         start, ntiles, iter, flexible, check_done);
+      break;
+  }
+}
+
+template void launch_stencil_batched<float>(int, const BatchTile<float>*, const int32_t*, int, int,
+                                            int, int, int, hipStream_t);
 
 }  // namespace irlsu

@@ -1,0 +1,117 @@
+"""Adjoint (frozen weights) of the GPU path against the oracle's adjoint at
+the same converged U, and against FP64 finite differences of the frozen map.
+
+Bars: FP64 plan 1e-8 relative (norm-wise; the adjoint PCG solve runs to
+1e-12), FP32 plan 2e-3 (FP32 vectors, solve to 1e-6).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2401_09961_amd as pkg
+from oracle import reduced as R
+
+pytestmark = pytest.mark.gpu
+
+
+def residue_field(seed, N, M):
+    rng = np.random.default_rng(seed)
+    phi = synth.gaussian_sum_field(rng, N, M, amp=3.0, noise=1.2)
+    return phi, synth.observe(phi)
+
+
+def forward(prec, X, Cv, Ch, eps=1e-3):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    N, M = X.shape
+    plan = pkg.Plan(N, M, prec)
+    p = pkg.default_params(prec)
+    p.irls_iters, p.pcg_max, p.eps = 30, 3000, eps
+    p.pcg_rtol = 1e-12 if prec == "f64" else 1e-6
+    U = plan.unwrap(torch.from_numpy(X).to("cuda", dt), Cv=torch.from_numpy(Cv).to("cuda", dt),
+                    Ch=torch.from_numpy(Ch).to("cuda", dt), params=p)
+    torch.cuda.synchronize()
+    return plan, p, U
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-8), ("f32", 2e-3)])
+@pytest.mark.parametrize("shape", [(40, 33), (130, 140)])
+def test_adjoint_matches_oracle(prec, tol, shape):
+    N, M = shape
+    phi, X = residue_field(1, N, M)
+    w5 = synth.field_c5(2, N, M)
+    dt = np.float64 if prec == "f64" else np.float32
+    X, Cv, Ch = X.astype(dt), w5.Cv.astype(dt), w5.Ch.astype(dt)
+    plan, p, U = forward(prec, X, Cv, Ch)
+    rng = np.random.default_rng(3)
+    gU = rng.standard_normal((N, M)).astype(dt)
+    gCv, gCh, gX, st = plan.adjoint(torch.from_numpy(gU).cuda(), params=p, stats=True)
+    torch.cuda.synchronize()
+    Ug = U.cpu().numpy().astype(np.float64)
+    Gv, Gh = R.wrapped_gradients(X.astype(np.float64))
+    ref = R.adjoint(Ug, Gv, Gh, Cv.astype(np.float64), Ch.astype(np.float64), p.eps,
+                    gU.astype(np.float64), tol=1e-13, maxit=20000)
+    e = [rel(gCv.cpu().numpy().astype(np.float64), ref["gCv"]),
+         rel(gCh.cpu().numpy().astype(np.float64), ref["gCh"]),
+         rel(gX.cpu().numpy().astype(np.float64), ref["gX"])]
+    print(f"adjoint {prec} {shape}: rel err gCv {e[0]:.2e} gCh {e[1]:.2e} gX {e[2]:.2e} "
+          f"pcg {st['pcg_total']}")
+    assert max(e) <= tol
+    plan.close()
+
+
+def test_adjoint_matches_fp64_finite_differences():
+    """FD of the frozen map (oracle's dense-free PCG to 1e-14) at the GPU's U."""
+    N, M = 24, 21
+    phi, X = residue_field(4, N, M)
+    w5 = synth.field_c5(5, N, M)
+    plan, p, U = forward("f64", X, w5.Cv, w5.Ch)
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal((N, M))
+    gCv, gCh, gX = plan.adjoint(torch.from_numpy(a).cuda(), params=p)
+    Ug = U.cpu().numpy()
+    Gv, Gh = R.wrapped_gradients(X)
+    wv, wh = R.frozen_weights(Ug, Gv, Gh, p.eps)
+    loss = lambda Uc: float(np.sum(a * Uc))  # noqa: E731
+    h = 1e-3
+    for _ in range(6):
+        i, j = rng.integers(0, N - 1), rng.integers(0, M)
+        Cp, Cm = w5.Cv.copy(), w5.Cv.copy()
+        Cp[i, j] += h
+        Cm[i, j] -= h
+        fd = (loss(R.frozen_solve(Cp, w5.Ch, Gv, Gh, wv, wh))
+              - loss(R.frozen_solve(Cm, w5.Ch, Gv, Gh, wv, wh))) / (2 * h)
+        g = gCv.cpu().numpy()[i, j]
+        assert abs(fd - g) <= 1e-4 * abs(fd) + 1e-9, (i, j, fd, g)
+    plan.close()
+
+
+def test_autograd_function_mse_loss():
+    """Config-5 style loss through torch.autograd (small grid), against the
+    oracle adjoint of the same loss at the GPU's U."""
+    N, M = 64, 48
+    phi, X = residue_field(7, N, M)
+    w5 = synth.field_c5(8, N, M)
+    plan = pkg.Plan(N, M, "f64")
+    p = pkg.default_params("f64")
+    p.irls_iters, p.pcg_max, p.pcg_rtol = 30, 3000, 1e-12
+    logits_v = torch.from_numpy(w5.meta["zv"]).cuda().requires_grad_(True)
+    logits_h = torch.from_numpy(w5.meta["zh"]).cuda().requires_grad_(True)
+    Xt = torch.from_numpy(X).cuda().requires_grad_(True)
+    Cv, Ch = torch.sigmoid(logits_v), torch.sigmoid(logits_h)
+    U = pkg.UnwrapFn.apply(Xt, Cv, Ch, plan, p)
+    target = torch.from_numpy(phi - phi.mean()).cuda()
+    loss = ((U - U.mean() - target) ** 2).mean()
+    loss.backward()
+    Ug = U.detach().cpu().numpy()
+    gU = 2.0 * (Ug - Ug.mean() - (phi - phi.mean())) / (N * M)
+    Gv, Gh = R.wrapped_gradients(X)
+    ref = R.adjoint(Ug, Gv, Gh, w5.Cv, w5.Ch, p.eps, gU, tol=1e-13, maxit=20000)
+    sv = w5.Cv * (1 - w5.Cv)
+    assert rel(logits_v.grad.cpu().numpy(), ref["gCv"] * sv) <= 1e-7
+    assert rel(Xt.grad.cpu().numpy(), ref["gX"]) <= 1e-7
+    plan.close()

@@ -21,6 +21,8 @@ from oracle import reduced as R
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(96, 80), (131, 257), (256, 256)]
+# sizes whose padded dimensions are multiples of 256 select the 256 x 256 tile
+BIG_SHAPES = [(512, 768), (1000, 515)]
 UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24}
 PRECOND_RTOL = {"f64": 1e-11, "f32": 2e-5, "bf16": 3e-2}
 
@@ -162,6 +164,24 @@ def test_precond_matches_dct_oracle(prec, shape):
     assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
     ref = float(np.sum(r.astype(np.float64) * z_o))
     assert abs(rz.item() - ref) <= 2 * PRECOND_RTOL[prec] * abs(ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", BIG_SHAPES)
+@pytest.mark.parametrize("p16", ["bf16", "f16"])
+def test_precond_big_tiles(p16, shape):
+    N, M = shape
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal((N, M)).astype(np.float32)
+    plan = pkg.Plan(N, M, p16)
+    z, rz = plan.precond(internal(plan, r))
+    torch.cuda.synchronize()
+    z_o = R.apply_precond(r.astype(np.float64))
+    zg = z.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
+    print(f"precond {p16} {shape}: rel err {rel:.3e}")
+    assert rel <= PRECOND_RTOL["bf16"]
+    assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
     plan.close()
 
 
