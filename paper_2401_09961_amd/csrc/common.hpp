@@ -25,6 +25,7 @@ enum Scalar : int {
   SC_MEAN = 10,
   SC_TOL2 = 11,    // pcg_rtol^2
   SC_ZSUM = 12,
+  SC_SCALE = 13,   // FP16 preconditioner input scale
   SC_COUNT = 32
 };
 
@@ -66,11 +67,11 @@ constexpr int PR_AUX = 6;
 // scalars and flags, and its range [off, off + blocks) of every row of the
 // shared partial-sum table.
 struct DevState {
-  double* sc;       // SC_COUNT doubles
-  int32_t* fl;      // FL_COUNT ints
-  double* part;     // kPartSlots * kMaxPartials doubles (shared by all problems)
-  int32_t off;      // first partial index of this problem
-  int32_t pad_;
+  double* sc = nullptr;    // SC_COUNT doubles
+  int32_t* fl = nullptr;   // FL_COUNT ints
+  double* part = nullptr;  // kPartSlots * kMaxPartials doubles (shared by all problems)
+  int32_t off = 0;         // first partial index of this problem
+  int32_t pad_ = 0;
 };
 
 __device__ __forceinline__ double wave_sum(double x) {

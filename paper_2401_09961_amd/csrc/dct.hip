@@ -99,6 +99,8 @@ struct GemmCtl {
   int check_done;   // return when the PCG done flag is set
   int check_conv;   // G1: reduce ||r||^2 partials and stop on convergence
   int nparts_rr;
+  int scale_in;     // G1 (FP16 operands): scale r by s = 1e-3 sqrt(N M / ||r||^2)
+  int64_t npix;     // N M of the problem (for the scale)
 };
 
 // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
@@ -143,13 +145,23 @@ __device__ __forceinline__ void gemm_body(const AT* __restrict__ A, int64_t lda,
   static_assert(B_CHUNKS * CH * NT == BN * BK, "B tile staging");
 
   if (ctl.check_done && ctl.st.fl[FL_DONE]) return;
-  if (ctl.check_conv) {
+  if (ctl.check_conv || ctl.scale_in) {
     const double rr = reduce_slot<NT>(ctl.st, PR_RR, ctl.nparts_rr);
-    const double thr = ctl.st.sc[SC_TOL2] * ctl.st.sc[SC_BB];
-    if (bid == 0 && threadIdx.x == 0) ctl.st.sc[SC_RR] = rr;
-    if (rr <= thr) {
-      if (bid == 0 && threadIdx.x == 0) ctl.st.fl[FL_DONE] = 1;
-      return;
+    if (ctl.check_conv) {
+      const double thr = ctl.st.sc[SC_TOL2] * ctl.st.sc[SC_BB];
+      if (bid == 0 && threadIdx.x == 0) ctl.st.sc[SC_RR] = rr;
+      if (rr <= thr) {
+        if (bid == 0 && threadIdx.x == 0) ctl.st.fl[FL_DONE] = 1;
+        return;
+      }
+    }
+    if (ctl.scale_in) {
+      // FP16 range: unit-RMS input times 1e-3 keeps the spectral division's
+      // amplification (up to 1 / lambda_min) below the FP16 maximum and the
+      // high modes above its smallest normal number.
+      const double sc = rr > 0.0 ? 1e-3 * sqrt((double)ctl.npix / rr) : 1.0;
+      ascale = (float)sc;
+      if (bid == 0 && threadIdx.x == 0) ctl.st.sc[SC_SCALE] = (double)ascale;
     }
   }
 
@@ -334,15 +346,17 @@ struct EpiFinal {
   const T* q;  // nullable
   int64_t ldc;
   double zscale;
+  const double* dscale;  // nullable: divide by the device-side input scale
   struct Acc {
     double zr = 0.0, zq = 0.0, zs = 0.0;
   };
   template <int RS, class V>
   __device__ __forceinline__ void apply(int64_t m, int64_t n, const V (&v)[4], Acc& acc) const {
+    const double zs = dscale ? zscale / *dscale : zscale;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t o = (m + t * RS) * ldc + n;
-      const T zt = (T)((double)v[t] * zscale);
+      const T zt = (T)((double)v[t] * zs);
       z[o] = zt;
       const double zd = (double)zt;
       acc.zr += zd * (double)r[o];
@@ -403,8 +417,9 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
   OT* T2 = static_cast<OT*>(a.T2);
   OT* T3 = static_cast<OT*>(a.T3);
   const T* r = static_cast<const T*>(a.r);
-  GemmCtl c1{a.st, 1, a.check_conv, a.nparts_rr};
-  GemmCtl cn{a.st, 1, 0, 0};
+  const int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
+  GemmCtl c1{a.st, 1, a.check_conv, a.nparts_rr, f16, a.N * a.M};
+  GemmCtl cn{a.st, 1, 0, 0, 0, 0};
   // G1: T1^T = (r P_M)^T
   gemm<OT, T>(r, Mp, PMt, Mp, Np, Mp, Mp, (float)a.scale, EpiStoreT<OT>{T1, Np}, c1, s);
   // G2: T2^T = (P_N^T T1)^T ./ lambda
@@ -419,7 +434,7 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
   // tile's registers)
   return gemm<OT, OT, EpiFinal<T>, false>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
                       EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
-                                  1.0 / a.scale},
+                                  1.0 / a.scale, f16 ? a.st.sc + SC_SCALE : nullptr},
                       cn, s);
 }
 
@@ -454,7 +469,8 @@ __global__ __launch_bounds__(batch_threads<G>()) void gemm_batched_kernel(
   const BatchTile<T>& bt = tiles[t];
   const int bid = (int)blockIdx.x - start[t];
   const int64_t Np = bt.Np, Mp = bt.ld;
-  GemmCtl ctl{bt.st, 1, G == 1 ? check_conv : 0, bt.st_nblk};
+  constexpr int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
+  GemmCtl ctl{bt.st, 1, G == 1 ? check_conv : 0, bt.st_nblk, G == 1 ? f16 : 0, bt.N * bt.M};
   if constexpr (G == 1) {
     gemm_body<OT, T, C>(bt.r, Mp, static_cast<const OT*>(bt.PMt), Mp, Mp, (int)(Np / C::BM),
                         (int)(Mp / C::BN), 4, bid, 1.0f,
@@ -470,7 +486,9 @@ __global__ __launch_bounds__(batch_threads<G>()) void gemm_batched_kernel(
   } else {
     gemm_body<OT, OT, C>(static_cast<const OT*>(bt.T3), Mp, static_cast<const OT*>(bt.PM), Mp, Mp,
                          (int)(Np / C::BM), (int)(Mp / C::BN), 8, bid, 1.0f,
-                         EpiFinal<T>{bt.z, bt.r, bt.flexible_q ? bt.q : nullptr, Mp, 1.0}, ctl);
+                         EpiFinal<T>{bt.z, bt.r, bt.flexible_q ? bt.q : nullptr, Mp, 1.0,
+                                     f16 ? bt.st.sc + SC_SCALE : nullptr},
+                         ctl);
   }
 }
 

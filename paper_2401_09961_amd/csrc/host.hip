@@ -127,6 +127,8 @@ Ws<T> carve(const irlsu_plan* p, void* base) {
   w.st.part = reinterpret_cast<double*>(b + L.part);
   w.st.sc = reinterpret_cast<double*>(b + L.sc);
   w.st.fl = reinterpret_cast<int32_t*>(b + L.fl);
+  w.st.off = 0;
+  w.st.pad_ = 0;
   return w;
 }
 
@@ -983,8 +985,13 @@ irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, doubl
     using T = decltype(tag);
     const Ws<T> W = carve<T>(plan, workspace);
     HIP_OK(hipMemsetAsync(W.st.fl, 0, FL_COUNT * sizeof(int32_t), s));
+    int nrr = 0;
+    if constexpr (sizeof(T) == 4) {
+      if (plan->kind == OK_F16)
+        nrr = launch_sumsq<float>(static_cast<const float*>(r), plan->Np * plan->Mp, W.st, s);
+    }
     PrecondArgs a = precond_args<T>(plan, W, static_cast<const T*>(r), static_cast<T*>(z), nullptr,
-                                    0, 0);
+                                    0, nrr);
     const int n = launch_precond(a, s);
     if (rz) launch_reduce_to(W.st, PR_ZR, n, rz, s);
     return IRLSU_OK;

@@ -275,6 +275,26 @@ __global__ __launch_bounds__(kThreads) void finalize_rr_kernel(DevState st, int 
   if (threadIdx.x == 0) st.sc[SC_RR] = rr;
 }
 
+// Partial sums of squares of an array into the ||r||^2 slot (the step-level
+// preconditioner of FP16 plans derives its input scale from them).
+template <class T>
+__global__ __launch_bounds__(kThreads) void sumsq_kernel(const T* x, int64_t n, DevState st) {
+  double acc[1] = {0.0};
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads)
+    acc[0] += (double)x[k] * (double)x[k];
+  const int slots[1] = {PR_RR};
+  write_partials<1>(st, slots, acc, linear_block());
+}
+
+template <class T>
+int launch_sumsq(const T* x, int64_t n, DevState st, hipStream_t s) {
+  const int nb = elementwise_blocks(n);
+  hipLaunchKernelGGL(sumsq_kernel<T>, dim3(nb), dim3(kThreads), 0, s, x, n, st);
+  return nb;
+}
+template int launch_sumsq<float>(const float*, int64_t, DevState, hipStream_t);
+
 // Reduce one partial slot into a device double (step-level entry points).
 __global__ __launch_bounds__(kThreads) void reduce_to_kernel(DevState st, int slot, int nparts,
                                                             double* out) {
