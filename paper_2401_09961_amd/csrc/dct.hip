@@ -338,6 +338,52 @@ struct EpiScale {
   __device__ __forceinline__ void finish(Acc&, const DevState&, int) const {}
 };
 
+// Final product, direct store: z = v * zscale (divided by the device-side
+// input scale when given); the dot products follow in zdots_kernel.
+template <class T>
+struct EpiStoreZ {
+  T* z;
+  int64_t ldc;
+  double zscale;
+  const double* dscale;
+  using Acc = NoAcc;
+  template <int RS, class V>
+  __device__ __forceinline__ void apply(int64_t m, int64_t n, const V (&v)[4], Acc&) const {
+    const double zs = dscale ? zscale / *dscale : zscale;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) z[(m + t * RS) * ldc + n] = (T)((double)v[t] * zs);
+  }
+  template <int NT>
+  __device__ __forceinline__ void finish(Acc&, const DevState&, int) const {}
+};
+
+// z.r, z.q and sum z in one pass (FP64 partials), after the last product.
+template <class T>
+__device__ __forceinline__ void zdots_body(const T* z, const T* r, const T* q, int64_t n,
+                                           const DevState& st, int lb, int nb) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int64_t n4 = n / 4;
+  for (int64_t k = (int64_t)lb * kThreads + threadIdx.x; k < n4; k += (int64_t)nb * kThreads) {
+    const int64_t o = 4 * k;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double zd = (double)z[o + e];
+      acc[0] += zd * (double)r[o + e];
+      if (q) acc[1] += zd * (double)q[o + e];
+      acc[2] += zd;
+    }
+  }
+  const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
+  write_partials<3>(st, slots, acc, lb);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void zdots_kernel(const T* z, const T* r, const T* q,
+                                                         int64_t n, DevState st, int check_done) {
+  if (check_done && st.fl[FL_DONE]) return;
+  zdots_body<T>(z, r, q, n, st, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // Final product: z (vector type T), partial sums of z.r, z.q, sum z.
 template <class T>
 struct EpiFinal {
@@ -429,13 +475,24 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
                cn, s);
   // G3: T3 = (T2^T P_N^T)^T = P_N T2
   gemm<OT, OT>(T2, Np, PN, Np, Mp, Np, Np, 1.0f, EpiStoreT<OT>{T3, Mp}, cn, s);
-  // G4: z = T3 P_M^T (the 128 x 128 tile: its epilogue reads r and q and
-  // accumulates three FP64 sums, which does not fit beside the 256 x 256
-  // tile's registers)
-  return gemm<OT, OT, EpiFinal<T>, false>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
-                      EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
-                                  1.0 / a.scale, f16 ? a.st.sc + SC_SCALE : nullptr},
-                      cn, s);
+  // G4: z = T3 P_M^T.  16-bit operands: the 256 x 256 tile stores z only and
+  // a light pass forms z.r, z.q, sum z (the fused epilogue does not fit
+  // beside that tile's registers); FP32 / FP64 fuse the sums.
+  if constexpr (sizeof(OT) == 2) {
+    gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
+                 EpiStoreZ<T>{static_cast<T*>(a.z), Mp, 1.0 / a.scale,
+                              f16 ? a.st.sc + SC_SCALE : nullptr},
+                 cn, s);
+    const int nb = elementwise_blocks(Np * Mp);
+    hipLaunchKernelGGL(zdots_kernel<T>, dim3(nb), dim3(kThreads), 0, s, static_cast<const T*>(a.z),
+                       r, static_cast<const T*>(a.q), Np * Mp, a.st, 1);
+    return nb;
+  } else {
+    return gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
+                        EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
+                                    1.0 / a.scale, nullptr},
+                        cn, s);
+  }
 }
 
 int launch_precond(const PrecondArgs& a, hipStream_t s) {
@@ -453,12 +510,12 @@ int launch_precond(const PrecondArgs& a, hipStream_t s) {
 // multiples of 256 so that G1..G3 use the 256 x 256 tile, G4 the 128 x 128.
 template <class OT, int G>
 struct BatchCfg {
-  using type = typename std::conditional<G == 4, CfgSmall16, CfgBig16>::type;
+  using type = CfgBig16;
 };
 
 template <int G>
 constexpr int batch_threads() {
-  return G == 4 ? CfgSmall16::THREADS : CfgBig16::THREADS;
+  return CfgBig16::THREADS;
 }
 
 template <class OT, class T, int G>
@@ -485,20 +542,30 @@ __global__ __launch_bounds__(batch_threads<G>()) void gemm_batched_kernel(
                          EpiStoreT<OT>{static_cast<OT*>(bt.T3), Mp}, ctl);
   } else {
     gemm_body<OT, OT, C>(static_cast<const OT*>(bt.T3), Mp, static_cast<const OT*>(bt.PM), Mp, Mp,
-                         (int)(Np / C::BM), (int)(Mp / C::BN), 8, bid, 1.0f,
-                         EpiFinal<T>{bt.z, bt.r, bt.flexible_q ? bt.q : nullptr, Mp, 1.0,
-                                     f16 ? bt.st.sc + SC_SCALE : nullptr},
-                         ctl);
+                         (int)(Np / C::BM), (int)(Mp / C::BN), 4, bid, 1.0f,
+                         EpiStoreZ<T>{bt.z, Mp, 1.0, f16 ? bt.st.sc + SC_SCALE : nullptr}, ctl);
   }
 }
 
 void precond_blocks(int kind, int64_t Np, int64_t Mp, int out[4]) {
   (void)kind;
-  const int64_t B = CfgBig16::BM, S = CfgSmall16::BM;
+  const int64_t B = CfgBig16::BM;
   out[0] = (int)((Np / B) * (Mp / B));
   out[1] = (int)((Mp / B) * (Np / B));
   out[2] = out[1];
-  out[3] = (int)((Np / S) * (Mp / S));
+  out[3] = out[0];
+}
+
+// Grouped z.r / z.q / sum z over a batch: each tile uses its stencil block
+// count (st_nblk), which is also its g4_nparts.
+template <class T>
+__global__ __launch_bounds__(kThreads) void zdots_batched_kernel(const BatchTile<T>* tiles,
+                                                                 const int32_t* start, int ntiles) {
+  const int t = find_tile(start, ntiles, (int)blockIdx.x);
+  const BatchTile<T>& bt = tiles[t];
+  if (bt.st.fl[FL_DONE]) return;
+  zdots_body<T>(bt.z, bt.r, bt.flexible_q ? bt.q : nullptr, bt.Np * bt.ld, bt.st,
+                (int)blockIdx.x - start[t], bt.st_nblk);
 }
 
 template <class OT>
@@ -516,20 +583,15 @@ static void precond_batched_impl(const BatchTile<float>* tiles, const int32_t* s
 }
 
 void launch_precond_batched(int kind, const void* tiles, const int32_t* starts, int ntiles,
-                            const int* totals, int check_conv, hipStream_t s) {
+                            const int* totals, int check_conv, const int32_t* st_start,
+                            int st_total, hipStream_t s) {
   const BatchTile<float>* t = static_cast<const BatchTile<float>*>(tiles);
   if (kind == OK_F16)
     precond_batched_impl<_Float16>(t, starts, ntiles, totals, check_conv, s);
   else
     precond_batched_impl<__bf16>(t, starts, ntiles, totals, check_conv, s);
-}
-
-int precond_nparts(int kind, int64_t Np, int64_t Mp) {
-  switch (kind) {
-    case OK_F64: return (int)((Np / CfgF64::BM) * (Mp / CfgF64::BN));
-    case OK_F32: return (int)((Np / CfgF32::BM) * (Mp / CfgF32::BN));
-    default: return (int)((Np / CfgSmall16::BM) * (Mp / CfgSmall16::BN));
-  }
+  hipLaunchKernelGGL(zdots_batched_kernel<float>, dim3(st_total), dim3(kThreads), 0, s, t, st_start,
+                     ntiles);
 }
 
 // ---- basis tables ------------------------------------------------------

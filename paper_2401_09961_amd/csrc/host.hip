@@ -625,7 +625,8 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
       }
     }
     launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, 0, flexible, 0, s);
-    launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, s);
+    launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
+                           b->st_total, s);
     for (int l = 0; l < prm.pcg_max; ++l) {
       launch_stencil_batched<float>(ST_FUSED, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
                                     s);
@@ -633,7 +634,8 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
       if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max)
         launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
                                       s);
-      if (l + 1 < prm.pcg_max) launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, s);
+      if (l + 1 < prm.pcg_max) launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
+                           b->st_total, s);
       if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
       if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
         HIP_OK(hipMemcpyAsync(b->h_flags, base + b->fl_off, (size_t)nt * FL_COUNT * sizeof(int32_t),
@@ -1048,7 +1050,7 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
     b->st_nblk.push_back((int32_t)(g.x * g.y));
     int gb[4];
     precond_blocks(b->kind, Np, Mp, gb);
-    b->g4_nparts.push_back(gb[3]);
+    b->g4_nparts.push_back((int32_t)(g.x * g.y));
     const int64_t bw = ((Mp + kThreads - 1) / kThreads);
     int64_t wrows = 1;
     while (bw * ((Np + wrows - 1) / wrows) > kMaxPartials / 2) wrows *= 2;

@@ -183,13 +183,12 @@ struct PrecondArgs {
 };
 // Returns the number of partials written by the last product (z.r etc.).
 int launch_precond(const PrecondArgs& a, hipStream_t s);
-// Number of partials the preconditioner's last product writes for a problem.
-int precond_nparts(int kind, int64_t Np, int64_t Mp);
 // Grouped preconditioner over the tiles of a batch (operand kind of the
 // batch); starts[g] are the per-tile block prefixes of product g (4 x
 // (ntiles + 1) entries, device), totals[g] the grid sizes.
 void launch_precond_batched(int kind, const void* tiles, const int32_t* starts, int ntiles,
-                            const int* totals, int check_conv, hipStream_t s);
+                            const int* totals, int check_conv, const int32_t* st_start,
+                            int st_total, hipStream_t s);
 // Per-tile block counts of the four products (host side, for the prefixes).
 void precond_blocks(int kind, int64_t Np, int64_t Mp, int out[4]);
 void launch_basis(int kind, int64_t n, int64_t npad, void* P, void* Pt, void* eig_inv,
