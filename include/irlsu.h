@@ -109,7 +109,18 @@ typedef struct irlsu_plan_desc {
   int32_t elem_bytes;     /* 8 for F64 plans, 4 otherwise */
   size_t workspace_bytes; /* workspace needed by irlsu_unwrap and the step functions */
   size_t plan_bytes;      /* device memory owned by the plan (basis, eigenvalues) */
+  int32_t folded;         /* 1: preconditioner in the folded (even/odd) form */
+  int32_t reserved_;
 } irlsu_plan_desc;
+
+/* Form of the preconditioner products (irlsu_plan_create_ex). */
+enum {
+  IRLSU_PLAN_AUTO = 0,   /* folded when N, M are even and N M >= 2^20, else dense */
+  IRLSU_PLAN_DENSE = 1,  /* four dense products (Section 3.3 as written) */
+  IRLSU_PLAN_FOLDED = 2  /* reflection symmetry of the DCT-II basis: each product
+                            splits into even / odd halves, half the MFMA work;
+                            N and M must be even (else ERR_SHAPE) */
+};
 
 /* Human-readable name of a status code (static storage). */
 const char* irlsu_status_string(irlsu_status st);
@@ -121,10 +132,17 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec);
  * bases P_N, P_M and the Laplacian eigenvalues 2 - 2 cos(pi k / n) on the
  * current HIP device (Section 3.3, eq:eigendecompositions: computed once,
  * reused by every PCG iteration).  Synchronises the stream before returning.
+ * Sizes: 2 <= N, M <= 32768 and (ceil(N/128) * ceil(M/128)) <= 16384 (the
+ * 64 x 64 tile count of the padded image must fit the partial-sum table).
  * Errors: ERR_INVALID_ARG (out null), ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM,
  * ERR_HIP.  On error *out is NULL and nothing is leaked. */
 irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M,
                                irlsu_precision prec, void* stream);
+
+/* As irlsu_plan_create, choosing the form of the preconditioner products
+ * (IRLSU_PLAN_AUTO / _DENSE / _FOLDED); both forms compute the same map. */
+irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M,
+                                  irlsu_precision prec, int32_t form, void* stream);
 
 /* Release a plan and its device memory.  NULL is accepted. */
 irlsu_status irlsu_plan_destroy(irlsu_plan* plan);

@@ -29,7 +29,7 @@ IRLSU_MAX_IRLS = 256
 # every function declared in include/irlsu.h
 DECLARED_SYMBOLS = (
     "irlsu_status_string", "irlsu_params_default", "irlsu_plan_create",
-    "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
+    "irlsu_plan_create_ex", "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
     "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
     "irlsu_operator", "irlsu_precond", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
@@ -94,7 +94,12 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64),
                 ("Np", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_size_t), ("plan_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("plan_bytes", ctypes.c_size_t),
+                ("folded", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
+# form of the preconditioner products (irlsu_plan_create_ex)
+PLAN_FORMS = {"auto": 0, "dense": 1, "folded": 2}
 
 
 _lib = None
@@ -118,6 +123,7 @@ def load_library():
         "irlsu_status_string": (ctypes.c_char_p, [I32]),
         "irlsu_params_default": (I32, [ctypes.POINTER(Params), I32]),
         "irlsu_plan_create": (I32, [ctypes.POINTER(P), I64, I64, I32, P]),
+        "irlsu_plan_create_ex": (I32, [ctypes.POINTER(P), I64, I64, I32, I32, P]),
         "irlsu_plan_destroy": (I32, [P]),
         "irlsu_plan_info": (I32, [P, ctypes.POINTER(PlanDesc)]),
         "irlsu_workspace_bytes": (SZ, [P]),
@@ -171,7 +177,7 @@ class Plan:
     tensor allocated by torch.
     """
 
-    def __init__(self, N: int, M: int, precision: str = "f32", device=None):
+    def __init__(self, N: int, M: int, precision: str = "f32", device=None, form: str = "auto"):
         import torch
         self.lib = load_library()
         self.precision = precision
@@ -179,14 +185,16 @@ class Plan:
                        else torch.device(device))
         with torch.cuda.device(self.device):
             h = ctypes.c_void_p()
-            _check(self.lib.irlsu_plan_create(ctypes.byref(h), int(N), int(M),
-                                              PRECISIONS[precision], _stream()), "plan_create")
+            _check(self.lib.irlsu_plan_create_ex(ctypes.byref(h), int(N), int(M),
+                                                 PRECISIONS[precision], PLAN_FORMS[form],
+                                                 _stream()), "plan_create")
             self.handle = h
             d = PlanDesc()
             _check(self.lib.irlsu_plan_info(h, ctypes.byref(d)))
             self.desc = d
             self.workspace = torch.empty(int(d.workspace_bytes), dtype=torch.uint8, device=self.device)
         self.N, self.M, self.Np, self.ld = d.N, d.M, d.Np, d.ld
+        self.folded = bool(d.folded)
         self.dtype = torch.float64 if d.elem_bytes == 8 else torch.float32
 
     def close(self):

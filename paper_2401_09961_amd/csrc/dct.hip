@@ -322,6 +322,7 @@ struct EpiScale {
   int64_t ldc;
   const double* eigM;  // rows of this product are the l (column) modes
   const double* eigN;  // columns are the k (row) modes
+  int zero_origin = 1; // (m, n) = (0, 0) is the constant mode (set to zero)
   using Acc = NoAcc;
   template <int RS, class V>
   __device__ __forceinline__ void apply(int64_t m, int64_t n, const V (&v)[4], Acc&) const {
@@ -330,7 +331,7 @@ struct EpiScale {
     for (int t = 0; t < 4; ++t) {
       const int64_t mm = m + t * RS;
       const double lam = eigM[mm] + en;
-      const double f = (mm == 0 && n == 0) ? 0.0 : 1.0 / lam;
+      const double f = (zero_origin && mm == 0 && n == 0) ? 0.0 : 1.0 / lam;
       C[mm * ldc + n] = (OT)((double)v[t] * f);
     }
   }
@@ -495,7 +496,65 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
   }
 }
 
+// Folded form: the same map with every dense product split into its even
+// and odd halves (half the MFMA work); see fold.hip for the identities.
+template <class OT, class T>
+static int precond_folded_impl(const PrecondArgs& a, hipStream_t s) {
+  const int64_t N = a.N, M = a.M, Np = a.Np, Mp = a.Mp, hN = a.hNp, hM = a.hMp;
+  const int64_t wN = 2 * hN, wM = 2 * hM;  // folded widths
+  const OT* PeN = static_cast<const OT*>(a.PeN);
+  const OT* PeNt = static_cast<const OT*>(a.PeNt);
+  const OT* PoN = static_cast<const OT*>(a.PoN);
+  const OT* PoNt = static_cast<const OT*>(a.PoNt);
+  const OT* PeM = static_cast<const OT*>(a.PeM);
+  const OT* PeMt = static_cast<const OT*>(a.PeMt);
+  const OT* PoM = static_cast<const OT*>(a.PoM);
+  const OT* PoMt = static_cast<const OT*>(a.PoMt);
+  const double* eN = static_cast<const double*>(a.eigNf);
+  const double* eM = static_cast<const double*>(a.eigMf);
+  OT* X1 = static_cast<OT*>(a.T1);
+  OT* X2 = static_cast<OT*>(a.T2);
+  T* ZEO = static_cast<T*>(a.ZEO);
+  const T* r = static_cast<const T*>(a.r);
+  const int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
+  const int32_t* done = a.st.fl + FL_DONE;
+  GemmCtl cn{a.st, 1, 0, 0, 0, 0};
+  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
+  // S = [r_j + r_{M-1-j} | r_j - r_{M-1-j}]           (Np x wM)
+  launch_fold_rows<T, OT>(r, Mp, M, N, Np, X1, hM, f16 ? a.st.sc + SC_SCALE : nullptr, done, s);
+  // T1^T: even / odd column modes, transposed stores     (wM x Np)
+  gemm<OT, OT>(X1, wM, PeMt, hM, Np, hM, hM, 1.0f, EpiStoreT<OT>{X2, Np}, cn, s);
+  gemm<OT, OT>(X1 + hM, wM, PoMt, hM, Np, hM, hM, 1.0f, EpiStoreT<OT>{X2 + hM * Np, Np}, cn, s);
+  // fold the rows index of T1^T                           (wM x wN)
+  launch_fold_rows<OT, OT>(X2, Np, N, wM, wM, X1, hN, nullptr, done, s);
+  // T2^T = (P_N^T T1)^T ./ lambda: even / odd row modes   (wM x wN)
+  gemm<OT, OT>(X1, wN, PeNt, hN, wM, hN, hN, 1.0f, EpiScale<OT>{X2, wN, eM, eN, 1}, cn, s);
+  gemm<OT, OT>(X1 + hN, wN, PoNt, hN, wM, hN, hN, 1.0f, EpiScale<OT>{X2 + hN, wN, eM, eN + hN, 0},
+               cn, s);
+  // inverse along rows: E and O stacked                   (wN x wM)
+  gemm<OT, OT>(X2, wN, PeN, hN, wM, hN, hN, 1.0f, EpiStoreT<OT>{X1, wM}, cn, s);
+  gemm<OT, OT>(X2 + hN, wN, PoN, hN, wM, hN, hN, 1.0f, EpiStoreT<OT>{X1 + hN * wM, wM}, cn, s);
+  // T3 rows i, N-1-i = E +- O                              (Np x wM)
+  launch_unfold_rows<OT>(X1, wM, N, hN, Np, X2, done, s);
+  // inverse along columns: zE | zO                         (Np x wM, vector type)
+  gemm<OT, OT>(X2, wM, PeM, hM, Np, hM, hM, 1.0f, EpiStoreZ<T>{ZEO, wM, 1.0, nullptr}, cn, s);
+  gemm<OT, OT>(X2 + hM, wM, PoM, hM, Np, hM, hM, 1.0f, EpiStoreZ<T>{ZEO + hM, wM, 1.0, nullptr}, cn,
+               s);
+  // z = zE +- zO (undoing the FP16 scale), z.r, z.q, sum z
+  return launch_unfold_cols_dots<T>(ZEO, hM, N, M, Np, Mp, static_cast<T*>(a.z), r,
+                                    static_cast<const T*>(a.q), 1.0,
+                                    f16 ? a.st.sc + SC_SCALE : nullptr, a.st, s);
+}
+
 int launch_precond(const PrecondArgs& a, hipStream_t s) {
+  if (a.folded) {
+    switch (a.kind) {
+      case OK_F64: return precond_folded_impl<double, double>(a, s);
+      case OK_F32: return precond_folded_impl<float, float>(a, s);
+      case OK_BF16: return precond_folded_impl<__bf16, float>(a, s);
+      case OK_F16: return precond_folded_impl<_Float16, float>(a, s);
+    }
+  }
   switch (a.kind) {
     case OK_F64: return precond_impl<double, double>(a, s);
     case OK_F32: return precond_impl<float, float>(a, s);

@@ -38,6 +38,12 @@ struct irlsu_plan {
   int32_t* h_flags = nullptr;   // pinned
   double* h_sc = nullptr;       // pinned
   int device = 0;
+  // folded preconditioner (even N and M)
+  int folded = 0;
+  int64_t hNp = 0, hMp = 0;
+  void *PeN = nullptr, *PeNt = nullptr, *PoN = nullptr, *PoNt = nullptr;
+  void *PeM = nullptr, *PeMt = nullptr, *PoM = nullptr, *PoMt = nullptr;
+  double *eigNf = nullptr, *eigMf = nullptr;
 };
 
 struct irlsu_batch {
@@ -73,7 +79,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 enum VecId { V_R, V_Z, V_P0, V_P1, V_Q, V_B, V_GV, V_GH, V_CV, V_CH, V_OV, V_OH, V_COUNT };
 
 struct Layout {
-  size_t u, lam, vec[V_COUNT], t1, t2, t3, part, sc, fl, total;
+  size_t u, lam, vec[V_COUNT], t1, t2, t3, zeo, part, sc, fl, total;
 };
 
 Layout layout(const irlsu_plan* p) {
@@ -88,12 +94,17 @@ Layout layout(const irlsu_plan* p) {
     L.vec[v] = off;
     off = align_up(off + npx * p->elem);
   }
+  // preconditioner intermediates: dense form Np x Mp each; folded form two
+  // ping-pong buffers of 2 hNp x 2 hMp and an Np x 2 hMp vector-type buffer
+  const size_t inter = p->folded ? (size_t)(2 * p->hNp) * (size_t)(2 * p->hMp) : npx;
   L.t1 = off;
-  off = align_up(off + npx * p->opsz);
+  off = align_up(off + inter * p->opsz);
   L.t2 = off;
-  off = align_up(off + npx * p->opsz);
+  off = align_up(off + inter * p->opsz);
   L.t3 = off;
-  off = align_up(off + npx * p->opsz);
+  off = align_up(off + (p->folded ? 0 : npx) * p->opsz);
+  L.zeo = off;
+  off = align_up(off + (p->folded ? (size_t)p->Np * (size_t)(2 * p->hMp) : 0) * p->elem);
   L.part = off;
   off = align_up(off + (size_t)kPartSlots * kMaxPartials * sizeof(double));
   L.sc = off;
@@ -109,7 +120,7 @@ struct Ws {
   double* U;
   double* lam;
   T* v[V_COUNT];
-  void *T1, *T2, *T3;
+  void *T1, *T2, *T3, *ZEO;
   DevState st;
 };
 
@@ -124,6 +135,7 @@ Ws<T> carve(const irlsu_plan* p, void* base) {
   w.T1 = b + L.t1;
   w.T2 = b + L.t2;
   w.T3 = b + L.t3;
+  w.ZEO = b + L.zeo;
   w.st.part = reinterpret_cast<double*>(b + L.part);
   w.st.sc = reinterpret_cast<double*>(b + L.sc);
   w.st.fl = reinterpret_cast<int32_t*>(b + L.fl);
@@ -168,6 +180,20 @@ PrecondArgs precond_args(const irlsu_plan* pl, const Ws<T>& W, const T* r, T* z,
   a.check_conv = check_conv;
   a.nparts_rr = nparts_rr;
   a.st = W.st;
+  a.folded = pl->folded;
+  a.hNp = pl->hNp;
+  a.hMp = pl->hMp;
+  a.PeN = pl->PeN;
+  a.PeNt = pl->PeNt;
+  a.PoN = pl->PoN;
+  a.PoNt = pl->PoNt;
+  a.PeM = pl->PeM;
+  a.PeMt = pl->PeMt;
+  a.PoM = pl->PoM;
+  a.PoMt = pl->PoMt;
+  a.eigNf = pl->eigNf;
+  a.eigMf = pl->eigMf;
+  a.ZEO = W.ZEO;
   return a;
 }
 
@@ -737,11 +763,19 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec) {
 
 irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M, irlsu_precision prec,
                                void* stream) {
+  return irlsu_plan_create_ex(out, N, M, prec, IRLSU_PLAN_AUTO, stream);
+}
+
+irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_precision prec,
+                                  int32_t form, void* stream) {
   if (!out) return IRLSU_ERR_INVALID_ARG;
   *out = nullptr;
   if (N < 2 || M < 2) return IRLSU_ERR_SHAPE;
   if (prec < IRLSU_F64 || prec > IRLSU_MIXED_F16) return IRLSU_ERR_UNSUPPORTED;
-  if (N > (int64_t)1 << 20 || M > (int64_t)1 << 20) return IRLSU_ERR_SHAPE;
+  if (form < IRLSU_PLAN_AUTO || form > IRLSU_PLAN_FOLDED) return IRLSU_ERR_INVALID_ARG;
+  if (N > kMaxSide || M > kMaxSide) return IRLSU_ERR_SHAPE;
+  const bool even = (N % 2 == 0) && (M % 2 == 0);
+  if (form == IRLSU_PLAN_FOLDED && !even) return IRLSU_ERR_SHAPE;
   irlsu_plan* p = new (std::nothrow) irlsu_plan;
   if (!p) return IRLSU_ERR_OOM;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -756,6 +790,11 @@ irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M, irlsu_pre
     case IRLSU_MIXED_BF16: p->kind = OK_BF16; p->elem = 4; p->opsz = 2; break;
     case IRLSU_MIXED_F16: p->kind = OK_F16; p->elem = 4; p->opsz = 2; break;
   }
+  // the folded form pays off once the products dominate the extra passes
+  p->folded = form == IRLSU_PLAN_FOLDED ||
+              (form == IRLSU_PLAN_AUTO && even && p->Np * p->Mp >= ((int64_t)1 << 20));
+  p->hNp = round_up(N / 2, kTilePad);
+  p->hMp = round_up(M / 2, kTilePad);
   // the GEMM grids and the partial-sum table bound the supported size
   const int64_t tiles = (p->Np / 64) * (p->Mp / 64);
   if (tiles > kMaxPartials) {
@@ -763,14 +802,44 @@ irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M, irlsu_pre
     return IRLSU_ERR_SHAPE;
   }
   (void)hipGetDevice(&p->device);
-  const bool share = (p->Np == p->Mp) && (N == M);
-  const size_t bN = (size_t)p->Np * p->Np * p->opsz;
-  const size_t bM = (size_t)p->Mp * p->Mp * p->opsz;
-  bool ok = hipMalloc(&p->PN, bN) == hipSuccess && hipMalloc(&p->PNt, bN) == hipSuccess &&
-            hipMalloc(&p->eigN, p->Np * sizeof(double)) == hipSuccess;
-  if (ok && !share) {
-    ok = hipMalloc(&p->PM, bM) == hipSuccess && hipMalloc(&p->PMt, bM) == hipSuccess &&
-         hipMalloc(&p->eigM, p->Mp * sizeof(double)) == hipSuccess;
+  bool ok = true;
+  if (p->folded) {
+    const bool share = (N == M);
+    const size_t bN = (size_t)p->hNp * p->hNp * p->opsz;
+    const size_t bM = (size_t)p->hMp * p->hMp * p->opsz;
+    ok = hipMalloc(&p->PeN, bN) == hipSuccess && hipMalloc(&p->PeNt, bN) == hipSuccess &&
+         hipMalloc(&p->PoN, bN) == hipSuccess && hipMalloc(&p->PoNt, bN) == hipSuccess &&
+         hipMalloc(reinterpret_cast<void**>(&p->eigNf), 2 * p->hNp * sizeof(double)) == hipSuccess;
+    if (ok && !share) {
+      ok = hipMalloc(&p->PeM, bM) == hipSuccess && hipMalloc(&p->PeMt, bM) == hipSuccess &&
+           hipMalloc(&p->PoM, bM) == hipSuccess && hipMalloc(&p->PoMt, bM) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void**>(&p->eigMf), 2 * p->hMp * sizeof(double)) == hipSuccess;
+    }
+    if (ok && share) {
+      p->PeM = p->PeN;
+      p->PeMt = p->PeNt;
+      p->PoM = p->PoN;
+      p->PoMt = p->PoNt;
+      p->eigMf = p->eigNf;
+    }
+    p->plan_bytes = 4 * bN + 2 * p->hNp * sizeof(double) +
+                    (share ? 0 : 4 * bM + 2 * p->hMp * sizeof(double));
+  } else {
+    const bool share = (p->Np == p->Mp) && (N == M);
+    const size_t bN = (size_t)p->Np * p->Np * p->opsz;
+    const size_t bM = (size_t)p->Mp * p->Mp * p->opsz;
+    ok = hipMalloc(&p->PN, bN) == hipSuccess && hipMalloc(&p->PNt, bN) == hipSuccess &&
+         hipMalloc(reinterpret_cast<void**>(&p->eigN), p->Np * sizeof(double)) == hipSuccess;
+    if (ok && !share) {
+      ok = hipMalloc(&p->PM, bM) == hipSuccess && hipMalloc(&p->PMt, bM) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void**>(&p->eigM), p->Mp * sizeof(double)) == hipSuccess;
+    }
+    if (ok && share) {
+      p->PM = p->PN;
+      p->PMt = p->PNt;
+      p->eigM = p->eigN;
+    }
+    p->plan_bytes = 2 * bN + p->Np * sizeof(double) + (share ? 0 : 2 * bM + p->Mp * sizeof(double));
   }
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), 256, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&p->h_sc), 512, hipHostMallocDefault) == hipSuccess;
@@ -779,14 +848,14 @@ irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M, irlsu_pre
     irlsu_plan_destroy(p);
     return IRLSU_ERR_OOM;
   }
-  if (share) {
-    p->PM = p->PN;
-    p->PMt = p->PNt;
-    p->eigM = p->eigN;
+  if (p->folded) {
+    launch_fold_basis(p->kind, N, p->hNp, p->PeN, p->PeNt, p->PoN, p->PoNt, p->eigNf, s);
+    if (p->PeM != p->PeN)
+      launch_fold_basis(p->kind, M, p->hMp, p->PeM, p->PeMt, p->PoM, p->PoMt, p->eigMf, s);
+  } else {
+    launch_basis(p->kind, N, p->Np, p->PN, p->PNt, p->eigN, s);
+    if (p->PM != p->PN) launch_basis(p->kind, M, p->Mp, p->PM, p->PMt, p->eigM, s);
   }
-  p->plan_bytes = 2 * bN + p->Np * sizeof(double) + (share ? 0 : 2 * bM + p->Mp * sizeof(double));
-  launch_basis(p->kind, N, p->Np, p->PN, p->PNt, p->eigN, s);
-  if (!share) launch_basis(p->kind, M, p->Mp, p->PM, p->PMt, p->eigM, s);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     irlsu_plan_destroy(p);
     return IRLSU_ERR_HIP;
@@ -798,6 +867,11 @@ irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M, irlsu_pre
 
 irlsu_status irlsu_plan_destroy(irlsu_plan* p) {
   if (!p) return IRLSU_OK;
+  const bool fshare = p->PeM == p->PeN;
+  void* fold_n[] = {p->PeN, p->PeNt, p->PoN, p->PoNt, p->eigNf};
+  void* fold_m[] = {p->PeM, p->PeMt, p->PoM, p->PoMt, p->eigMf};
+  for (void* q : fold_n) if (q) (void)hipFree(q);
+  if (!fshare) for (void* q : fold_m) if (q) (void)hipFree(q);
   const bool share = p->PM == p->PN;
   if (p->PN) (void)hipFree(p->PN);
   if (p->PNt) (void)hipFree(p->PNt);
@@ -823,6 +897,7 @@ irlsu_status irlsu_plan_info(const irlsu_plan* p, irlsu_plan_desc* out) {
   out->elem_bytes = (int32_t)p->elem;
   out->workspace_bytes = p->ws_bytes;
   out->plan_bytes = p->plan_bytes;
+  out->folded = p->folded;
   return IRLSU_OK;
 }
 
@@ -1024,8 +1099,8 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
   *out = nullptr;
   if (prec != IRLSU_MIXED_BF16 && prec != IRLSU_MIXED_F16) return IRLSU_ERR_UNSUPPORTED;
   for (int t = 0; t < ntiles; ++t)
-    if (shapes[2 * t] < 2 || shapes[2 * t + 1] < 2 || shapes[2 * t] > 65536 ||
-        shapes[2 * t + 1] > 65536)
+    if (shapes[2 * t] < 2 || shapes[2 * t + 1] < 2 || shapes[2 * t] > kMaxSide ||
+        shapes[2 * t + 1] > kMaxSide)
       return IRLSU_ERR_SHAPE;
   irlsu_batch* b = new (std::nothrow) irlsu_batch;
   if (!b) return IRLSU_ERR_OOM;

@@ -180,6 +180,15 @@ struct PrecondArgs {
   int check_conv;           // first product checks ||r|| <= tol ||b|| and stops
   int nparts_rr;            // partials of ||r||^2 for the convergence check
   DevState st;
+  // folded form (even N and M): half-size bases, even-first eigenvalue
+  // tables (length 2 hNp / 2 hMp), two ping-pong operand buffers of
+  // 2 hNp x 2 hMp elements and an FP32/FP64 buffer of Np x 2 hMp.
+  int folded = 0;
+  int64_t hNp = 0, hMp = 0;
+  const void *PeN = nullptr, *PeNt = nullptr, *PoN = nullptr, *PoNt = nullptr;
+  const void *PeM = nullptr, *PeMt = nullptr, *PoM = nullptr, *PoMt = nullptr;
+  const void *eigNf = nullptr, *eigMf = nullptr;
+  void* ZEO = nullptr;
 };
 // Returns the number of partials written by the last product (z.r etc.).
 int launch_precond(const PrecondArgs& a, hipStream_t s);
@@ -193,5 +202,20 @@ void launch_precond_batched(int kind, const void* tiles, const int32_t* starts, 
 void precond_blocks(int kind, int64_t Np, int64_t Mp, int out[4]);
 void launch_basis(int kind, int64_t n, int64_t npad, void* P, void* Pt, void* eig_inv,
                   hipStream_t s);
+void launch_fold_basis(int kind, int64_t n, int64_t hp, void* Pe, void* Pet, void* Po, void* Pot,
+                       void* eig, hipStream_t s);
+void launch_fold_prologue(DevState st, int nparts_rr, int check_conv, int want_scale, int64_t npix,
+                          hipStream_t s);
+template <class TI, class TO>
+void launch_fold_rows(const TI* in, int64_t ldin, int64_t n, int64_t rows_valid, int64_t rows,
+                      TO* out, int64_t hp, const double* dscale, const int32_t* done,
+                      hipStream_t s);
+template <class OT>
+void launch_unfold_rows(const OT* eo, int64_t ld, int64_t N, int64_t hNp, int64_t Np, OT* out,
+                        const int32_t* done, hipStream_t s);
+template <class T>
+int launch_unfold_cols_dots(const T* zeo, int64_t hMp, int64_t N, int64_t M, int64_t Np, int64_t ld,
+                            T* z, const T* r, const T* q, double zscale, const double* dscale,
+                            DevState st, hipStream_t s);
 
 }  // namespace irlsu

@@ -64,6 +64,12 @@ def test_host_validation_without_gpu(lib):
     assert lib.irlsu_plan_create(ctypes.byref(h), 1, 8, 1, None) == -2
     assert lib.irlsu_plan_create(ctypes.byref(h), 8, 0, 1, None) == -2
     assert lib.irlsu_plan_create(ctypes.byref(h), 8, 8, 7, None) == -8
+    assert lib.irlsu_plan_create(ctypes.byref(h), 32769, 8, 1, None) == -2
+    # form: 0 auto, 1 dense, 2 folded (even sides only)
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 8, 8, 1, 3, None) == -1
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 8, 8, 1, -1, None) == -1
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 9, 8, 1, 2, None) == -2
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 8, 7, 1, 2, None) == -2
     assert h.value is None
     assert lib.irlsu_workspace_bytes(None) == 0
     assert lib.irlsu_plan_destroy(None) == 0
@@ -85,8 +91,8 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(irlsu_params), sizeof(irlsu_iter_stats),
          sizeof(irlsu_stats), sizeof(irlsu_plan_desc));
-  printf("%zu %zu %zu\\n", offsetof(irlsu_params, irls_iters), offsetof(irlsu_stats, iter),
-         offsetof(irlsu_plan_desc, workspace_bytes));
+  printf("%zu %zu %zu %zu\\n", offsetof(irlsu_params, irls_iters), offsetof(irlsu_stats, iter),
+         offsetof(irlsu_plan_desc, workspace_bytes), offsetof(irlsu_plan_desc, folded));
   return 0;
 }
 """)
@@ -98,4 +104,4 @@ int main(void) {
     assert sizes == [ctypes.sizeof(pkg.Params), ctypes.sizeof(pkg.IterStats),
                      ctypes.sizeof(pkg.Stats), ctypes.sizeof(pkg.PlanDesc)]
     assert offs == [pkg.Params.irls_iters.offset, pkg.Stats.iter.offset,
-                    pkg.PlanDesc.workspace_bytes.offset]
+                    pkg.PlanDesc.workspace_bytes.offset, pkg.PlanDesc.folded.offset]

@@ -185,6 +185,47 @@ def test_precond_big_tiles(p16, shape):
     plan.close()
 
 
+# even sides: the folded (even / odd) form; N/2 or M/2 not a multiple of 128
+# pads the half-size products
+FOLD_SHAPES = [(96, 80), (130, 514), (256, 256), (1000, 512)]
+
+
+@pytest.mark.parametrize("shape", FOLD_SHAPES)
+@pytest.mark.parametrize("fprec", ["f64", "f32", "bf16", "f16"])
+def test_precond_folded_matches_dct_oracle(fprec, shape):
+    N, M = shape
+    dt = npdt(fprec)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((N, M)).astype(dt)
+    plan = pkg.Plan(N, M, fprec, form="folded")
+    assert plan.folded
+    z, rz = plan.precond(internal(plan, r))
+    torch.cuda.synchronize()
+    z_o = R.apply_precond(r.astype(np.float64))
+    zg = z.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
+    print(f"precond folded {fprec} {shape}: rel err {rel:.3e}")
+    assert rel <= PRECOND_RTOL["bf16" if fprec == "f16" else fprec]
+    assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
+    ref = float(np.sum(r.astype(np.float64) * z_o))
+    assert abs(rz.item() - ref) <= 2 * PRECOND_RTOL["bf16" if fprec == "f16" else fprec] * abs(ref)
+    plan.close()
+
+
+def test_precond_folded_is_pseudo_inverse_property_f64():
+    """The folded form solves the same Neumann problem: L z = r - mean(r)."""
+    N, M = 384, 200
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal((N, M))
+    plan = pkg.Plan(N, M, "f64", form="folded")
+    z, _ = plan.precond(internal(plan, r))
+    zg = z.cpu().numpy()[:N, :M]
+    Lz = R.apply_A(np.ones((N - 1, M)), np.ones((N, M - 1)), zg)
+    assert np.abs(Lz - (r - r.mean())).max() < 1e-10
+    assert abs(zg.mean()) < 1e-12
+    plan.close()
+
+
 def test_precond_is_pseudo_inverse_property_f64():
     """L z = r - mean(r) with L the unweighted Neumann Laplacian (applied by
     the oracle's plain stencil), at a size with several GEMM tiles."""

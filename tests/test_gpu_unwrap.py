@@ -32,7 +32,7 @@ def npdt(prec):
     return np.float64 if prec == "f64" else np.float32
 
 
-def run_both(f, prec, iters, maxit, tol=None, eps=1e-3, weights=True):
+def run_both(f, prec, iters, maxit, tol=None, eps=1e-3, weights=True, form="auto"):
     dt = npdt(prec)
     N, M = f.X.shape
     X = f.X.astype(dt)
@@ -41,7 +41,7 @@ def run_both(f, prec, iters, maxit, tol=None, eps=1e-3, weights=True):
     p.irls_iters, p.pcg_max, p.eps = iters, maxit, eps
     if tol is not None:
         p.pcg_rtol = tol
-    plan = pkg.Plan(N, M, prec)
+    plan = pkg.Plan(N, M, prec, form=form)
     U, st = plan.unwrap(torch.from_numpy(X).cuda(),
                         None if w is None else torch.from_numpy(w).cuda(), params=p, stats=True)
     torch.cuda.synchronize()
@@ -90,6 +90,21 @@ def test_reduced_precision_objective(prec, gen, shape):
           f"gap {gap:.2e} pcg {st['pcg_total']}")
     assert gap <= L1_RTOL[prec]
     assert abs(Ug.mean()) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_folded_plan_objective(prec):
+    """The whole path with the folded preconditioner (c3 residue field,
+    even sides with padded half-size products)."""
+    f = synth.field_c3(4, 260, 192)
+    tol = 1e-10 if prec == "f64" else 1e-6
+    Ug, st, Uo, hist = run_both(f, prec, iters=5, maxit=3000, tol=tol, form="folded")
+    gap = abs(st["L1_final"] - hist[-1]["L1"]) / hist[-1]["L1"]
+    print(f"folded {prec}: GPU L1 {st['L1_final']:.10g} oracle {hist[-1]['L1']:.10g} gap {gap:.2e}")
+    assert gap <= L1_RTOL[prec]
+    assert abs(Ug.mean()) < (1e-12 if prec == "f64" else 1e-5)
+    if prec == "f64":
+        assert np.abs(Ug - Uo).max() < 1e-6
 
 
 def test_two_by_two_single_loop_closed_form():
