@@ -7,8 +7,10 @@ HIP events from X resident in HBM to U resident in HBM; the clock stops at
 the first IRLS iterate whose L1 is within 1e-3 of the stored oracle value.
 
 Also reported on the same JSON line:
-* roofline of the dominant kernel (the MFMA cosine-basis GEMMs of the
-  preconditioner), timed live with HIP events on the launch stream;
+* roofline of the dominant kernel (the MFMA cosine-basis products of the
+  preconditioner), each launch timed live with HIP events on the launch
+  stream; flops are the dense-equivalent 4NM(N+M) per application (the
+  folded even/odd form executes half of them, reported beside);
 * the stencil's achieved HBM bandwidth (algorithmic 24 B/px, fused form);
 * cpu_baseline: the FP64 oracle on a bounded sample of the same workload,
   scaled by its recorded iteration counts to the same target.
@@ -132,6 +134,30 @@ def time_stencil(plan, torch, reps=20):
     return e0.elapsed_time(e1) / reps
 
 
+def kernels_only(pkg, torch, N, M, prec):
+    """Fixed launch sequence for counter runs (no unwrap, no oracle)."""
+    torch.cuda.set_device(0)
+    plan = pkg.Plan(N, M, prec)
+    r = torch.randn((plan.Np, plan.ld), dtype=plan.dtype, device=plan.device)
+    r[N:, :] = 0
+    r[:, M:] = 0
+    tim = plan.precond_timed(r, reps=3)
+    ms_st = time_stencil(plan, torch, reps=3)
+    nbytes = 256 << 20
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device=plan.device).uniform_()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    out = {"N": N, "M": M, "precision": prec, "folded": plan.folded,
+           "precond_products_ms": tim["ms_products"] / tim["n_products"],
+           "precond_launches": tim["n_products"] // 3, "stencil_ms": ms_st,
+           "copy_bytes_each_way": nbytes}
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +169,10 @@ def main(argv=None):
     ap.add_argument("--gap", type=float, default=1e-3)
     ap.add_argument("--max-irls", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="a short fixed launch sequence for hardware-counter runs: "
+                         "3 preconditioner applications, 3 stencil applications and 3 "
+                         "copies of 256 MiB (the byte-count calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU path is "
@@ -156,6 +186,8 @@ def main(argv=None):
     cfg = CONFIGS[a.config]
     prec = a.precision or cfg["precision"]
     N = M = cfg["N"]
+    if a.kernels_only:
+        return kernels_only(pkg, torch, N, M, prec)
     ref = load_reference(cfg["ref"])
     L1_ref = ref["L1_final"]
     target = L1_ref * (1.0 + a.gap)
@@ -197,10 +229,22 @@ def main(argv=None):
     last = runs[-1]
     L1_reached = last["history"][last["irls_done"]]["L1"] if hit else last["L1_final"]
 
-    # dominant kernel: the preconditioner GEMMs (dense cosine-basis contractions)
-    ms_prec = time_precond(plan, torch)
-    flops = 4.0 * N * M * (N + M)
-    tf = flops / (ms_prec * 1e-3) / 1e12
+    # dominant kernel: the preconditioner's MFMA products, each launch timed
+    # with HIP events on the launch stream (irlsu_precond_timed)
+    rr = torch.randn((plan.Np, plan.ld), dtype=plan.dtype, device=plan.device)
+    rr[N:, :] = 0
+    rr[:, M:] = 0
+    plan.precond_timed(rr, reps=1)
+    reps = 5
+    tim = plan.precond_timed(rr, reps=reps)
+    n_prod = tim["n_products"] // reps           # 4 dense, 8 folded
+    ms_launch = tim["ms_products"] / tim["n_products"]
+    ms_prec = (tim["ms_products"] + tim["ms_passes"]) / reps
+    flops_app = 4.0 * N * M * (N + M)             # dense eigen-products per application
+    flops_launch = flops_app / n_prod             # dense-equivalent per launch
+    exec_launch = flops_launch / (2.0 if plan.folded else 1.0)
+    tf = flops_launch / (ms_launch * 1e-3) / 1e12
+    tf_exec = exec_launch / (ms_launch * 1e-3) / 1e12
     peak = PEAK[prec]
     ms_st = time_stencil(plan, torch)
     gbs = 16.0 * N * M / (ms_st * 1e-3) / 1e9
@@ -222,10 +266,17 @@ def main(argv=None):
                    "irls_iters": last["irls_done"], "pcg_iters": pcg_per_step,
                    "ms_per_pcg_iter": round(ms / max(1, pcg_per_step), 4),
                    "plan_create_s": round(plan_s, 3)},
-        "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel (4 launches per preconditioner)",
+        "roofline": {"bound": "mfma",
+                     "kernel": f"gemm_nt_kernel ({n_prod} launches per preconditioner, "
+                               f"{'folded even/odd' if plan.folded else 'dense'} form)",
                      "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(tf / peak, 4), "traffic": None,
-                     "flops_per_launch": flops / 4, "ms_per_launch": round(ms_prec / 4, 4)},
+                     "flops_per_launch": flops_launch,
+                     "flops_basis": "dense-equivalent 4NM(N+M) per application / launches",
+                     "executed_TFLOPs": round(tf_exec, 2),
+                     "executed_frac": round(tf_exec / peak, 4),
+                     "ms_per_launch": round(ms_launch, 4),
+                     "precond_ms": round(ms_prec, 4)},
         "stencil": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBps"],
                     "unit": "GB/s", "frac": round(gbs / PEAK["hbm_GBps"], 4),
                     "bytes_per_px": 16, "ms": round(ms_st, 4)},

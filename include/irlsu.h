@@ -285,6 +285,19 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
 irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* Timing of the preconditioner of Section 3.3 (the products named there as
+ * the main cost): reps applications of irlsu_precond's map, with a HIP event
+ * recorded on `stream` before the first launch and after every launch.
+ * Returns the summed durations (ms) and launch counts of the MFMA products
+ * (*ms_products, *n_products) and of every other pass (*ms_passes,
+ * *n_passes) over all reps; z receives the last application.  Synchronises
+ * the stream.  Errors as irlsu_precond; ERR_INVALID_ARG also for reps < 1 or
+ * a null output pointer; ERR_HIP when events cannot be created. */
+irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
+                                 void* workspace, size_t workspace_bytes, int32_t reps,
+                                 double* ms_products, int32_t* n_products,
+                                 double* ms_passes, int32_t* n_passes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,7 @@ DECLARED_SYMBOLS = (
     "irlsu_status_string", "irlsu_params_default", "irlsu_plan_create",
     "irlsu_plan_create_ex", "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
     "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
-    "irlsu_operator", "irlsu_precond", "irlsu_batch_create", "irlsu_batch_destroy",
+    "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
 )
 
@@ -140,6 +140,9 @@ def load_library():
         "irlsu_weights": (I32, [P, D, P, P, P, P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
+        "irlsu_precond_timed": (I32, [P, P, P, P, SZ, I32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(I32), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -316,6 +319,20 @@ class Plan:
                                       _ptr(self.workspace), self.workspace.numel(), _stream()),
                "precond")
         return z, rz
+
+    def precond_timed(self, r, reps=5):
+        """Per-launch HIP-event timing of reps preconditioner applications:
+        {"ms_products", "n_products", "ms_passes", "n_passes"} (summed)."""
+        import torch
+        z = torch.empty_like(r)
+        mp, mo = ctypes.c_double(), ctypes.c_double()
+        npr, npa = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.irlsu_precond_timed(self.handle, _ptr(r), _ptr(z), _ptr(self.workspace),
+                                            self.workspace.numel(), int(reps), ctypes.byref(mp),
+                                            ctypes.byref(npr), ctypes.byref(mo), ctypes.byref(npa),
+                                            _stream()), "precond_timed")
+        return {"ms_products": mp.value, "n_products": npr.value,
+                "ms_passes": mo.value, "n_passes": npa.value, "z": z}
 
 
 class Batch:

@@ -467,32 +467,41 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
   const int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
   GemmCtl c1{a.st, 1, a.check_conv, a.nparts_rr, f16, a.N * a.M};
   GemmCtl cn{a.st, 1, 0, 0, 0, 0};
+  LaunchLog* L = a.log;
+  log_start(L, s);
   // G1: T1^T = (r P_M)^T
-  gemm<OT, T>(r, Mp, PMt, Mp, Np, Mp, Mp, (float)a.scale, EpiStoreT<OT>{T1, Np}, c1, s);
+  gemm<OT, T>(r, Mp, PMt, Mp, Np, Mp, Mp, 1.0f, EpiStoreT<OT>{T1, Np}, c1, s);
+  log_mark(L, LC_PRODUCT, s);
   // G2: T2^T = (P_N^T T1)^T ./ lambda
   gemm<OT, OT>(T1, Np, PNt, Np, Mp, Np, Np, 1.0f,
                EpiScale<OT>{T2, Np, static_cast<const double*>(a.eigM),
                             static_cast<const double*>(a.eigN)},
                cn, s);
+  log_mark(L, LC_PRODUCT, s);
   // G3: T3 = (T2^T P_N^T)^T = P_N T2
   gemm<OT, OT>(T2, Np, PN, Np, Mp, Np, Np, 1.0f, EpiStoreT<OT>{T3, Mp}, cn, s);
+  log_mark(L, LC_PRODUCT, s);
   // G4: z = T3 P_M^T.  16-bit operands: the 256 x 256 tile stores z only and
   // a light pass forms z.r, z.q, sum z (the fused epilogue does not fit
   // beside that tile's registers); FP32 / FP64 fuse the sums.
   if constexpr (sizeof(OT) == 2) {
     gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
-                 EpiStoreZ<T>{static_cast<T*>(a.z), Mp, 1.0 / a.scale,
+                 EpiStoreZ<T>{static_cast<T*>(a.z), Mp, 1.0,
                               f16 ? a.st.sc + SC_SCALE : nullptr},
                  cn, s);
+    log_mark(L, LC_PRODUCT, s);
     const int nb = elementwise_blocks(Np * Mp);
     hipLaunchKernelGGL(zdots_kernel<T>, dim3(nb), dim3(kThreads), 0, s, static_cast<const T*>(a.z),
                        r, static_cast<const T*>(a.q), Np * Mp, a.st, 1);
+    log_mark(L, LC_PASS, s);
     return nb;
   } else {
-    return gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
-                        EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
-                                    1.0 / a.scale, nullptr},
-                        cn, s);
+    const int nb = gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
+                                EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
+                                            1.0, nullptr},
+                                cn, s);
+    log_mark(L, LC_PRODUCT, s);
+    return nb;
   }
 }
 
@@ -519,31 +528,49 @@ static int precond_folded_impl(const PrecondArgs& a, hipStream_t s) {
   const int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
   const int32_t* done = a.st.fl + FL_DONE;
   GemmCtl cn{a.st, 1, 0, 0, 0, 0};
+  LaunchLog* L = a.log;
+  auto prod = [&]() { log_mark(L, LC_PRODUCT, s); };
+  auto pass = [&]() { log_mark(L, LC_PASS, s); };
+  log_start(L, s);
   launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
+  pass();
   // S = [r_j + r_{M-1-j} | r_j - r_{M-1-j}]           (Np x wM)
   launch_fold_rows<T, OT>(r, Mp, M, N, Np, X1, hM, f16 ? a.st.sc + SC_SCALE : nullptr, done, s);
+  pass();
   // T1^T: even / odd column modes, transposed stores     (wM x Np)
   gemm<OT, OT>(X1, wM, PeMt, hM, Np, hM, hM, 1.0f, EpiStoreT<OT>{X2, Np}, cn, s);
+  prod();
   gemm<OT, OT>(X1 + hM, wM, PoMt, hM, Np, hM, hM, 1.0f, EpiStoreT<OT>{X2 + hM * Np, Np}, cn, s);
+  prod();
   // fold the rows index of T1^T                           (wM x wN)
   launch_fold_rows<OT, OT>(X2, Np, N, wM, wM, X1, hN, nullptr, done, s);
+  pass();
   // T2^T = (P_N^T T1)^T ./ lambda: even / odd row modes   (wM x wN)
   gemm<OT, OT>(X1, wN, PeNt, hN, wM, hN, hN, 1.0f, EpiScale<OT>{X2, wN, eM, eN, 1}, cn, s);
+  prod();
   gemm<OT, OT>(X1 + hN, wN, PoNt, hN, wM, hN, hN, 1.0f, EpiScale<OT>{X2 + hN, wN, eM, eN + hN, 0},
                cn, s);
+  prod();
   // inverse along rows: E and O stacked                   (wN x wM)
   gemm<OT, OT>(X2, wN, PeN, hN, wM, hN, hN, 1.0f, EpiStoreT<OT>{X1, wM}, cn, s);
+  prod();
   gemm<OT, OT>(X2 + hN, wN, PoN, hN, wM, hN, hN, 1.0f, EpiStoreT<OT>{X1 + hN * wM, wM}, cn, s);
+  prod();
   // T3 rows i, N-1-i = E +- O                              (Np x wM)
   launch_unfold_rows<OT>(X1, wM, N, hN, Np, X2, done, s);
+  pass();
   // inverse along columns: zE | zO                         (Np x wM, vector type)
   gemm<OT, OT>(X2, wM, PeM, hM, Np, hM, hM, 1.0f, EpiStoreZ<T>{ZEO, wM, 1.0, nullptr}, cn, s);
+  prod();
   gemm<OT, OT>(X2 + hM, wM, PoM, hM, Np, hM, hM, 1.0f, EpiStoreZ<T>{ZEO + hM, wM, 1.0, nullptr}, cn,
                s);
+  prod();
   // z = zE +- zO (undoing the FP16 scale), z.r, z.q, sum z
-  return launch_unfold_cols_dots<T>(ZEO, hM, N, M, Np, Mp, static_cast<T*>(a.z), r,
-                                    static_cast<const T*>(a.q), 1.0,
-                                    f16 ? a.st.sc + SC_SCALE : nullptr, a.st, s);
+  const int nb = launch_unfold_cols_dots<T>(ZEO, hM, N, M, Np, Mp, static_cast<T*>(a.z), r,
+                                            static_cast<const T*>(a.q), 1.0,
+                                            f16 ? a.st.sc + SC_SCALE : nullptr, a.st, s);
+  pass();
+  return nb;
 }
 
 int launch_precond(const PrecondArgs& a, hipStream_t s) {

@@ -176,7 +176,6 @@ PrecondArgs precond_args(const irlsu_plan* pl, const Ws<T>& W, const T* r, T* z,
   a.r = r;
   a.z = z;
   a.q = q;
-  a.scale = 1.0;
   a.check_conv = check_conv;
   a.nparts_rr = nparts_rr;
   a.st = W.st;
@@ -1074,6 +1073,66 @@ irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, doubl
     return IRLSU_OK;
   };
   st = plan->elem == 8 ? go(double{}) : go(float{});
+  if (st != IRLSU_OK) return st;
+  return last_launch();
+}
+
+irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z, void* workspace,
+                                 size_t workspace_bytes, int32_t reps, double* ms_products,
+                                 int32_t* n_products, double* ms_passes, int32_t* n_passes,
+                                 void* stream) {
+  if (!plan || !r || !z || r == z || reps < 1 || !ms_products || !n_products || !ms_passes ||
+      !n_passes)
+    return IRLSU_ERR_INVALID_ARG;
+  irlsu_status st = check_ws(plan, workspace, workspace_bytes);
+  if (st != IRLSU_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LaunchLog L;
+  int created = 0;
+  for (; created <= LaunchLog::kMax; ++created)
+    if (hipEventCreate(&L.ev[created]) != hipSuccess) break;
+  auto destroy = [&]() {
+    for (int i = 0; i < created; ++i) (void)hipEventDestroy(L.ev[i]);
+  };
+  if (created <= LaunchLog::kMax) {
+    destroy();
+    return IRLSU_ERR_HIP;
+  }
+  *ms_products = 0.0;
+  *ms_passes = 0.0;
+  *n_products = 0;
+  *n_passes = 0;
+  auto go = [&](auto tag) -> irlsu_status {
+    using T = decltype(tag);
+    const Ws<T> W = carve<T>(plan, workspace);
+    for (int rep = 0; rep < reps; ++rep) {
+      HIP_OK(hipMemsetAsync(W.st.fl, 0, FL_COUNT * sizeof(int32_t), s));
+      int nrr = 0;
+      if constexpr (sizeof(T) == 4) {
+        if (plan->kind == OK_F16)
+          nrr = launch_sumsq<float>(static_cast<const float*>(r), plan->Np * plan->Mp, W.st, s);
+      }
+      PrecondArgs a = precond_args<T>(plan, W, static_cast<const T*>(r), static_cast<T*>(z),
+                                      nullptr, 0, nrr);
+      a.log = &L;
+      launch_precond(a, s);
+      HIP_OK(hipEventSynchronize(L.ev[L.n]));
+      for (int i = 0; i < L.n; ++i) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, L.ev[i], L.ev[i + 1]));
+        if (L.cls[i] == LC_PRODUCT) {
+          *ms_products += ms;
+          ++*n_products;
+        } else {
+          *ms_passes += ms;
+          ++*n_passes;
+        }
+      }
+    }
+    return IRLSU_OK;
+  };
+  st = plan->elem == 8 ? go(double{}) : go(float{});
+  destroy();
   if (st != IRLSU_OK) return st;
   return last_launch();
 }

@@ -166,6 +166,29 @@ template <class T> void launch_adjoint_edges(const AdjEdgeArgs<T>& a, hipStream_
 // ---- DCT preconditioner (dense cosine-basis products on MFMA) ----------
 enum OperandKind : int { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2, OK_F16 = 3 };
 
+// Optional per-launch timing of one preconditioner application: an event
+// is recorded before the first launch and after every launch, each launch
+// tagged with its class (LC_PRODUCT: an MFMA product, LC_PASS: any other).
+enum LaunchClass : int { LC_PRODUCT = 0, LC_PASS = 1 };
+struct LaunchLog {
+  static constexpr int kMax = 32;
+  hipEvent_t ev[kMax + 1];
+  int cls[kMax];
+  int n = 0;
+};
+inline void log_start(LaunchLog* L, hipStream_t s) {
+  if (L) {
+    L->n = 0;
+    (void)hipEventRecord(L->ev[0], s);
+  }
+}
+inline void log_mark(LaunchLog* L, int cls, hipStream_t s) {
+  if (L && L->n < LaunchLog::kMax) {
+    L->cls[L->n] = cls;
+    (void)hipEventRecord(L->ev[++L->n], s);
+  }
+}
+
 struct PrecondArgs {
   int kind;                 // OperandKind
   int64_t N, M, Np, Mp;     // Mp == ld
@@ -176,7 +199,6 @@ struct PrecondArgs {
   const void* r;            // residual (T)
   void* z;                  // output (T)
   const void* q;            // nullable: previous A p for the flexible beta (T)
-  double scale;             // r is multiplied by scale on load, z by 1/scale
   int check_conv;           // first product checks ||r|| <= tol ||b|| and stops
   int nparts_rr;            // partials of ||r||^2 for the convergence check
   DevState st;
@@ -189,6 +211,7 @@ struct PrecondArgs {
   const void *PeM = nullptr, *PeMt = nullptr, *PoM = nullptr, *PoMt = nullptr;
   const void *eigNf = nullptr, *eigMf = nullptr;
   void* ZEO = nullptr;
+  LaunchLog* log = nullptr;   // nullable: per-launch events
 };
 // Returns the number of partials written by the last product (z.r etc.).
 int launch_precond(const PrecondArgs& a, hipStream_t s);
