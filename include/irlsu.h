@@ -110,16 +110,22 @@ typedef struct irlsu_plan_desc {
   size_t workspace_bytes; /* workspace needed by irlsu_unwrap and the step functions */
   size_t plan_bytes;      /* device memory owned by the plan (basis, eigenvalues) */
   int32_t folded;         /* 1: preconditioner in the folded (even/odd) form */
-  int32_t reserved_;
+  int32_t form;           /* IRLSU_PLAN_DENSE, _FOLDED or _FAST: the form in use */
 } irlsu_plan_desc;
 
 /* Form of the preconditioner products (irlsu_plan_create_ex). */
 enum {
-  IRLSU_PLAN_AUTO = 0,   /* folded when N, M are even and N M >= 2^20, else dense */
-  IRLSU_PLAN_DENSE = 1,  /* four dense products (Section 3.3 as written) */
-  IRLSU_PLAN_FOLDED = 2  /* reflection symmetry of the DCT-II basis: each product
+  IRLSU_PLAN_AUTO = 0,   /* fast when N, M are powers of two in [128, 16384];
+                            else folded when N, M are even and N M >= 2^20;
+                            else dense */
+  IRLSU_PLAN_DENSE = 1,  /* four dense MFMA products (Section 3.3 as written) */
+  IRLSU_PLAN_FOLDED = 2, /* reflection symmetry of the DCT-II basis: each product
                             splits into even / odd halves, half the MFMA work;
                             N and M must be even (else ERR_SHAPE) */
+  IRLSU_PLAN_FAST = 3    /* the same products by fast cosine transforms
+                            (half-length FFTs in LDS, FP32 arithmetic for FP32
+                            and mixed plans, FP64 for FP64 plans); N and M
+                            powers of two in [128, 16384] (else ERR_SHAPE) */
 };
 
 /* Human-readable name of a status code (static storage). */

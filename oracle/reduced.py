@@ -156,9 +156,13 @@ def weight_step(U, Gv, Gh, Cv, Ch, eps):
 # Preconditioner: eigendecomposition of the Neumann Laplacian (Section 3.3)
 # ----------------------------------------------------------------------------
 def laplacian_eigenvalues(n):
-    """Eigenvalues of S^T S (n x n): 2 - 2 cos(pi k / n), k = 0..n-1."""
+    """Eigenvalues of S^T S (n x n): 2 - 2 cos(pi k / n), k = 0..n-1
+    (Appendix A), evaluated as 4 sin^2(pi k / 2n) -- the same numbers by the
+    half-angle identity, without the cancellation of 2 - 2 cos near k = 0
+    (which would cost a relative error of about u / lambda_1 in the lowest
+    modes of the preconditioner)."""
     k = np.arange(n, dtype=np.float64)
-    return 2.0 - 2.0 * np.cos(math.pi * k / n)
+    return 4.0 * np.sin(math.pi * k / (2.0 * n)) ** 2
 
 
 def dct_basis(n):

@@ -95,11 +95,11 @@ class PlanDesc(ctypes.Structure):
                 ("Np", ctypes.c_int64), ("ld", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t), ("plan_bytes", ctypes.c_size_t),
-                ("folded", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("folded", ctypes.c_int32), ("form", ctypes.c_int32)]
 
 
 # form of the preconditioner products (irlsu_plan_create_ex)
-PLAN_FORMS = {"auto": 0, "dense": 1, "folded": 2}
+PLAN_FORMS = {"auto": 0, "dense": 1, "folded": 2, "fast": 3}
 
 
 _lib = None
@@ -198,6 +198,7 @@ class Plan:
             self.workspace = torch.empty(int(d.workspace_bytes), dtype=torch.uint8, device=self.device)
         self.N, self.M, self.Np, self.ld = d.N, d.M, d.Np, d.ld
         self.folded = bool(d.folded)
+        self.form = {v: k for k, v in PLAN_FORMS.items()}[d.form]
         self.dtype = torch.float64 if d.elem_bytes == 8 else torch.float32
 
     def close(self):

@@ -574,6 +574,7 @@ static int precond_folded_impl(const PrecondArgs& a, hipStream_t s) {
 }
 
 int launch_precond(const PrecondArgs& a, hipStream_t s) {
+  if (a.fast) return launch_precond_fast(a, s);
   if (a.folded) {
     switch (a.kind) {
       case OK_F64: return precond_folded_impl<double, double>(a, s);

@@ -1,0 +1,529 @@
+// Fast form of the preconditioner z = P_N [(P_N^T r P_M) ./ (lambda + mu)] P_M^T
+// (Section 3.3; mode (0,0) set to zero, Appendix B) for power-of-two sides:
+// the products with the orthonormal DCT-II basis are computed by fast
+// cosine transforms instead of dense contractions, O(log n) work per pixel
+// instead of O(n), which leaves the map bound by HBM traffic.
+//
+// One length-n DCT-II (n = 2h) of a row x:
+//   v[m] = x[2m], v[n-1-m] = x[2m+1]          (even samples up, odd down)
+//   w[m] = v[2m] + i v[2m+1]                  (v read as h complex numbers)
+//   W = FFT_h(w)                              (Stockham radix-16/8/4/2 in LDS)
+//   V_k = E_k + e^{-2 pi i k/n} O_k,  E_k = (W_k + conj W_{h-k}) / 2,
+//                                      O_k = (W_k - conj W_{h-k}) / (2i)
+//   c_k = e^{-i pi k/(2n)} V_k,  X_k = s_k Re c_k,  X_{n-k} = -s_{n-k} Im c_k
+// with s_0 = sqrt(1/n), s_k = sqrt(2/n) (orthonormal).  The DCT-III (the
+// transpose, i.e. the inverse) runs the same steps backwards, the inverse
+// FFT as conj(FFT(conj(.))) / h.
+//
+// Passes of one application (FP32 arithmetic for FP32 and mixed plans, FP64
+// for FP64 plans):
+//   rows_fwd      T1[i][l]  = DCT-II along each row of r
+//   transpose     T2 = T1^T
+//   cols_fused    T1[l][.]  = DCT-III( DCT-II(T2[l][.]) ./ (lambda_k + mu_l) )
+//   transpose     T2 = T1^T
+//   rows_inv      z[i][.]   = DCT-III along each row of T2; z.r, z.q, sum z
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace irlsu {
+
+template <class CT>
+struct Cx {
+  CT x, y;
+};
+
+template <class CT>
+__device__ __forceinline__ Cx<CT> cadd(Cx<CT> a, Cx<CT> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <class CT>
+__device__ __forceinline__ Cx<CT> csub(Cx<CT> a, Cx<CT> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <class CT>
+__device__ __forceinline__ Cx<CT> cmul(Cx<CT> a, Cx<CT> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <class CT>
+__device__ __forceinline__ Cx<CT> cmulc(Cx<CT> a, Cx<CT> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <class CT>
+__device__ __forceinline__ Cx<CT> conjg(Cx<CT> a) {
+  return {a.x, -a.y};
+}
+// -i a
+template <class CT>
+__device__ __forceinline__ Cx<CT> mul_mi(Cx<CT> a) {
+  return {a.y, -a.x};
+}
+// i a
+template <class CT>
+__device__ __forceinline__ Cx<CT> mul_i(Cx<CT> a) {
+  return {-a.y, a.x};
+}
+template <class CT>
+__device__ __forceinline__ Cx<CT> cscale(Cx<CT> a, CT s) {
+  return {a.x * s, a.y * s};
+}
+
+// ---- small forward DFTs in registers (natural order in and out) ----------
+template <class CT>
+__device__ __forceinline__ void dft4(Cx<CT>& a0, Cx<CT>& a1, Cx<CT>& a2, Cx<CT>& a3) {
+  const Cx<CT> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// e^{-2 pi i j / 16}, j = 0..9 (the twiddles of the 4 x 4 split)
+template <class CT>
+__device__ __forceinline__ Cx<CT> w16(int j) {
+  constexpr double c[10] = {1.0,
+                            0.92387953251128675613,
+                            0.70710678118654752440,
+                            0.38268343236508977173,
+                            0.0,
+                            -0.38268343236508977173,
+                            -0.70710678118654752440,
+                            -0.92387953251128675613,
+                            -1.0,
+                            -0.92387953251128675613};
+  constexpr double s[10] = {0.0,
+                            0.38268343236508977173,
+                            0.70710678118654752440,
+                            0.92387953251128675613,
+                            1.0,
+                            0.92387953251128675613,
+                            0.70710678118654752440,
+                            0.38268343236508977173,
+                            0.0,
+                            -0.38268343236508977173};
+  return {(CT)c[j], (CT)(-s[j])};
+}
+
+template <class CT, int R>
+__device__ __forceinline__ void dft(Cx<CT> (&a)[R]) {
+  if constexpr (R == 2) {
+    const Cx<CT> t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  } else if constexpr (R == 4) {
+    dft4(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    // n = 4 n1 + n2, k = k1 + 2 k2: length-2 DFTs over n1, twiddle
+    // e^{-2 pi i n2 k1 / 8}, length-4 DFTs over n2
+    Cx<CT> b0[4], b1[4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      b0[n2] = cadd(a[n2], a[4 + n2]);
+      b1[n2] = cmul(csub(a[n2], a[4 + n2]), w16<CT>(2 * n2));
+    }
+    dft4(b0[0], b0[1], b0[2], b0[3]);
+    dft4(b1[0], b1[1], b1[2], b1[3]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      a[2 * k2] = b0[k2];
+      a[1 + 2 * k2] = b1[k2];
+    }
+  } else {
+    static_assert(R == 16, "radix");
+    // n = 4 n1 + n2, k = k1 + 4 k2
+    Cx<CT> b[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      Cx<CT> c0 = a[n2], c1 = a[4 + n2], c2 = a[8 + n2], c3 = a[12 + n2];
+      dft4(c0, c1, c2, c3);
+      b[0][n2] = c0;
+      b[1][n2] = cmul(c1, w16<CT>(n2));
+      b[2][n2] = cmul(c2, w16<CT>(2 * n2));
+      b[3][n2] = cmul(c3, w16<CT>(3 * n2));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      dft4(b[k1][0], b[k1][1], b[k1][2], b[k1][3]);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = b[k1][k2];
+    }
+  }
+}
+
+// ---- Stockham FFT of ROWS rows of H complex points held in LDS ----------
+// Stage with span NS and radix R: butterfly j of a row reads points
+// j + r H/R, applies e^{-2 pi i r (j mod NS) / (NS R)}, and writes the
+// R-point DFT to (j / NS) NS R + (j mod NS) + r NS.  In place: every thread
+// holds its butterflies in registers across a barrier.
+template <class CT, int H, int ROWS, int R, int NS>
+__device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict__ tw) {
+  constexpr int BPR = H / R;
+  constexpr int NB = ROWS * BPR / kThreads;
+  static_assert(NB >= 1 && NB * kThreads == ROWS * BPR, "butterflies per thread");
+  Cx<CT> a[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int bi = threadIdx.x + b * kThreads;
+    const int row = bi / BPR, j = bi % BPR;
+    const int k = j % NS;
+    const Cx<CT>* src = buf + row * H + j;
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[b][r] = src[r * BPR];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], tw[r * k * (H / (NS * R))]);
+    }
+    dft<CT, R>(a[b]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int bi = threadIdx.x + b * kThreads;
+    const int row = bi / BPR, j = bi % BPR;
+    const int k = j % NS;
+    Cx<CT>* dst = buf + row * H + (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r * NS] = a[b][r];
+  }
+  __syncthreads();
+}
+
+template <class CT, int H, int ROWS, int NS = 1>
+__device__ __forceinline__ void fft_rows(Cx<CT>* buf, const Cx<CT>* __restrict__ tw) {
+  if constexpr (NS < H) {
+    constexpr int REM = H / NS;
+    constexpr int R = REM >= 16 ? 16 : REM;
+    fft_stage<CT, H, ROWS, R, NS>(buf, tw);
+    fft_rows<CT, H, ROWS, NS * R>(buf, tw);
+  }
+}
+
+// Rows per block: at least 4096 complex points per block so that every
+// stage has one butterfly per thread or more.
+template <int H>
+constexpr int rows_per_block() {
+  return H >= 4096 ? 1 : 4096 / H;
+}
+
+// Twiddle tables of one side n = 2h (complex, CT): [0, h) e^{-2 pi i j/h};
+// [h, 2h] e^{-2 pi i k/n}, k = 0..h; [2h+1, 3h+1] e^{-i pi k/(2n)}, k = 0..h.
+template <class CT>
+struct Tw {
+  const Cx<CT>* fft;
+  const Cx<CT>* tn;
+  const Cx<CT>* tq;
+};
+template <class CT, int H>
+__device__ __forceinline__ Tw<CT> tw_of(const void* p) {
+  const Cx<CT>* t = static_cast<const Cx<CT>*>(p);
+  return {t, t + H, t + 2 * H + 1};
+}
+
+// position of row element e in the even-up / odd-down sequence v
+template <int N>
+__device__ __forceinline__ int perm(int e) {
+  return (e & 1) ? N - 1 - (e >> 1) : (e >> 1);
+}
+
+// Forward post-processing of pair k (0 <= k <= h/2): c_k and c_{h-k} from
+// W_k and W_{h-k}.
+template <class CT, int H>
+__device__ __forceinline__ void post_pair(const Cx<CT>* W, int k, const Tw<CT>& tw, Cx<CT>& ck,
+                                          Cx<CT>& cp) {
+  const Cx<CT> wa = W[k & (H - 1)], wb = W[(H - k) & (H - 1)];
+  auto c_of = [&](int kk, Cx<CT> x, Cx<CT> y) {
+    const Cx<CT> E = cscale(cadd(x, conjg(y)), (CT)0.5);
+    const Cx<CT> O = cscale(mul_mi(csub(x, conjg(y))), (CT)0.5);
+    return cmul(tw.tq[kk], cadd(E, cmul(tw.tn[kk], O)));
+  };
+  ck = c_of(k, wa, wb);
+  cp = c_of(H - k, wb, wa);
+}
+
+// Inverse pre-processing of pair k: from c_k = Xt_k - i Xt_{n-k} and
+// c_{h-k}, the FFT inputs W_k, W_{h-k} (conjugated for the forward FFT).
+template <class CT, int H>
+__device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<CT>& tw, Cx<CT>* W) {
+  const Cx<CT> vk = cmulc(ck, tw.tq[k]);      // e^{+i pi k/(2n)} c_k
+  const Cx<CT> vp = cmulc(cp, tw.tq[H - k]);
+  const Cx<CT> Ek = cscale(cadd(vk, conjg(vp)), (CT)0.5);
+  const Cx<CT> Ok = cmulc(cscale(csub(vk, conjg(vp)), (CT)0.5), tw.tn[k]);
+  W[k & (H - 1)] = conjg(cadd(Ek, mul_i(Ok)));
+  if (k != H - k && k > 0) {
+    const Cx<CT> Ep = cscale(cadd(vp, conjg(vk)), (CT)0.5);
+    const Cx<CT> Op = cmulc(cscale(csub(vp, conjg(vk)), (CT)0.5), tw.tn[H - k]);
+    W[H - k] = conjg(cadd(Ep, mul_i(Op)));
+  }
+}
+
+// ---- pass 1: DCT-II along rows ------------------------------------------
+template <class CT, class TI, int H>
+__global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __restrict__ in,
+                                                               int64_t ld, CT* __restrict__ out,
+                                                               const void* twp,
+                                                               const int32_t* done) {
+  if (*done) return;
+  constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  __shared__ Cx<CT> buf[ROWS * H];
+  const Tw<CT> tw = tw_of<CT, H>(twp);
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  CT* v = reinterpret_cast<CT*>(buf);
+  for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
+    const int row = e / N, c = e % N;
+    v[row * N + perm<N>(c)] = (CT)in[(row0 + row) * ld + c];
+  }
+  __syncthreads();
+  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
+  constexpr int NP = H / 2 + 1;
+  for (int p = threadIdx.x; p < ROWS * NP; p += kThreads) {
+    const int row = p / NP, k = p % NP;
+    Cx<CT> ck, cp;
+    post_pair<CT, H>(buf + row * H, k, tw, ck, cp);
+    CT* o = out + (row0 + row) * ld;
+    o[k] = ck.x * (k == 0 ? s0 : s1);
+    if (k > 0) o[N - k] = -ck.y * s1;
+    if (H - k != k) {
+      o[H - k] = cp.x * s1;
+      if (k > 0) o[H + k] = -cp.y * s1;
+    }
+  }
+}
+
+// ---- pass 3: DCT-II, spectral division, DCT-III along rows of the
+// transposed intermediate (the columns of the image) ----------------------
+template <class CT, int H>
+__global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io, int64_t ld,
+                                                           const void* twp,
+                                                           const double* __restrict__ eig_k,
+                                                           const double* __restrict__ eig_l,
+                                                           const int32_t* done) {
+  if (*done) return;
+  constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  constexpr int NP = H / 2 + 1;
+  constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
+  __shared__ Cx<CT> buf[ROWS * H];
+  const Tw<CT> tw = tw_of<CT, H>(twp);
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  CT* v = reinterpret_cast<CT*>(buf);
+  for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
+    const int row = e / N, c = e % N;
+    v[row * N + perm<N>(c)] = io[(row0 + row) * ld + c];
+  }
+  __syncthreads();
+  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  // forward post-processing and division, held in registers: with
+  // d = 1 / (lambda_k + mu_l), the scaled coefficient divided by s_k is
+  // Re(c_k) d_k, and -Im(c_k) d_{n-k} for index n - k
+  Cx<CT> cks[PP], cps[PP];
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = threadIdx.x + q * kThreads;
+    if (p < ROWS * NP) {
+      const int row = p / NP, k = p % NP;
+      const int64_t l = row0 + row;
+      const double mu = eig_l[l];
+      auto d = [&](int kk) -> CT {
+        return (l == 0 && kk == 0) ? (CT)0 : (CT)(1.0 / (eig_k[kk] + mu));
+      };
+      Cx<CT> ck, cp;
+      post_pair<CT, H>(buf + row * H, k, tw, ck, cp);
+      // X~ at k, n-k, h-k, h+k; c_k (inverse) = X~_k - i X~_{n-k}
+      const CT xk = ck.x * d(k);
+      const CT xnk = k > 0 ? -ck.y * d(N - k) : (CT)0;
+      const CT xp = cp.x * d(H - k);
+      const CT xnp = -cp.y * d(H + k);   // k = 0: index h, equal to xp
+      cks[q] = {xk, -xnk};
+      cps[q] = {xp, -xnp};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = threadIdx.x + q * kThreads;
+    if (p < ROWS * NP) {
+      const int row = p / NP, k = p % NP;
+      pre_pair<CT, H>(cks[q], cps[q], k, tw, buf + row * H);
+    }
+  }
+  __syncthreads();
+  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  const CT inv_h = (CT)(1.0 / H);
+  for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
+    const int row = e / N, c = e % N;
+    const int m = perm<N>(c);
+    // w = conj(FFT(conj W)) / h: v[2m] = Re, v[2m+1] = Im of w
+    const CT val = (m & 1) ? -v[row * N + m] : v[row * N + m];
+    io[(row0 + row) * ld + c] = val * inv_h;
+  }
+}
+
+// ---- pass 5: DCT-III along rows, z.r, z.q, sum z -------------------------
+template <class CT, class TO, int H>
+__global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
+    const CT* __restrict__ in, int64_t ld, int64_t nrows, TO* __restrict__ z,
+    const TO* __restrict__ r, const TO* __restrict__ q, const void* twp, DevState st) {
+  if (st.fl[FL_DONE]) return;
+  constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  constexpr int NP = H / 2 + 1;
+  __shared__ Cx<CT> buf[ROWS * H];
+  const Tw<CT> tw = tw_of<CT, H>(twp);
+  CT* v = reinterpret_cast<CT*>(buf);
+  const CT inv_h = (CT)(1.0 / H);
+  const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int64_t ngroups = nrows / ROWS;
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int64_t row0 = g * ROWS;
+    for (int p = threadIdx.x; p < ROWS * NP; p += kThreads) {
+      const int row = p / NP, k = p % NP;
+      const CT* x = in + (row0 + row) * ld;
+      const CT xk = x[k] * (k == 0 ? is0 : is1);
+      const CT xnk = k > 0 ? x[N - k] * is1 : (CT)0;
+      const CT xp = x[H - k] * is1;
+      const CT xnp = x[H + k] * is1;
+      pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf + row * H);
+    }
+    __syncthreads();
+    fft_rows<CT, H, ROWS>(buf, tw.fft);
+    for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
+      const int row = e / N, c = e % N;
+      const int m = perm<N>(c);
+      const CT val = ((m & 1) ? -v[row * N + m] : v[row * N + m]) * inv_h;
+      const int64_t o = (row0 + row) * ld + c;
+      const TO zt = (TO)val;
+      z[o] = zt;
+      const double zd = (double)zt;
+      acc[0] += zd * (double)r[o];
+      if (q) acc[1] += zd * (double)q[o];
+      acc[2] += zd;
+    }
+    __syncthreads();
+  }
+  const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
+  write_partials<3>(st, slots, acc, (int)blockIdx.x);
+}
+
+// ---- transpose (64 x 64 tiles through LDS) -------------------------------
+template <class T>
+__global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, int64_t ldin,
+                                                            T* __restrict__ out, int64_t ldout,
+                                                            const int32_t* done) {
+  if (*done) return;
+  __shared__ T tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = ty; i < 64; i += 4) tile[i][tx] = in[(r0 + i) * ldin + c0 + tx];
+  __syncthreads();
+#pragma unroll
+  for (int i = ty; i < 64; i += 4) out[(c0 + i) * ldout + r0 + tx] = tile[tx][i];
+}
+
+// ---- tables -----------------------------------------------------------------
+template <class CT>
+__global__ __launch_bounds__(kThreads) void fct_tables_kernel(int64_t n, Cx<CT>* tw, double* eig) {
+  const int64_t h = n / 2;
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double s, c;
+  if (j < h) {
+    sincospi(2.0 * (double)j / (double)h, &s, &c);
+    tw[j] = {(CT)c, (CT)(-s)};
+  }
+  if (j <= h) {
+    sincospi(2.0 * (double)j / (double)n, &s, &c);
+    tw[h + j] = {(CT)c, (CT)(-s)};
+    sincospi(0.5 * (double)j / (double)n, &s, &c);
+    tw[2 * h + 1 + j] = {(CT)c, (CT)(-s)};
+  }
+  if (j < n) {
+    const double sv = sinpi(0.5 * (double)j / (double)n);
+    eig[j] = 4.0 * sv * sv;
+  }
+}
+
+size_t fct_table_bytes(int64_t n, int elem) {
+  return (size_t)(3 * (n / 2) + 2) * 2 * (size_t)elem;
+}
+
+void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s) {
+  const int nb = (int)((n + kThreads - 1) / kThreads);
+  if (elem == 8)
+    hipLaunchKernelGGL(fct_tables_kernel<double>, dim3(nb), dim3(kThreads), 0, s, n,
+                       static_cast<Cx<double>*>(tw), eig);
+  else
+    hipLaunchKernelGGL(fct_tables_kernel<float>, dim3(nb), dim3(kThreads), 0, s, n,
+                       static_cast<Cx<float>*>(tw), eig);
+}
+
+bool fct_supported(int64_t n) {
+  return n >= 128 && n <= 16384 && (n & (n - 1)) == 0;
+}
+
+// ---- one application -----------------------------------------------------
+template <class F>
+static void with_h(int64_t h, F&& f) {
+  switch (h) {
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    case 1024: f(std::integral_constant<int, 1024>{}); break;
+    case 2048: f(std::integral_constant<int, 2048>{}); break;
+    case 4096: f(std::integral_constant<int, 4096>{}); break;
+    case 8192: f(std::integral_constant<int, 8192>{}); break;
+    default: break;
+  }
+}
+
+template <class CT>
+static int fast_impl(const PrecondArgs& a, hipStream_t s) {
+  const int64_t N = a.N, M = a.M;
+  const CT* r = static_cast<const CT*>(a.r);
+  CT* z = static_cast<CT*>(a.z);
+  const CT* q = static_cast<const CT*>(a.q);
+  CT* T1 = static_cast<CT*>(a.T1);
+  CT* T2 = static_cast<CT*>(a.T2);
+  const int32_t* done = a.st.fl + FL_DONE;
+  LaunchLog* L = a.log;
+  log_start(L, s);
+  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, 0, N * M, s);
+  log_mark(L, LC_PASS, s);
+  with_h(M / 2, [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, CT, H>), dim3((unsigned)(N / rows_per_block<H>())),
+                       dim3(kThreads), 0, s, r, M, T1, a.twM, done);
+  });
+  log_mark(L, LC_PASS, s);
+  hipLaunchKernelGGL(transpose_kernel<CT>, dim3((unsigned)(M / 64), (unsigned)(N / 64)),
+                     dim3(kThreads), 0, s, T1, M, T2, N, done);
+  log_mark(L, LC_PASS, s);
+  with_h(N / 2, [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    hipLaunchKernelGGL((fct_cols_kernel<CT, H>), dim3((unsigned)(M / rows_per_block<H>())),
+                       dim3(kThreads), 0, s, T2, N, a.twN, static_cast<const double*>(a.eigN),
+                       static_cast<const double*>(a.eigM), done);
+  });
+  log_mark(L, LC_PASS, s);
+  hipLaunchKernelGGL(transpose_kernel<CT>, dim3((unsigned)(N / 64), (unsigned)(M / 64)),
+                     dim3(kThreads), 0, s, T2, N, T1, M, done);
+  log_mark(L, LC_PASS, s);
+  int nb = 0;
+  with_h(M / 2, [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    const int64_t ngroups = N / rows_per_block<H>();
+    nb = (int)(ngroups < 1024 ? ngroups : 1024);
+    hipLaunchKernelGGL((fct_rows_inv_kernel<CT, CT, H>), dim3((unsigned)nb), dim3(kThreads), 0, s,
+                       T1, M, N, z, r, q, a.twM, a.st);
+  });
+  log_mark(L, LC_PASS, s);
+  return nb;
+}
+
+int launch_precond_fast(const PrecondArgs& a, hipStream_t s) {
+  if (a.kind == OK_F64) return fast_impl<double>(a, s);
+  return fast_impl<float>(a, s);
+}
+
+}  // namespace irlsu

@@ -38,6 +38,9 @@ struct irlsu_plan {
   int32_t* h_flags = nullptr;   // pinned
   double* h_sc = nullptr;       // pinned
   int device = 0;
+  // fast preconditioner (power-of-two N and M): twiddle tables
+  int fast = 0;
+  void *twN = nullptr, *twM = nullptr;
   // folded preconditioner (even N and M)
   int folded = 0;
   int64_t hNp = 0, hMp = 0;
@@ -96,13 +99,15 @@ Layout layout(const irlsu_plan* p) {
   }
   // preconditioner intermediates: dense form Np x Mp each; folded form two
   // ping-pong buffers of 2 hNp x 2 hMp and an Np x 2 hMp vector-type buffer
+  // (fast form: two N x M buffers of the vector type)
   const size_t inter = p->folded ? (size_t)(2 * p->hNp) * (size_t)(2 * p->hMp) : npx;
+  const size_t isz = p->fast ? p->elem : p->opsz;
   L.t1 = off;
-  off = align_up(off + inter * p->opsz);
+  off = align_up(off + inter * isz);
   L.t2 = off;
-  off = align_up(off + inter * p->opsz);
+  off = align_up(off + inter * isz);
   L.t3 = off;
-  off = align_up(off + (p->folded ? 0 : npx) * p->opsz);
+  off = align_up(off + ((p->folded || p->fast) ? 0 : npx) * p->opsz);
   L.zeo = off;
   off = align_up(off + (p->folded ? (size_t)p->Np * (size_t)(2 * p->hMp) : 0) * p->elem);
   L.part = off;
@@ -193,6 +198,9 @@ PrecondArgs precond_args(const irlsu_plan* pl, const Ws<T>& W, const T* r, T* z,
   a.eigNf = pl->eigNf;
   a.eigMf = pl->eigMf;
   a.ZEO = W.ZEO;
+  a.fast = pl->fast;
+  a.twN = pl->twN;
+  a.twM = pl->twM;
   return a;
 }
 
@@ -771,10 +779,12 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
   *out = nullptr;
   if (N < 2 || M < 2) return IRLSU_ERR_SHAPE;
   if (prec < IRLSU_F64 || prec > IRLSU_MIXED_F16) return IRLSU_ERR_UNSUPPORTED;
-  if (form < IRLSU_PLAN_AUTO || form > IRLSU_PLAN_FOLDED) return IRLSU_ERR_INVALID_ARG;
+  if (form < IRLSU_PLAN_AUTO || form > IRLSU_PLAN_FAST) return IRLSU_ERR_INVALID_ARG;
   if (N > kMaxSide || M > kMaxSide) return IRLSU_ERR_SHAPE;
   const bool even = (N % 2 == 0) && (M % 2 == 0);
   if (form == IRLSU_PLAN_FOLDED && !even) return IRLSU_ERR_SHAPE;
+  const bool pow2 = fct_supported(N) && fct_supported(M);
+  if (form == IRLSU_PLAN_FAST && !pow2) return IRLSU_ERR_SHAPE;
   irlsu_plan* p = new (std::nothrow) irlsu_plan;
   if (!p) return IRLSU_ERR_OOM;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -789,9 +799,11 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     case IRLSU_MIXED_BF16: p->kind = OK_BF16; p->elem = 4; p->opsz = 2; break;
     case IRLSU_MIXED_F16: p->kind = OK_F16; p->elem = 4; p->opsz = 2; break;
   }
-  // the folded form pays off once the products dominate the extra passes
-  p->folded = form == IRLSU_PLAN_FOLDED ||
-              (form == IRLSU_PLAN_AUTO && even && p->Np * p->Mp >= ((int64_t)1 << 20));
+  // the fast form wherever it applies; else the folded form once the
+  // products dominate its extra passes
+  p->fast = form == IRLSU_PLAN_FAST || (form == IRLSU_PLAN_AUTO && pow2);
+  p->folded = !p->fast && (form == IRLSU_PLAN_FOLDED ||
+                           (form == IRLSU_PLAN_AUTO && even && p->Np * p->Mp >= ((int64_t)1 << 20)));
   p->hNp = round_up(N / 2, kTilePad);
   p->hMp = round_up(M / 2, kTilePad);
   // the GEMM grids and the partial-sum table bound the supported size
@@ -802,7 +814,20 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
   }
   (void)hipGetDevice(&p->device);
   bool ok = true;
-  if (p->folded) {
+  if (p->fast) {
+    const bool share = (N == M);
+    const size_t bN = fct_table_bytes(N, p->elem), bM = fct_table_bytes(M, p->elem);
+    ok = hipMalloc(&p->twN, bN) == hipSuccess &&
+         hipMalloc(reinterpret_cast<void**>(&p->eigN), N * sizeof(double)) == hipSuccess;
+    if (ok && !share)
+      ok = hipMalloc(&p->twM, bM) == hipSuccess &&
+           hipMalloc(reinterpret_cast<void**>(&p->eigM), M * sizeof(double)) == hipSuccess;
+    if (ok && share) {
+      p->twM = p->twN;
+      p->eigM = p->eigN;
+    }
+    p->plan_bytes = bN + N * sizeof(double) + (share ? 0 : bM + M * sizeof(double));
+  } else if (p->folded) {
     const bool share = (N == M);
     const size_t bN = (size_t)p->hNp * p->hNp * p->opsz;
     const size_t bM = (size_t)p->hMp * p->hMp * p->opsz;
@@ -847,7 +872,10 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     irlsu_plan_destroy(p);
     return IRLSU_ERR_OOM;
   }
-  if (p->folded) {
+  if (p->fast) {
+    launch_fct_tables(p->elem, N, p->twN, p->eigN, s);
+    if (p->twM != p->twN) launch_fct_tables(p->elem, M, p->twM, p->eigM, s);
+  } else if (p->folded) {
     launch_fold_basis(p->kind, N, p->hNp, p->PeN, p->PeNt, p->PoN, p->PoNt, p->eigNf, s);
     if (p->PeM != p->PeN)
       launch_fold_basis(p->kind, M, p->hMp, p->PeM, p->PeMt, p->PoM, p->PoMt, p->eigMf, s);
@@ -871,15 +899,17 @@ irlsu_status irlsu_plan_destroy(irlsu_plan* p) {
   void* fold_m[] = {p->PeM, p->PeMt, p->PoM, p->PoMt, p->eigMf};
   for (void* q : fold_n) if (q) (void)hipFree(q);
   if (!fshare) for (void* q : fold_m) if (q) (void)hipFree(q);
+  if (p->twN) (void)hipFree(p->twN);
+  if (p->twM && p->twM != p->twN) (void)hipFree(p->twM);
   const bool share = p->PM == p->PN;
   if (p->PN) (void)hipFree(p->PN);
   if (p->PNt) (void)hipFree(p->PNt);
-  if (p->eigN) (void)hipFree(p->eigN);
   if (!share) {
     if (p->PM) (void)hipFree(p->PM);
     if (p->PMt) (void)hipFree(p->PMt);
-    if (p->eigM) (void)hipFree(p->eigM);
   }
+  if (p->eigN) (void)hipFree(p->eigN);
+  if (p->eigM && p->eigM != p->eigN) (void)hipFree(p->eigM);
   if (p->h_flags) (void)hipHostFree(p->h_flags);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
   delete p;
@@ -897,6 +927,7 @@ irlsu_status irlsu_plan_info(const irlsu_plan* p, irlsu_plan_desc* out) {
   out->workspace_bytes = p->ws_bytes;
   out->plan_bytes = p->plan_bytes;
   out->folded = p->folded;
+  out->form = p->fast ? IRLSU_PLAN_FAST : (p->folded ? IRLSU_PLAN_FOLDED : IRLSU_PLAN_DENSE);
   return IRLSU_OK;
 }
 

@@ -211,8 +211,18 @@ struct PrecondArgs {
   const void *PeM = nullptr, *PeMt = nullptr, *PoM = nullptr, *PoMt = nullptr;
   const void *eigNf = nullptr, *eigMf = nullptr;
   void* ZEO = nullptr;
+  // fast form (power-of-two sides): twiddle tables per side; eigN / eigM
+  // are then unpadded natural-order tables; T1, T2 hold N x M vector-type
+  // elements each
+  int fast = 0;
+  const void* twN = nullptr;
+  const void* twM = nullptr;
   LaunchLog* log = nullptr;   // nullable: per-launch events
 };
+int launch_precond_fast(const PrecondArgs& a, hipStream_t s);
+bool fct_supported(int64_t n);
+size_t fct_table_bytes(int64_t n, int elem);
+void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s);
 // Returns the number of partials written by the last product (z.r etc.).
 int launch_precond(const PrecondArgs& a, hipStream_t s);
 // Grouped preconditioner over the tiles of a batch (operand kind of the

@@ -153,7 +153,7 @@ def test_precond_matches_dct_oracle(prec, shape):
     dt = npdt(prec)
     rng = np.random.default_rng(5)
     r = rng.standard_normal((N, M)).astype(dt)
-    plan = pkg.Plan(N, M, prec)
+    plan = pkg.Plan(N, M, prec, form="dense")
     z, rz = plan.precond(internal(plan, r))
     torch.cuda.synchronize()
     z_o = R.apply_precond(r.astype(np.float64))
@@ -173,7 +173,7 @@ def test_precond_big_tiles(p16, shape):
     N, M = shape
     rng = np.random.default_rng(7)
     r = rng.standard_normal((N, M)).astype(np.float32)
-    plan = pkg.Plan(N, M, p16)
+    plan = pkg.Plan(N, M, p16, form="dense")
     z, rz = plan.precond(internal(plan, r))
     torch.cuda.synchronize()
     z_o = R.apply_precond(r.astype(np.float64))
@@ -226,13 +226,57 @@ def test_precond_folded_is_pseudo_inverse_property_f64():
     plan.close()
 
 
+# powers of two: the fast (cosine-transform) form; one and several rows per
+# block, square and both orientations of rectangles
+FAST_SHAPES = [(128, 128), (128, 512), (1024, 256), (256, 4096)]
+FAST_RTOL = {"f64": 1e-13, "f32": 2e-6, "bf16": 2e-6, "f16": 2e-6}
+
+
+@pytest.mark.parametrize("shape", FAST_SHAPES)
+@pytest.mark.parametrize("fprec", ["f64", "f32", "bf16", "f16"])
+def test_precond_fast_matches_dct_oracle(fprec, shape):
+    """The fast form computes in FP32 for FP32 and mixed plans (FP64 for
+    FP64): a handful of roundings per transform, so the relative error is a
+    small multiple of the unit roundoff times log2 n."""
+    N, M = shape
+    dt = npdt(fprec)
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal((N, M)).astype(dt)
+    plan = pkg.Plan(N, M, fprec, form="fast")
+    assert plan.form == "fast"
+    z, rz = plan.precond(internal(plan, r))
+    torch.cuda.synchronize()
+    z_o = R.apply_precond(r.astype(np.float64))
+    zg = z.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
+    print(f"precond fast {fprec} {shape}: rel err {rel:.3e}")
+    assert rel <= FAST_RTOL[fprec]
+    ref = float(np.sum(r.astype(np.float64) * z_o))
+    assert abs(rz.item() - ref) <= 2 * FAST_RTOL[fprec] * abs(ref)
+    plan.close()
+
+
+def test_precond_fast_is_pseudo_inverse_property_f64():
+    """The fast form solves the Neumann problem: L z = r - mean(r)."""
+    N, M = 512, 256
+    rng = np.random.default_rng(10)
+    r = rng.standard_normal((N, M))
+    plan = pkg.Plan(N, M, "f64", form="fast")
+    z, _ = plan.precond(internal(plan, r))
+    zg = z.cpu().numpy()[:N, :M]
+    Lz = R.apply_A(np.ones((N - 1, M)), np.ones((N, M - 1)), zg)
+    assert np.abs(Lz - (r - r.mean())).max() < 1e-10
+    assert abs(zg.mean()) < 1e-12
+    plan.close()
+
+
 def test_precond_is_pseudo_inverse_property_f64():
     """L z = r - mean(r) with L the unweighted Neumann Laplacian (applied by
     the oracle's plain stencil), at a size with several GEMM tiles."""
     N, M = 384, 200
     rng = np.random.default_rng(6)
     r = rng.standard_normal((N, M))
-    plan = pkg.Plan(N, M, "f64")
+    plan = pkg.Plan(N, M, "f64", form="dense")
     z, _ = plan.precond(internal(plan, r))
     zg = z.cpu().numpy()[:N, :M]
     Lz = R.apply_A(np.ones((N - 1, M)), np.ones((N, M - 1)), zg)

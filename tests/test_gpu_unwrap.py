@@ -107,6 +107,21 @@ def test_folded_plan_objective(prec):
         assert np.abs(Ug - Uo).max() < 1e-6
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_fast_plan_objective(prec):
+    """The whole path with the fast (cosine-transform) preconditioner on a
+    rectangular power-of-two c3 residue field."""
+    f = synth.field_c3(5, 256, 128)
+    tol = 1e-10 if prec == "f64" else 1e-6
+    Ug, st, Uo, hist = run_both(f, prec, iters=5, maxit=3000, tol=tol, form="fast")
+    gap = abs(st["L1_final"] - hist[-1]["L1"]) / hist[-1]["L1"]
+    print(f"fast {prec}: GPU L1 {st['L1_final']:.10g} oracle {hist[-1]['L1']:.10g} gap {gap:.2e}")
+    assert gap <= L1_RTOL[prec]
+    assert abs(Ug.mean()) < (1e-12 if prec == "f64" else 1e-5)
+    if prec == "f64":
+        assert np.abs(Ug - Uo).max() < 1e-6
+
+
 def test_two_by_two_single_loop_closed_form():
     g = json.load(open(os.path.join(GOLDEN, "loop2x2.json")))
     X = torch.tensor(g["X"], dtype=torch.float64, device="cuda")

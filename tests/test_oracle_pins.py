@@ -90,6 +90,24 @@ def residue_count(X):
 # ---------------------------------------------------------------------------
 # Problem data
 # ---------------------------------------------------------------------------
+def test_eigenvalues_equal_printed_form_in_extended_precision():
+    """Appendix A's eigenvalues 2 - 2 cos(pi k / n), evaluated at 50 digits
+    (no cancellation left at that precision), equal the oracle's FP64 values
+    to a few ulps for every k, the lowest modes included."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    for n in (2, 3, 64, 1000, 8192):
+        lam = R.laplacian_eigenvalues(n)
+        assert lam[0] == 0.0
+        ks = sorted(set([1, 2, 3, n // 2, n - 1] + list(range(1, min(n, 40)))))
+        for k in ks:
+            if k < 1 or k >= n:
+                continue
+            exact = 2 - 2 * mpmath.cos(mpmath.pi * k / n)
+            rel = abs(float((mpmath.mpf(float(lam[k])) - exact) / exact))
+            assert rel < 5e-16 * 8, (n, k, rel)
+
+
 def test_wrap_is_symmetric_residue():
     x = np.array([0.0, PI, -PI, 1.5 * PI, -1.5 * PI, 7.0, -7.0, 2 * PI, 1e-17, 100.0])
     w = R.wrap(x)
