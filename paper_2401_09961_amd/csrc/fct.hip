@@ -152,6 +152,40 @@ __device__ __forceinline__ void dft(Cx<CT> (&a)[R]) {
 }
 
 // ---- Stockham FFT of ROWS rows of H complex points held in LDS ----------
+// LDS holds complex point x at slot pc(x) = x + x / 16: one pad slot per 16
+// points keeps the stride-16 writes of the first stages (and the strided
+// reads of the last) off a single bank.
+__device__ __forceinline__ int pc(int x) { return x + (x >> 4); }
+template <int NPTS>
+constexpr int padded() {
+  return NPTS + NPTS / 16;
+}
+// real element e of the block's rows (two per complex slot)
+__device__ __forceinline__ int pr(int e) { return 2 * pc(e >> 1) + (e & 1); }
+
+// Twiddles w^r, w = e^{-2 pi i step / H}, r = 1..R-1: w, w^2, w^4, w^8 from
+// the table, the others as products of two of them (at most three
+// roundings each).
+template <class CT, int R>
+__device__ __forceinline__ void twiddles(const Cx<CT>* __restrict__ tw, int step, Cx<CT> (&w)[R]) {
+  w[1] = tw[step];
+  if constexpr (R > 2) {
+    w[2] = tw[2 * step];
+    w[3] = cmul(w[1], w[2]);
+  }
+  if constexpr (R > 4) {
+    w[4] = tw[4 * step];
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+  }
+  if constexpr (R > 8) {
+    w[8] = tw[8 * step];
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+  }
+}
+
 // Stage with span NS and radix R: butterfly j of a row reads points
 // j + r H/R, applies e^{-2 pi i r (j mod NS) / (NS R)}, and writes the
 // R-point DFT to (j / NS) NS R + (j mod NS) + r NS.  In place: every thread
@@ -167,12 +201,14 @@ __device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict_
     const int bi = threadIdx.x + b * kThreads;
     const int row = bi / BPR, j = bi % BPR;
     const int k = j % NS;
-    const Cx<CT>* src = buf + row * H + j;
+    const int src = row * H + j;
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[b][r] = src[r * BPR];
+    for (int r = 0; r < R; ++r) a[b][r] = buf[pc(src + r * BPR)];
     if constexpr (NS > 1) {
+      Cx<CT> w[R];
+      twiddles<CT, R>(tw, k * (H / (NS * R)), w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], tw[r * k * (H / (NS * R))]);
+      for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], w[r]);
     }
     dft<CT, R>(a[b]);
   }
@@ -182,9 +218,9 @@ __device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict_
     const int bi = threadIdx.x + b * kThreads;
     const int row = bi / BPR, j = bi % BPR;
     const int k = j % NS;
-    Cx<CT>* dst = buf + row * H + (j / NS) * NS * R + k;
+    const int dst = row * H + (j / NS) * NS * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[r * NS] = a[b][r];
+    for (int r = 0; r < R; ++r) buf[pc(dst + r * NS)] = a[b][r];
   }
   __syncthreads();
 }
@@ -229,9 +265,9 @@ __device__ __forceinline__ int perm(int e) {
 // Forward post-processing of pair k (0 <= k <= h/2): c_k and c_{h-k} from
 // W_k and W_{h-k}.
 template <class CT, int H>
-__device__ __forceinline__ void post_pair(const Cx<CT>* W, int k, const Tw<CT>& tw, Cx<CT>& ck,
-                                          Cx<CT>& cp) {
-  const Cx<CT> wa = W[k & (H - 1)], wb = W[(H - k) & (H - 1)];
+__device__ __forceinline__ void post_pair(const Cx<CT>* buf, int base, int k, const Tw<CT>& tw,
+                                          Cx<CT>& ck, Cx<CT>& cp) {
+  const Cx<CT> wa = buf[pc(base + (k & (H - 1)))], wb = buf[pc(base + ((H - k) & (H - 1)))];
   auto c_of = [&](int kk, Cx<CT> x, Cx<CT> y) {
     const Cx<CT> E = cscale(cadd(x, conjg(y)), (CT)0.5);
     const Cx<CT> O = cscale(mul_mi(csub(x, conjg(y))), (CT)0.5);
@@ -244,17 +280,62 @@ __device__ __forceinline__ void post_pair(const Cx<CT>* W, int k, const Tw<CT>& 
 // Inverse pre-processing of pair k: from c_k = Xt_k - i Xt_{n-k} and
 // c_{h-k}, the FFT inputs W_k, W_{h-k} (conjugated for the forward FFT).
 template <class CT, int H>
-__device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<CT>& tw, Cx<CT>* W) {
+__device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<CT>& tw, Cx<CT>* buf,
+                                         int base) {
   const Cx<CT> vk = cmulc(ck, tw.tq[k]);      // e^{+i pi k/(2n)} c_k
   const Cx<CT> vp = cmulc(cp, tw.tq[H - k]);
   const Cx<CT> Ek = cscale(cadd(vk, conjg(vp)), (CT)0.5);
   const Cx<CT> Ok = cmulc(cscale(csub(vk, conjg(vp)), (CT)0.5), tw.tn[k]);
-  W[k & (H - 1)] = conjg(cadd(Ek, mul_i(Ok)));
+  buf[pc(base + (k & (H - 1)))] = conjg(cadd(Ek, mul_i(Ok)));
   if (k != H - k && k > 0) {
     const Cx<CT> Ep = cscale(cadd(vp, conjg(vk)), (CT)0.5);
     const Cx<CT> Op = cmulc(cscale(csub(vp, conjg(vk)), (CT)0.5), tw.tn[H - k]);
-    W[H - k] = conjg(cadd(Ep, mul_i(Op)));
+    buf[pc(base + H - k)] = conjg(cadd(Ep, mul_i(Op)));
   }
+}
+
+// ---- row staging ----------------------------------------------------------
+// Every thread moves whole 16-byte chunks of the block's rows; all of a
+// thread's global loads are issued before the first LDS write, so a block
+// waits for memory once per pass rather than once per element.
+template <class T>
+struct Vec16 {
+  static constexpr int W = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+// LDS <- rows (even-up / odd-down order), as CT
+template <class CT, class TI, int H>
+__device__ __forceinline__ void stage_in(const TI* __restrict__ in, int64_t ld, int64_t row0,
+                                         CT* v) {
+  constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  using V = typename Vec16<TI>::type;
+  constexpr int W = Vec16<TI>::W;
+  constexpr int NCH = ROWS * N / W / kThreads;
+  static_assert(NCH * W * kThreads == ROWS * N, "chunks per thread");
+  V d[NCH];
+#pragma unroll
+  for (int i = 0; i < NCH; ++i) {
+    const int e0 = (threadIdx.x + i * kThreads) * W;
+    const int row = e0 / N, c = e0 % N;
+    d[i] = *reinterpret_cast<const V*>(in + (row0 + row) * ld + c);
+  }
+#pragma unroll
+  for (int i = 0; i < NCH; ++i) {
+    const int e0 = (threadIdx.x + i * kThreads) * W;
+    const int row = e0 / N, c = e0 % N;
+#pragma unroll
+    for (int t = 0; t < W; ++t) v[pr(row * N + perm<N>(c + t))] = (CT)d[i][t];
+  }
+}
+
+// value of output element c of a row after the inverse FFT:
+// w = conj(FFT(conj W)) / h, v[2m] = Re w[m], v[2m+1] = Im w[m]
+template <class CT, int N>
+__device__ __forceinline__ CT inv_value(const CT* v, int row, int c, CT inv_h) {
+  const int m = perm<N>(c);
+  const CT x = v[pr(row * N + m)];
+  return ((m & 1) ? -x : x) * inv_h;
 }
 
 // ---- pass 1: DCT-II along rows ------------------------------------------
@@ -265,28 +346,30 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
                                                                const int32_t* done) {
   if (*done) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
-  __shared__ Cx<CT> buf[ROWS * H];
+  constexpr int NP = H / 2 + 1;
+  constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
+  __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
-    const int row = e / N, c = e % N;
-    v[row * N + perm<N>(c)] = (CT)in[(row0 + row) * ld + c];
-  }
+  stage_in<CT, TI, H>(in, ld, row0, v);
   __syncthreads();
   fft_rows<CT, H, ROWS>(buf, tw.fft);
   const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
-  constexpr int NP = H / 2 + 1;
-  for (int p = threadIdx.x; p < ROWS * NP; p += kThreads) {
-    const int row = p / NP, k = p % NP;
-    Cx<CT> ck, cp;
-    post_pair<CT, H>(buf + row * H, k, tw, ck, cp);
-    CT* o = out + (row0 + row) * ld;
-    o[k] = ck.x * (k == 0 ? s0 : s1);
-    if (k > 0) o[N - k] = -ck.y * s1;
-    if (H - k != k) {
-      o[H - k] = cp.x * s1;
-      if (k > 0) o[H + k] = -cp.y * s1;
+#pragma unroll
+  for (int qq = 0; qq < PP; ++qq) {
+    const int p = threadIdx.x + qq * kThreads;
+    if (p < ROWS * NP) {
+      const int row = p / NP, k = p % NP;
+      Cx<CT> ck, cp;
+      post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
+      CT* o = out + (row0 + row) * ld;
+      o[k] = ck.x * (k == 0 ? s0 : s1);
+      if (k > 0) o[N - k] = -ck.y * s1;
+      if (H - k != k) {
+        o[H - k] = cp.x * s1;
+        if (k > 0) o[H + k] = -cp.y * s1;
+      }
     }
   }
 }
@@ -303,23 +386,20 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io,
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
-  __shared__ Cx<CT> buf[ROWS * H];
+  __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
-    const int row = e / N, c = e % N;
-    v[row * N + perm<N>(c)] = io[(row0 + row) * ld + c];
-  }
+  stage_in<CT, CT, H>(io, ld, row0, v);
   __syncthreads();
   fft_rows<CT, H, ROWS>(buf, tw.fft);
-  // forward post-processing and division, held in registers: with
-  // d = 1 / (lambda_k + mu_l), the scaled coefficient divided by s_k is
-  // Re(c_k) d_k, and -Im(c_k) d_{n-k} for index n - k
-  Cx<CT> cks[PP], cps[PP];
+  // forward post-processing, division and inverse pre-processing of pair
+  // (k, h-k), in place: the pair's two slots are read and written by the
+  // same thread only.  With d = 1 / (lambda_k + mu_l), the scaled
+  // coefficient divided by s_k is Re(c_k) d_k, and -Im(c_k) d_{n-k} at n-k.
 #pragma unroll
-  for (int q = 0; q < PP; ++q) {
-    const int p = threadIdx.x + q * kThreads;
+  for (int qq = 0; qq < PP; ++qq) {
+    const int p = threadIdx.x + qq * kThreads;
     if (p < ROWS * NP) {
       const int row = p / NP, k = p % NP;
       const int64_t l = row0 + row;
@@ -328,81 +408,110 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io,
         return (l == 0 && kk == 0) ? (CT)0 : (CT)(1.0 / (eig_k[kk] + mu));
       };
       Cx<CT> ck, cp;
-      post_pair<CT, H>(buf + row * H, k, tw, ck, cp);
+      post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
       // X~ at k, n-k, h-k, h+k; c_k (inverse) = X~_k - i X~_{n-k}
       const CT xk = ck.x * d(k);
       const CT xnk = k > 0 ? -ck.y * d(N - k) : (CT)0;
       const CT xp = cp.x * d(H - k);
       const CT xnp = -cp.y * d(H + k);   // k = 0: index h, equal to xp
-      cks[q] = {xk, -xnk};
-      cps[q] = {xp, -xnp};
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PP; ++q) {
-    const int p = threadIdx.x + q * kThreads;
-    if (p < ROWS * NP) {
-      const int row = p / NP, k = p % NP;
-      pre_pair<CT, H>(cks[q], cps[q], k, tw, buf + row * H);
+      pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf, row * H);
     }
   }
   __syncthreads();
   fft_rows<CT, H, ROWS>(buf, tw.fft);
   const CT inv_h = (CT)(1.0 / H);
-  for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
-    const int row = e / N, c = e % N;
-    const int m = perm<N>(c);
-    // w = conj(FFT(conj W)) / h: v[2m] = Re, v[2m+1] = Im of w
-    const CT val = (m & 1) ? -v[row * N + m] : v[row * N + m];
-    io[(row0 + row) * ld + c] = val * inv_h;
+  using V = typename Vec16<CT>::type;
+  constexpr int W = Vec16<CT>::W;
+  constexpr int NCH = ROWS * N / W / kThreads;
+#pragma unroll
+  for (int i = 0; i < NCH; ++i) {
+    const int e0 = (threadIdx.x + i * kThreads) * W;
+    const int row = e0 / N, c = e0 % N;
+    V o;
+#pragma unroll
+    for (int t = 0; t < W; ++t) o[t] = inv_value<CT, N>(v, row, c + t, inv_h);
+    *reinterpret_cast<V*>(io + (row0 + row) * ld + c) = o;
   }
 }
 
 // ---- pass 5: DCT-III along rows, z.r, z.q, sum z -------------------------
 template <class CT, class TO, int H>
 __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
-    const CT* __restrict__ in, int64_t ld, int64_t nrows, TO* __restrict__ z,
-    const TO* __restrict__ r, const TO* __restrict__ q, const void* twp, DevState st) {
+    const CT* __restrict__ in, int64_t ld, TO* __restrict__ z, const TO* __restrict__ r,
+    const TO* __restrict__ q, const void* twp, DevState st) {
   if (st.fl[FL_DONE]) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
-  __shared__ Cx<CT> buf[ROWS * H];
+  constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
+  __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
   CT* v = reinterpret_cast<CT*>(buf);
   const CT inv_h = (CT)(1.0 / H);
   const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
-  double acc[3] = {0.0, 0.0, 0.0};
-  const int64_t ngroups = nrows / ROWS;
-  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const int64_t row0 = g * ROWS;
-    for (int p = threadIdx.x; p < ROWS * NP; p += kThreads) {
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+#pragma unroll
+  for (int qq = 0; qq < PP; ++qq) {
+    const int p = threadIdx.x + qq * kThreads;
+    if (p < ROWS * NP) {
       const int row = p / NP, k = p % NP;
       const CT* x = in + (row0 + row) * ld;
       const CT xk = x[k] * (k == 0 ? is0 : is1);
       const CT xnk = k > 0 ? x[N - k] * is1 : (CT)0;
       const CT xp = x[H - k] * is1;
       const CT xnp = x[H + k] * is1;
-      pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf + row * H);
+      pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf, row * H);
     }
-    __syncthreads();
-    fft_rows<CT, H, ROWS>(buf, tw.fft);
-    for (int e = threadIdx.x; e < ROWS * N; e += kThreads) {
-      const int row = e / N, c = e % N;
-      const int m = perm<N>(c);
-      const CT val = ((m & 1) ? -v[row * N + m] : v[row * N + m]) * inv_h;
-      const int64_t o = (row0 + row) * ld + c;
-      const TO zt = (TO)val;
-      z[o] = zt;
-      const double zd = (double)zt;
-      acc[0] += zd * (double)r[o];
-      if (q) acc[1] += zd * (double)q[o];
-      acc[2] += zd;
+  }
+  __syncthreads();
+  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  using V = typename Vec16<TO>::type;
+  constexpr int W = Vec16<TO>::W;
+  constexpr int NCH = ROWS * N / W / kThreads;
+  constexpr int BATCH = NCH < 8 ? NCH : 8;
+  static_assert(NCH % BATCH == 0, "output batches");
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i0 = 0; i0 < NCH; i0 += BATCH) {
+    V rv[BATCH], qv[BATCH];
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      const int e0 = (threadIdx.x + (i0 + b) * kThreads) * W;
+      const int64_t o = (row0 + e0 / N) * ld + e0 % N;
+      rv[b] = *reinterpret_cast<const V*>(r + o);
+      if (q) qv[b] = *reinterpret_cast<const V*>(q + o);
     }
-    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      const int e0 = (threadIdx.x + (i0 + b) * kThreads) * W;
+      const int row = e0 / N, c = e0 % N;
+      V zv;
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const TO zt = (TO)inv_value<CT, N>(v, row, c + t, inv_h);
+        zv[t] = zt;
+        const double zd = (double)zt;
+        acc[0] += zd * (double)rv[b][t];
+        if (q) acc[1] += zd * (double)qv[b][t];
+        acc[2] += zd;
+      }
+      *reinterpret_cast<V*>(z + (row0 + row) * ld + c) = zv;
+    }
   }
   const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
   write_partials<3>(st, slots, acc, (int)blockIdx.x);
+}
+
+// The n per-block partials of z.r, z.q, sum z folded into partial 0 (one
+// block, fixed order), so that their consumers reduce a single value.
+constexpr int kFoldThreads = 1024;
+__global__ __launch_bounds__(kFoldThreads) void fct_fold_partials_kernel(DevState st, int n) {
+  if (st.fl[FL_DONE]) return;
+  const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double v = reduce_slot<kFoldThreads>(st, slots[i], n);
+    if (threadIdx.x == 0) st.part[(size_t)slots[i] * kMaxPartials + st.off] = v;
+  }
 }
 
 // ---- transpose (64 x 64 tiles through LDS) -------------------------------
@@ -512,13 +621,14 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   int nb = 0;
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
-    const int64_t ngroups = N / rows_per_block<H>();
-    nb = (int)(ngroups < 1024 ? ngroups : 1024);
+    nb = (int)(N / rows_per_block<H>());
     hipLaunchKernelGGL((fct_rows_inv_kernel<CT, CT, H>), dim3((unsigned)nb), dim3(kThreads), 0, s,
-                       T1, M, N, z, r, q, a.twM, a.st);
+                       T1, M, z, r, q, a.twM, a.st);
   });
   log_mark(L, LC_PASS, s);
-  return nb;
+  hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, a.st, nb);
+  log_mark(L, LC_PASS, s);
+  return 1;
 }
 
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s) {
