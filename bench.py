@@ -134,6 +134,65 @@ def time_stencil(plan, torch, reps=20):
     return e0.elapsed_time(e1) / reps
 
 
+# kernel name, algorithmic bytes per pixel (vector type of e bytes) per launch
+# kind of the fast form; products are priced in flops instead
+FAST_KERNELS = {"rows_dct2": ("fct_rows_fwd_kernel", 2), "transpose": ("transpose_kernel", 2),
+                "cols": ("fct_cols_kernel", 2), "rows_dct3": ("fct_rows_inv_kernel", 3)}
+
+
+def kernel_table(plan, launches, ms_st, prec, N, M):
+    """Time per PCG iteration of each kernel of the preconditioner and of
+    the stencil, with its algorithmic work: bytes for the HBM-bound passes
+    (the fast form's transforms and transposes, the stencil's 16 B/px),
+    dense-equivalent flops 4NM(N+M) per application for the MFMA products."""
+    e = 8 if prec == "f64" else 4
+    px = N * M
+    out = {}
+    n_prod = sum(1 for k, _ in launches if k == "product")
+    for kind, ms in launches:
+        if kind == "product":
+            name = "gemm_nt_kernel"
+            ent = out.setdefault(name, {"bound": "mfma", "launches": 0, "ms": 0.0,
+                                        "flops_per_launch": 4.0 * px * (N + M) / n_prod,
+                                        "folded": n_prod == 8})
+        elif kind in FAST_KERNELS:
+            name, bpp = FAST_KERNELS[kind]
+            ent = out.setdefault(name, {"bound": "hbm", "launches": 0, "ms": 0.0,
+                                        "bytes_per_launch": bpp * e * px})
+        else:
+            name = kind
+            ent = out.setdefault(name, {"bound": "other", "launches": 0, "ms": 0.0})
+        ent["launches"] += 1
+        ent["ms"] += ms
+    out["stencil_kernel"] = {"bound": "hbm", "launches": 1, "ms": ms_st,
+                             "bytes_per_launch": 16 * px * e // 4}
+    for ent in out.values():
+        ent["ms"] = round(ent["ms"], 4)
+    return out
+
+
+def roofline(kern, prec):
+    """Roofline object of the dominant kernel (largest time per iteration)."""
+    name, ent = max(((k, v) for k, v in kern.items() if v["bound"] != "other"),
+                    key=lambda kv: kv[1]["ms"])
+    ms_launch = ent["ms"] / ent["launches"]
+    if ent["bound"] == "mfma":
+        # the folded form executes half of the dense-equivalent flops
+        ach = ent["flops_per_launch"] / (ms_launch * 1e-3) / 1e12
+        ex = ach / (2.0 if ent["folded"] else 1.0)
+        return {"bound": "mfma", "kernel": name, "achieved": round(ach, 2), "peak": PEAK[prec],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK[prec], 4), "traffic": None,
+                "flops_per_launch": ent["flops_per_launch"],
+                "flops_basis": "dense-equivalent 4NM(N+M) per application / launches",
+                "executed_TFLOPs": round(ex, 2), "executed_frac": round(ex / PEAK[prec], 4),
+                "ms_per_launch": round(ms_launch, 4), "launches_per_iter": ent["launches"]}
+    ach = ent["bytes_per_launch"] / (ms_launch * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"],
+            "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": None,
+            "bytes_per_launch": ent["bytes_per_launch"], "ms_per_launch": round(ms_launch, 4),
+            "launches_per_iter": ent["launches"]}
+
+
 def kernels_only(pkg, torch, N, M, prec):
     """Fixed launch sequence for counter runs (no unwrap, no oracle)."""
     torch.cuda.set_device(0)
@@ -141,7 +200,7 @@ def kernels_only(pkg, torch, N, M, prec):
     r = torch.randn((plan.Np, plan.ld), dtype=plan.dtype, device=plan.device)
     r[N:, :] = 0
     r[:, M:] = 0
-    tim = plan.precond_timed(r, reps=3)
+    launches = plan.precond_timed(r, reps=3)
     ms_st = time_stencil(plan, torch, reps=3)
     nbytes = 256 << 20
     x = torch.empty(nbytes // 4, dtype=torch.float32, device=plan.device).uniform_()
@@ -149,9 +208,8 @@ def kernels_only(pkg, torch, N, M, prec):
     for _ in range(3):
         y.copy_(x)
     torch.cuda.synchronize()
-    out = {"N": N, "M": M, "precision": prec, "folded": plan.folded,
-           "precond_products_ms": tim["ms_products"] / tim["n_products"],
-           "precond_launches": tim["n_products"] // 3, "stencil_ms": ms_st,
+    out = {"N": N, "M": M, "precision": prec, "form": plan.form,
+           "launches": [[k, round(ms, 4)] for k, ms in launches], "stencil_ms": round(ms_st, 4),
            "copy_bytes_each_way": nbytes}
     print(json.dumps(out), flush=True)
     plan.close()
@@ -229,25 +287,17 @@ def main(argv=None):
     last = runs[-1]
     L1_reached = last["history"][last["irls_done"]]["L1"] if hit else last["L1_final"]
 
-    # dominant kernel: the preconditioner's MFMA products, each launch timed
-    # with HIP events on the launch stream (irlsu_precond_timed)
+    # per-launch HIP-event timing of one preconditioner application on the
+    # launch stream, and the stencil; the dominant kernel is the one with
+    # the largest time per PCG iteration
     rr = torch.randn((plan.Np, plan.ld), dtype=plan.dtype, device=plan.device)
     rr[N:, :] = 0
     rr[:, M:] = 0
     plan.precond_timed(rr, reps=1)
-    reps = 5
-    tim = plan.precond_timed(rr, reps=reps)
-    n_prod = tim["n_products"] // reps           # 4 dense, 8 folded
-    ms_launch = tim["ms_products"] / tim["n_products"]
-    ms_prec = (tim["ms_products"] + tim["ms_passes"]) / reps
-    flops_app = 4.0 * N * M * (N + M)             # dense eigen-products per application
-    flops_launch = flops_app / n_prod             # dense-equivalent per launch
-    exec_launch = flops_launch / (2.0 if plan.folded else 1.0)
-    tf = flops_launch / (ms_launch * 1e-3) / 1e12
-    tf_exec = exec_launch / (ms_launch * 1e-3) / 1e12
-    peak = PEAK[prec]
+    launches = plan.precond_timed(rr, reps=5)
     ms_st = time_stencil(plan, torch)
-    gbs = 16.0 * N * M / (ms_st * 1e-3) / 1e9
+    kern = kernel_table(plan, launches, ms_st, prec, N, M)
+    roof = roofline(kern, prec)
 
     pcg_per_step = last["pcg_total"]
     line = {
@@ -266,20 +316,10 @@ def main(argv=None):
                    "irls_iters": last["irls_done"], "pcg_iters": pcg_per_step,
                    "ms_per_pcg_iter": round(ms / max(1, pcg_per_step), 4),
                    "plan_create_s": round(plan_s, 3)},
-        "roofline": {"bound": "mfma",
-                     "kernel": f"gemm_nt_kernel ({n_prod} launches per preconditioner, "
-                               f"{'folded even/odd' if plan.folded else 'dense'} form)",
-                     "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(tf / peak, 4), "traffic": None,
-                     "flops_per_launch": flops_launch,
-                     "flops_basis": "dense-equivalent 4NM(N+M) per application / launches",
-                     "executed_TFLOPs": round(tf_exec, 2),
-                     "executed_frac": round(tf_exec / peak, 4),
-                     "ms_per_launch": round(ms_launch, 4),
-                     "precond_ms": round(ms_prec, 4)},
-        "stencil": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_GBps"],
-                    "unit": "GB/s", "frac": round(gbs / PEAK["hbm_GBps"], 4),
-                    "bytes_per_px": 16, "ms": round(ms_st, 4)},
+        "roofline": roof,
+        "kernels": kern,
+        "precond_form": plan.form,
+        "precond_ms": round(sum(ms for _, ms in launches), 4),
     }
     if not a.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -291,18 +291,33 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
 irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* Kinds of launch reported by irlsu_precond_timed. */
+#define IRLSU_MAX_LAUNCHES 32
+enum {
+  IRLSU_LK_PRODUCT = 0,    /* MFMA product with the cosine basis (dense / folded) */
+  IRLSU_LK_ROWS_DCT2 = 1,  /* fast form: DCT-II along rows */
+  IRLSU_LK_TRANSPOSE = 2,  /* fast form: transpose */
+  IRLSU_LK_COLS = 3,       /* fast form: DCT-II, division, DCT-III along columns */
+  IRLSU_LK_ROWS_DCT3 = 4,  /* fast form: DCT-III along rows with z.r, z.q, sum z */
+  IRLSU_LK_BUTTERFLY = 5,  /* folded form: sum / difference pass */
+  IRLSU_LK_DOTS = 6,       /* z.r, z.q, sum z pass (with the recombination when folded) */
+  IRLSU_LK_PROLOGUE = 7,   /* convergence test and input scale */
+  IRLSU_LK_PARTIALS = 8    /* fold of per-block partial sums */
+};
+
 /* Timing of the preconditioner of Section 3.3 (the products named there as
  * the main cost): reps applications of irlsu_precond's map, with a HIP event
  * recorded on `stream` before the first launch and after every launch.
- * Returns the summed durations (ms) and launch counts of the MFMA products
- * (*ms_products, *n_products) and of every other pass (*ms_passes,
- * *n_passes) over all reps; z receives the last application.  Synchronises
- * the stream.  Errors as irlsu_precond; ERR_INVALID_ARG also for reps < 1 or
- * a null output pointer; ERR_HIP when events cannot be created. */
+ * Writes, for each of the *n_launches launches of one application (at most
+ * IRLSU_MAX_LAUNCHES), its mean duration over the reps in ms_launch[i] and
+ * its IRLSU_LK_* kind in kind[i]; z receives the last application.
+ * Synchronises the stream.  Errors as irlsu_precond; ERR_INVALID_ARG also
+ * for reps < 1 or a null output pointer; ERR_HIP when events cannot be
+ * created. */
 irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
                                  void* workspace, size_t workspace_bytes, int32_t reps,
-                                 double* ms_products, int32_t* n_products,
-                                 double* ms_passes, int32_t* n_passes, void* stream);
+                                 double* ms_launch, int32_t* kind, int32_t* n_launches,
+                                 void* stream);
 
 #ifdef __cplusplus
 }

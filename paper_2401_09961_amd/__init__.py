@@ -100,6 +100,9 @@ class PlanDesc(ctypes.Structure):
 
 # form of the preconditioner products (irlsu_plan_create_ex)
 PLAN_FORMS = {"auto": 0, "dense": 1, "folded": 2, "fast": 3}
+IRLSU_MAX_LAUNCHES = 32
+LAUNCH_KINDS = {0: "product", 1: "rows_dct2", 2: "transpose", 3: "cols", 4: "rows_dct3",
+                5: "butterfly", 6: "dots", 7: "prologue", 8: "partials"}
 
 
 _lib = None
@@ -141,8 +144,7 @@ def load_library():
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
         "irlsu_precond_timed": (I32, [P, P, P, P, SZ, I32, ctypes.POINTER(ctypes.c_double),
-                                      ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double),
-                                      ctypes.POINTER(I32), P]),
+                                      ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -322,18 +324,16 @@ class Plan:
         return z, rz
 
     def precond_timed(self, r, reps=5):
-        """Per-launch HIP-event timing of reps preconditioner applications:
-        {"ms_products", "n_products", "ms_passes", "n_passes"} (summed)."""
-        import torch
-        z = torch.empty_like(r)
-        mp, mo = ctypes.c_double(), ctypes.c_double()
-        npr, npa = ctypes.c_int32(), ctypes.c_int32()
+        """Per-launch HIP-event timing of the preconditioner: a list of
+        (kind, mean ms) for the launches of one application, in order."""
+        ms = (ctypes.c_double * IRLSU_MAX_LAUNCHES)()
+        kind = (ctypes.c_int32 * IRLSU_MAX_LAUNCHES)()
+        n = ctypes.c_int32()
+        z = r.new_empty(r.shape)
         _check(self.lib.irlsu_precond_timed(self.handle, _ptr(r), _ptr(z), _ptr(self.workspace),
-                                            self.workspace.numel(), int(reps), ctypes.byref(mp),
-                                            ctypes.byref(npr), ctypes.byref(mo), ctypes.byref(npa),
-                                            _stream()), "precond_timed")
-        return {"ms_products": mp.value, "n_products": npr.value,
-                "ms_passes": mo.value, "n_passes": npa.value, "z": z}
+                                            self.workspace.numel(), int(reps), ms, kind,
+                                            ctypes.byref(n), _stream()), "precond_timed")
+        return [(LAUNCH_KINDS[kind[i]], ms[i]) for i in range(n.value)]
 
 
 class Batch:

@@ -471,16 +471,16 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
   log_start(L, s);
   // G1: T1^T = (r P_M)^T
   gemm<OT, T>(r, Mp, PMt, Mp, Np, Mp, Mp, 1.0f, EpiStoreT<OT>{T1, Np}, c1, s);
-  log_mark(L, LC_PRODUCT, s);
+  log_mark(L, IRLSU_LK_PRODUCT, s);
   // G2: T2^T = (P_N^T T1)^T ./ lambda
   gemm<OT, OT>(T1, Np, PNt, Np, Mp, Np, Np, 1.0f,
                EpiScale<OT>{T2, Np, static_cast<const double*>(a.eigM),
                             static_cast<const double*>(a.eigN)},
                cn, s);
-  log_mark(L, LC_PRODUCT, s);
+  log_mark(L, IRLSU_LK_PRODUCT, s);
   // G3: T3 = (T2^T P_N^T)^T = P_N T2
   gemm<OT, OT>(T2, Np, PN, Np, Mp, Np, Np, 1.0f, EpiStoreT<OT>{T3, Mp}, cn, s);
-  log_mark(L, LC_PRODUCT, s);
+  log_mark(L, IRLSU_LK_PRODUCT, s);
   // G4: z = T3 P_M^T.  16-bit operands: the 256 x 256 tile stores z only and
   // a light pass forms z.r, z.q, sum z (the fused epilogue does not fit
   // beside that tile's registers); FP32 / FP64 fuse the sums.
@@ -489,18 +489,18 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
                  EpiStoreZ<T>{static_cast<T*>(a.z), Mp, 1.0,
                               f16 ? a.st.sc + SC_SCALE : nullptr},
                  cn, s);
-    log_mark(L, LC_PRODUCT, s);
+    log_mark(L, IRLSU_LK_PRODUCT, s);
     const int nb = elementwise_blocks(Np * Mp);
     hipLaunchKernelGGL(zdots_kernel<T>, dim3(nb), dim3(kThreads), 0, s, static_cast<const T*>(a.z),
                        r, static_cast<const T*>(a.q), Np * Mp, a.st, 1);
-    log_mark(L, LC_PASS, s);
+    log_mark(L, IRLSU_LK_DOTS, s);
     return nb;
   } else {
     const int nb = gemm<OT, OT>(T3, Mp, PM, Mp, Np, Mp, Mp, 1.0f,
                                 EpiFinal<T>{static_cast<T*>(a.z), r, static_cast<const T*>(a.q), Mp,
                                             1.0, nullptr},
                                 cn, s);
-    log_mark(L, LC_PRODUCT, s);
+    log_mark(L, IRLSU_LK_PRODUCT, s);
     return nb;
   }
 }
@@ -529,11 +529,11 @@ static int precond_folded_impl(const PrecondArgs& a, hipStream_t s) {
   const int32_t* done = a.st.fl + FL_DONE;
   GemmCtl cn{a.st, 1, 0, 0, 0, 0};
   LaunchLog* L = a.log;
-  auto prod = [&]() { log_mark(L, LC_PRODUCT, s); };
-  auto pass = [&]() { log_mark(L, LC_PASS, s); };
+  auto prod = [&]() { log_mark(L, IRLSU_LK_PRODUCT, s); };
+  auto pass = [&]() { log_mark(L, IRLSU_LK_BUTTERFLY, s); };
   log_start(L, s);
   launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
-  pass();
+  log_mark(L, IRLSU_LK_PROLOGUE, s);
   // S = [r_j + r_{M-1-j} | r_j - r_{M-1-j}]           (Np x wM)
   launch_fold_rows<T, OT>(r, Mp, M, N, Np, X1, hM, f16 ? a.st.sc + SC_SCALE : nullptr, done, s);
   pass();
@@ -569,7 +569,7 @@ static int precond_folded_impl(const PrecondArgs& a, hipStream_t s) {
   const int nb = launch_unfold_cols_dots<T>(ZEO, hM, N, M, Np, Mp, static_cast<T*>(a.z), r,
                                             static_cast<const T*>(a.q), 1.0,
                                             f16 ? a.st.sc + SC_SCALE : nullptr, a.st, s);
-  pass();
+  log_mark(L, IRLSU_LK_DOTS, s);
   return nb;
 }
 

@@ -515,19 +515,38 @@ __global__ __launch_bounds__(kFoldThreads) void fct_fold_partials_kernel(DevStat
 }
 
 // ---- transpose (64 x 64 tiles through LDS) -------------------------------
+// 16-byte loads along the input rows and 16-byte stores along the output
+// rows; every load of a thread is issued before its first LDS write.
 template <class T>
 __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, int64_t ldin,
                                                             T* __restrict__ out, int64_t ldout,
                                                             const int32_t* done) {
   if (*done) return;
-  __shared__ T tile[64][65];
+  using V = typename Vec16<T>::type;
+  constexpr int W = Vec16<T>::W;
+  constexpr int CPR = 64 / W;            // chunks per tile row
+  constexpr int RPP = kThreads / CPR;    // tile rows per pass
+  constexpr int NPASS = 64 / RPP;
+  __shared__ T tile[64][64 + 1];
   const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int cq = threadIdx.x % CPR, rr = threadIdx.x / CPR;
+  V d[NPASS];
 #pragma unroll
-  for (int i = ty; i < 64; i += 4) tile[i][tx] = in[(r0 + i) * ldin + c0 + tx];
+  for (int i = 0; i < NPASS; ++i)
+    d[i] = *reinterpret_cast<const V*>(in + (r0 + rr + i * RPP) * ldin + c0 + cq * W);
+#pragma unroll
+  for (int i = 0; i < NPASS; ++i)
+#pragma unroll
+    for (int t = 0; t < W; ++t) tile[rr + i * RPP][cq * W + t] = d[i][t];
   __syncthreads();
 #pragma unroll
-  for (int i = ty; i < 64; i += 4) out[(c0 + i) * ldout + r0 + tx] = tile[tx][i];
+  for (int i = 0; i < NPASS; ++i) {
+    const int jrow = rr + i * RPP;   // output row = input column c0 + jrow
+    V o;
+#pragma unroll
+    for (int t = 0; t < W; ++t) o[t] = tile[cq * W + t][jrow];
+    *reinterpret_cast<V*>(out + (c0 + jrow) * ldout + r0 + cq * W) = o;
+  }
 }
 
 // ---- tables -----------------------------------------------------------------
@@ -598,26 +617,26 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   LaunchLog* L = a.log;
   log_start(L, s);
   launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, 0, N * M, s);
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_PROLOGUE, s);
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
     hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, CT, H>), dim3((unsigned)(N / rows_per_block<H>())),
                        dim3(kThreads), 0, s, r, M, T1, a.twM, done);
   });
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_ROWS_DCT2, s);
   hipLaunchKernelGGL(transpose_kernel<CT>, dim3((unsigned)(M / 64), (unsigned)(N / 64)),
                      dim3(kThreads), 0, s, T1, M, T2, N, done);
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_TRANSPOSE, s);
   with_h(N / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
     hipLaunchKernelGGL((fct_cols_kernel<CT, H>), dim3((unsigned)(M / rows_per_block<H>())),
                        dim3(kThreads), 0, s, T2, N, a.twN, static_cast<const double*>(a.eigN),
                        static_cast<const double*>(a.eigM), done);
   });
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_COLS, s);
   hipLaunchKernelGGL(transpose_kernel<CT>, dim3((unsigned)(N / 64), (unsigned)(M / 64)),
                      dim3(kThreads), 0, s, T2, N, T1, M, done);
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_TRANSPOSE, s);
   int nb = 0;
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
@@ -625,9 +644,9 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((fct_rows_inv_kernel<CT, CT, H>), dim3((unsigned)nb), dim3(kThreads), 0, s,
                        T1, M, z, r, q, a.twM, a.st);
   });
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_ROWS_DCT3, s);
   hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, a.st, nb);
-  log_mark(L, LC_PASS, s);
+  log_mark(L, IRLSU_LK_PARTIALS, s);
   return 1;
 }
 

@@ -1109,11 +1109,9 @@ irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, doubl
 }
 
 irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z, void* workspace,
-                                 size_t workspace_bytes, int32_t reps, double* ms_products,
-                                 int32_t* n_products, double* ms_passes, int32_t* n_passes,
-                                 void* stream) {
-  if (!plan || !r || !z || r == z || reps < 1 || !ms_products || !n_products || !ms_passes ||
-      !n_passes)
+                                 size_t workspace_bytes, int32_t reps, double* ms_launch,
+                                 int32_t* kind, int32_t* n_launches, void* stream) {
+  if (!plan || !r || !z || r == z || reps < 1 || !ms_launch || !kind || !n_launches)
     return IRLSU_ERR_INVALID_ARG;
   irlsu_status st = check_ws(plan, workspace, workspace_bytes);
   if (st != IRLSU_OK) return st;
@@ -1129,10 +1127,11 @@ irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
     destroy();
     return IRLSU_ERR_HIP;
   }
-  *ms_products = 0.0;
-  *ms_passes = 0.0;
-  *n_products = 0;
-  *n_passes = 0;
+  for (int i = 0; i < LaunchLog::kMax; ++i) {
+    ms_launch[i] = 0.0;
+    kind[i] = -1;
+  }
+  *n_launches = 0;
   auto go = [&](auto tag) -> irlsu_status {
     using T = decltype(tag);
     const Ws<T> W = carve<T>(plan, workspace);
@@ -1148,16 +1147,12 @@ irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
       a.log = &L;
       launch_precond(a, s);
       HIP_OK(hipEventSynchronize(L.ev[L.n]));
+      *n_launches = L.n;
       for (int i = 0; i < L.n; ++i) {
         float ms = 0.0f;
         HIP_OK(hipEventElapsedTime(&ms, L.ev[i], L.ev[i + 1]));
-        if (L.cls[i] == LC_PRODUCT) {
-          *ms_products += ms;
-          ++*n_products;
-        } else {
-          *ms_passes += ms;
-          ++*n_passes;
-        }
+        ms_launch[i] += ms / reps;
+        kind[i] = L.cls[i];
       }
     }
     return IRLSU_OK;

@@ -168,10 +168,9 @@ enum OperandKind : int { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2, OK_F16 = 3 };
 
 // Optional per-launch timing of one preconditioner application: an event
 // is recorded before the first launch and after every launch, each launch
-// tagged with its class (LC_PRODUCT: an MFMA product, LC_PASS: any other).
-enum LaunchClass : int { LC_PRODUCT = 0, LC_PASS = 1 };
+// tagged with its kind (IRLSU_LK_* of the public header).
 struct LaunchLog {
-  static constexpr int kMax = 32;
+  static constexpr int kMax = IRLSU_MAX_LAUNCHES;
   hipEvent_t ev[kMax + 1];
   int cls[kMax];
   int n = 0;
@@ -182,9 +181,9 @@ inline void log_start(LaunchLog* L, hipStream_t s) {
     (void)hipEventRecord(L->ev[0], s);
   }
 }
-inline void log_mark(LaunchLog* L, int cls, hipStream_t s) {
+inline void log_mark(LaunchLog* L, int kind, hipStream_t s) {
   if (L && L->n < LaunchLog::kMax) {
-    L->cls[L->n] = cls;
+    L->cls[L->n] = kind;
     (void)hipEventRecord(L->ev[++L->n], s);
   }
 }
