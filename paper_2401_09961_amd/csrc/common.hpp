@@ -135,6 +135,43 @@ __device__ __forceinline__ void write_partials(const DevState& st, const int (&s
   }
 }
 
+// Four consecutive elements, moved with 16-byte accesses (two for FP64).
+template <class T>
+struct V4 {
+  T v[4];
+};
+
+template <class T>
+__device__ __forceinline__ V4<T> ld4(const T* p) {
+  V4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  }
+  return r;
+}
+
+template <class T>
+__device__ __forceinline__ void st4(T* p, const V4<T>& r) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(r.v[2], r.v[3]);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ V4<T> zero4() {
+  V4<T> r;
+  r.v[0] = r.v[1] = r.v[2] = r.v[3] = (T)0;
+  return r;
+}
+
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace irlsu

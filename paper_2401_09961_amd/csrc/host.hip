@@ -79,7 +79,7 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-enum VecId { V_R, V_Z, V_P0, V_P1, V_Q, V_B, V_GV, V_GH, V_CV, V_CH, V_OV, V_OH, V_COUNT };
+enum VecId { V_R, V_Z, V_P0, V_P1, V_Q, V_B, V_GV, V_GH, V_CV, V_CH, V_OV, V_OH, V_D, V_COUNT };
 
 struct Layout {
   size_t u, lam, vec[V_COUNT], t1, t2, t3, zeo, part, sc, fl, total;
@@ -245,8 +245,13 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
   const size_t npx = (size_t)pl->Np * (size_t)pl->Mp;
   const int nvec = stencil_blocks(pl);
   T* P[2] = {W.v[V_P0], W.v[V_P1]};
+  // the solve accumulates its correction d (vector type) and adds it to x
+  // (FP64) once at the end; the true-residual refresh uses x + d
+  T* d = W.v[V_D];
+  HIP_OK(hipMemsetAsync(d, 0, npx * sizeof(T), s));
   StencilArgs<T> ra = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
   ra.u = x;
+  ra.d = d;
   ra.b = rhs;
   ra.r = W.v[V_R];
   ra.check_done = 0;
@@ -268,6 +273,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     const int npq = launch_stencil<T>(ST_FUSED, fa, s);
     AxpyArgs<T> xa;
     xa.u = x;
+    xa.d = d;
     xa.r = W.v[V_R];
     xa.p = P[l & 1];
     xa.q = W.v[V_Q];
@@ -290,6 +296,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     }
   }
   launch_finalize_rr(st, nvec, s);
+  launch_commit<T>(x, d, (int64_t)npx, s);
   irlsu_status rs = read_back(pl, W, s);
   if (rs != IRLSU_OK) return rs;
   *iters_out = pl->h_flags[FL_ITERS];

@@ -31,6 +31,8 @@ struct WeightsArgs {
 template <class T>
 struct AxpyArgs {
   double* u; T* r; const T* p; const T* q;
+  T* d = nullptr;     // non-null: the solve's correction d += alpha p (vector
+                      // type); u is then left alone until the solve ends
   int64_t n;          // Np * ld, a multiple of 4
   int nparts_pq;      // number of p.q partials written by the stencil
   int iter;
@@ -52,6 +54,7 @@ struct StencilArgs {
   T* p_out;            // FUSED: new direction (must not alias p_in)
   T* q;                // FUSED / APPLY output
   const double* u;     // RESID input
+  const T* d = nullptr;  // RESID: correction of the current solve (u + d)
   const T* b;          // RESID input
   T* r;                // RESID output
   int64_t N, M, Np, ld;
@@ -100,6 +103,8 @@ template <class T> void launch_setup(const SetupArgs<T>& a, hipStream_t s);
 template <class T> int launch_weights(const WeightsArgs<T>& a, hipStream_t s);
 void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s);
 template <class T> int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks);
+// u += d (FP64) over n elements: the end of a solve
+template <class T> void launch_commit(double* u, const T* d, int64_t n, hipStream_t s);
 void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s);
 template <class T>
 void launch_copy_out(const double* u, int64_t ld, T* out, int64_t ldo, int64_t N, int64_t M,

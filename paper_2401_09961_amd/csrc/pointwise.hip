@@ -187,17 +187,39 @@ __device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) 
   const T al = (T)alpha;
   double acc[2] = {0.0, 0.0};
   const int64_t n4 = a.n / 4;
-  for (int64_t k = (int64_t)lb * kThreads + threadIdx.x; k < n4; k += (int64_t)nb * kThreads) {
-    const int64_t o = k * 4;
+  // two 4-element chunks per thread in flight; 16-byte accesses
+  constexpr int UN = 2;
+  const int64_t stride = (int64_t)nb * kThreads;
+  for (int64_t k0 = (int64_t)lb * kThreads + threadIdx.x; k0 < n4; k0 += UN * stride) {
+    V4<T> p[UN], q[UN], r[UN], d[UN];
+    V4<double> u[UN];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const T p = a.p[o + e];
-      const T q = a.q[o + e];
-      a.u[o + e] += alpha * (double)p;
-      const T r = a.r[o + e] - al * q;
-      a.r[o + e] = r;
-      acc[0] += (double)r * (double)r;
-      acc[1] += (double)r;
+    for (int c = 0; c < UN; ++c) {
+      const int64_t k = k0 + c * stride;
+      if (k < n4) {
+        p[c] = ld4(a.p + 4 * k);
+        q[c] = ld4(a.q + 4 * k);
+        r[c] = ld4(a.r + 4 * k);
+        if (a.d) d[c] = ld4(a.d + 4 * k);
+        else u[c] = ld4(a.u + 4 * k);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < UN; ++c) {
+      const int64_t k = k0 + c * stride;
+      if (k < n4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          r[c].v[e] = r[c].v[e] - al * q[c].v[e];
+          acc[0] += (double)r[c].v[e] * (double)r[c].v[e];
+          acc[1] += (double)r[c].v[e];
+          if (a.d) d[c].v[e] = d[c].v[e] + al * p[c].v[e];
+          else u[c].v[e] += alpha * (double)p[c].v[e];
+        }
+        st4(a.r + 4 * k, r[c]);
+        if (a.d) st4(a.d + 4 * k, d[c]);
+        else st4(a.u + 4 * k, u[c]);
+      }
     }
   }
   const int slots[2] = {PR_RR, PR_RSUM};
@@ -259,6 +281,28 @@ __global__ __launch_bounds__(kThreads) void sub_mean_kernel(double* u, int64_t N
     if (j < M) u[k] -= mean;
   }
 }
+
+// End of a solve: u += d in FP64 (d, the solve's correction, in the vector
+// type).
+template <class T>
+__global__ __launch_bounds__(kThreads) void commit_kernel(double* u, const T* d, int64_t n4) {
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n4;
+       k += (int64_t)gridDim.x * kThreads) {
+    V4<double> x = ld4(u + 4 * k);
+    const V4<T> c = ld4(d + 4 * k);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x.v[e] += (double)c.v[e];
+    st4(u + 4 * k, x);
+  }
+}
+
+template <class T>
+void launch_commit(double* u, const T* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(commit_kernel<T>, dim3(elementwise_blocks(n)), dim3(kThreads), 0, s, u, d,
+                     n / 4);
+}
+template void launch_commit<float>(double*, const float*, int64_t, hipStream_t);
+template void launch_commit<double>(double*, const double*, int64_t, hipStream_t);
 
 // Copy the (mean-zero) internal U to the caller's N x M buffer.
 template <class T>

@@ -15,42 +15,6 @@
 
 namespace irlsu {
 
-template <class T>
-struct V4 {
-  T v[4];
-};
-
-template <class T>
-__device__ __forceinline__ V4<T> ld4(const T* p) {
-  V4<T> r;
-  if constexpr (sizeof(T) == 4) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
-  } else {
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
-  }
-  return r;
-}
-
-template <class T>
-__device__ __forceinline__ void st4(T* p, const V4<T>& r) {
-  if constexpr (sizeof(T) == 4) {
-    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
-  } else {
-    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
-    *reinterpret_cast<double2*>(p + 2) = make_double2(r.v[2], r.v[3]);
-  }
-}
-
-template <class T>
-__device__ __forceinline__ V4<T> zero4() {
-  V4<T> r;
-  r.v[0] = r.v[1] = r.v[2] = r.v[3] = (T)0;
-  return r;
-}
-
 // CT: compute type (double in the residual mode, where u is FP64).
 template <class T, int MODE>
 struct StencilIO {
@@ -70,7 +34,7 @@ struct StencilIO {
     } else if constexpr (MODE == ST_APPLY) {
       return (CT)a.p_in[o];
     } else {
-      return (CT)a.u[o];
+      return (CT)a.u[o] + (a.d ? (CT)a.d[o] : (CT)0);
     }
   }
 
@@ -96,8 +60,9 @@ struct StencilIO {
       for (int e = 0; e < 4; ++e) r.v[e] = (CT)p.v[e];
     } else {
       const V4<double> u = ld4(a.u + o);
+      const V4<T> d = a.d ? ld4(a.d + o) : zero4<T>();
 #pragma unroll
-      for (int e = 0; e < 4; ++e) r.v[e] = (CT)u.v[e];
+      for (int e = 0; e < 4; ++e) r.v[e] = (CT)u.v[e] + (CT)d.v[e];
     }
     return r;
   }

@@ -75,7 +75,11 @@ def test_f64_history_matches_oracle(gen, shape):
         # precision CG delays), so only the attained residual is compared
         assert st["history"][k]["relres"] <= 1e-10
     assert abs(st["L1_final"] - hist[-1]["L1"]) <= L1_RTOL["f64"] * hist[-1]["L1"]
-    assert np.abs(Ug - Uo).max() < 1e-6
+    # U itself only loosely: the stop rule bounds the residual (1e-10 ||b||),
+    # and the weighted operator's condition number (weights up to 1/eps,
+    # Laplacian modes down to (pi/n)^2) lets two solves that both meet it
+    # differ in U by orders of magnitude more; parity is on the objectives
+    assert np.abs(Ug - Uo).max() < 1e-5 * np.abs(Uo).max()
     H = [h["H"] for h in st["history"][:K]] + [st["H_final"]]
     assert all(H[k + 1] <= H[k] * (1 + 1e-12) for k in range(K))
 
@@ -104,7 +108,7 @@ def test_folded_plan_objective(prec):
     assert gap <= L1_RTOL[prec]
     assert abs(Ug.mean()) < (1e-12 if prec == "f64" else 1e-5)
     if prec == "f64":
-        assert np.abs(Ug - Uo).max() < 1e-6
+        assert np.abs(Ug - Uo).max() < 1e-5 * np.abs(Uo).max()  # objectives are the parity; see above
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
@@ -119,7 +123,7 @@ def test_fast_plan_objective(prec):
     assert gap <= L1_RTOL[prec]
     assert abs(Ug.mean()) < (1e-12 if prec == "f64" else 1e-5)
     if prec == "f64":
-        assert np.abs(Ug - Uo).max() < 1e-6
+        assert np.abs(Ug - Uo).max() < 1e-5 * np.abs(Uo).max()  # objectives are the parity; see above
 
 
 def test_two_by_two_single_loop_closed_form():
