@@ -35,7 +35,7 @@ PEAK = {  # MI355X published dense peaks
     "bf16": 2500.0, "f16": 2500.0, "f32": 157.3, "f64": 78.6,  # TFLOP/s
 }
 CONFIGS = {
-    "c3": dict(gen="field_c3", N=8192, precision="bf16", ref="c3_seed0_8192_float32.json",
+    "c3": dict(gen="field_c3", N=8192, precision="f16", ref="c3_seed0_8192_float32.json",
                desc="fringe-dense Gaussian-sum phase (+-400 rad), N(0,0.7^2) noise, 2% salt, "
                     "Beta(2,2) weights"),
     "c2": dict(gen="field_c2", N=2048, precision="f32", ref="c2_seed0_2048_float32.json",
@@ -134,44 +134,59 @@ def time_stencil(plan, torch, reps=20):
     return e0.elapsed_time(e1) / reps
 
 
-# kernel name, algorithmic bytes per pixel (vector type of e bytes) per launch
-# kind of the fast form; products are priced in flops instead
-FAST_KERNELS = {"rows_dct2": ("fct_rows_fwd_kernel", 2), "transpose": ("transpose_kernel", 2),
-                "cols": ("fct_cols_kernel", 2), "rows_dct3": ("fct_rows_inv_kernel", 3)}
-
-
-def kernel_table(plan, launches, ms_st, prec, N, M):
-    """Time per PCG iteration of each kernel of the preconditioner and of
-    the stencil, with its algorithmic work: bytes for the HBM-bound passes
-    (the fast form's transforms and transposes, the stencil's 16 B/px),
-    dense-equivalent flops 4NM(N+M) per application for the MFMA products."""
+def kernel_table(launches, prec, form, N, M, flexible):
+    """Kernels of one PCG iteration (as recorded inside the unwrap) with
+    their time and algorithmic work: bytes per launch for the HBM-bound
+    kernels (e = vector element bytes, s = bytes of the fast form's stored
+    intermediates), dense-equivalent flops 4NM(N+M) per application for the
+    MFMA products."""
     e = 8 if prec == "f64" else 4
+    s = 2 if (form == "fast" and prec in ("bf16", "f16")) else e
     px = N * M
-    out = {}
+    bpp = {  # kind -> (kernel, bytes per pixel)
+        "stencil": ("stencil_kernel", 6 * e),              # z, p_old, Ov, Oh in; p, q out
+        "axpy": ("axpy_kernel", 6 * e),                    # p, q, r, d in; r, d out
+        "residual": ("stencil_kernel(residual)", 8 + 5 * e),  # u, d, b, Ov, Oh in; r out
+        "rows_dct2": ("fct_rows_fwd_kernel", e + s),        # r in; T1 out
+        "transpose": ("transpose_kernel", 2 * s),
+        "cols": ("fct_cols_kernel", 2 * s),
+        "rows_dct3": ("fct_rows_inv_kernel", s + (3 if flexible else 2) * e),  # T, r, (q) in; z out
+    }
     n_prod = sum(1 for k, _ in launches if k == "product")
+    out = {}
     for kind, ms in launches:
         if kind == "product":
-            name = "gemm_nt_kernel"
-            ent = out.setdefault(name, {"bound": "mfma", "launches": 0, "ms": 0.0,
-                                        "flops_per_launch": 4.0 * px * (N + M) / n_prod,
-                                        "folded": n_prod == 8})
-        elif kind in FAST_KERNELS:
-            name, bpp = FAST_KERNELS[kind]
+            ent = out.setdefault("gemm_nt_kernel", {"bound": "mfma", "launches": 0, "ms": 0.0,
+                                                    "flops_per_launch": 4.0 * px * (N + M) / n_prod,
+                                                    "folded": n_prod == 8})
+        elif kind in bpp:
+            name, b = bpp[kind]
             ent = out.setdefault(name, {"bound": "hbm", "launches": 0, "ms": 0.0,
-                                        "bytes_per_launch": bpp * e * px})
+                                        "bytes_per_launch": b * px})
         else:
-            name = kind
-            ent = out.setdefault(name, {"bound": "other", "launches": 0, "ms": 0.0})
+            ent = out.setdefault(kind, {"bound": "other", "launches": 0, "ms": 0.0})
         ent["launches"] += 1
         ent["ms"] += ms
-    out["stencil_kernel"] = {"bound": "hbm", "launches": 1, "ms": ms_st,
-                             "bytes_per_launch": 16 * px * e // 4}
     for ent in out.values():
         ent["ms"] = round(ent["ms"], 4)
     return out
 
 
-def roofline(kern, prec):
+def profiled_traffic(config, N, prec, form):
+    """HBM bytes per launch of each kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, if there is one."""
+    path = os.path.join(ROOT, "profiles", f"{config}_{N}_{prec}_{form}_hbm_traffic.md")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 3 and f[0] == "traffic":
+                    out[f[1]] = int(f[2])
+    return out
+
+
+def roofline(kern, prec, traffic=None):
     """Roofline object of the dominant kernel (largest time per iteration)."""
     name, ent = max(((k, v) for k, v in kern.items() if v["bound"] != "other"),
                     key=lambda kv: kv[1]["ms"])
@@ -188,9 +203,70 @@ def roofline(kern, prec):
                 "ms_per_launch": round(ms_launch, 4), "launches_per_iter": ent["launches"]}
     ach = ent["bytes_per_launch"] / (ms_launch * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"],
-            "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBps"], 4),
+            "traffic": (traffic or {}).get(name),
             "bytes_per_launch": ent["bytes_per_launch"], "ms_per_launch": round(ms_launch, 4),
             "launches_per_iter": ent["launches"]}
+
+
+def dtype_label(prec, form):
+    """Arithmetic of the path: preconditioner / CG vectors / CG scalars."""
+    if prec in ("f64", "f32"):
+        return prec
+    if form == "fast":
+        return f"{prec}-storage+f32-transform/f32-vectors/f64-scalars"
+    return f"{prec}-mfma/f32-vectors/f64-scalars"
+
+
+def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a):
+    """Warm-up and timed unwraps with one plan form, then the per-kernel
+    table of one PCG iteration."""
+    t0 = time.perf_counter()
+    plan = pkg.Plan(N, M, prec, form=form)
+    plan_s = time.perf_counter() - t0
+    p = pkg.default_params(prec)
+    p.irls_iters = a.max_irls
+    p.pcg_max = ref["maxit"]
+    p.eps = ref["eps"]
+    p.l1_target = target
+    dt = torch.float64 if prec == "f64" else torch.float32
+    U = torch.empty((N, M), dtype=dt, device="cuda")
+    # per-launch events of one PCG iteration (mid-solve of the second IRLS
+    # iteration) recorded inside the first warm-up unwrap
+    plan.profile_arm(1, min(50, p.pcg_max - 2))
+    for i in range(a.warmup):
+        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+        if i == 0:
+            launches = plan.profile_result()
+            plan.profile_arm(-1, -1)
+        print(f"[bench] {plan.form} warmup {i}: irls={st['irls_done']} pcg={st['pcg_total']} "
+              f"hit={st['target_hit']}", file=sys.stderr, flush=True)
+        if i == 0:
+            traj = " ".join(f"{h['L1'] / ref['L1_final'] - 1:.2e}"
+                            for h in st["history"][:st["irls_done"] + 1])
+            print(f"[bench] {plan.form} L1/L1_ref - 1 by IRLS iteration: {traj}", file=sys.stderr,
+                  flush=True)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    runs = []
+    for i in range(a.steps):
+        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+        runs.append(st)
+        print(f"[bench] {plan.form} step {i}: irls={st['irls_done']} pcg={st['pcg_total']} "
+              f"hit={st['target_hit']}", file=sys.stderr, flush=True)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    flexible = prec in ("bf16", "f16")
+    kern = kernel_table(launches, prec, plan.form, N, M, flexible)
+    pre = ("stencil", "axpy", "residual")
+    return {"plan": plan, "plan_s": plan_s, "form": plan.form, "ms": ms,
+            "hit": all(r["target_hit"] for r in runs), "last": runs[-1], "kern": kern,
+            "roof": roofline(kern, prec, profiled_traffic(a.config, N, prec, plan.form)),
+            "iter_ms": round(sum(t for _, t in launches), 4),
+            "precond_ms": round(sum(t for k, t in launches if k not in pre), 4)}
 
 
 def kernels_only(pkg, torch, N, M, prec):
@@ -201,7 +277,7 @@ def kernels_only(pkg, torch, N, M, prec):
     r[N:, :] = 0
     r[:, M:] = 0
     launches = plan.precond_timed(r, reps=3)
-    ms_st = time_stencil(plan, torch, reps=3)
+    ms_st = time_stencil(plan, torch, reps=3)   # plain operator form, 16 B/px
     nbytes = 256 << 20
     x = torch.empty(nbytes // 4, dtype=torch.float32, device=plan.device).uniform_()
     y = torch.empty_like(x)
@@ -220,18 +296,25 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1, help="at least 1 (it records the kernel table)")
     ap.add_argument("--config", choices=sorted(CONFIGS), default="c3")
     ap.add_argument("--precision", choices=["f64", "f32", "bf16", "f16"], default=None)
+    ap.add_argument("--form", choices=["auto", "dense", "folded", "fast"], default="auto",
+                    help="preconditioner form of the primary measurement")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--gap", type=float, default=1e-3)
     ap.add_argument("--max-irls", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mfma-form", action="store_true",
+                    help="skip the second measurement with the MFMA preconditioner")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="3 device copies of 256 MiB first (hardware-counter byte calibration)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="a short fixed launch sequence for hardware-counter runs: "
                          "3 preconditioner applications, 3 stencil applications and 3 "
                          "copies of 256 MiB (the byte-count calibration)")
     a = ap.parse_args(argv)
+    a.warmup = max(1, a.warmup)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU path is "
               "not part of this build", file=sys.stderr)
@@ -246,6 +329,14 @@ def main(argv=None):
     N = M = cfg["N"]
     if a.kernels_only:
         return kernels_only(pkg, torch, N, M, prec)
+    if a.copy_calibration:
+        torch.cuda.set_device(0)
+        xc = torch.empty((256 << 20) // 4, dtype=torch.float32, device="cuda").uniform_()
+        yc = torch.empty_like(xc)
+        for _ in range(3):
+            yc.copy_(xc)
+        torch.cuda.synchronize()
+        del xc, yc
     ref = load_reference(cfg["ref"])
     L1_ref = ref["L1_final"]
     target = L1_ref * (1.0 + a.gap)
@@ -255,51 +346,26 @@ def main(argv=None):
     torch.cuda.set_device(0)
     X = torch.from_numpy(field.X).to(device="cuda", dtype=torch.float32).to(dt)
     w = torch.from_numpy(field.w).to(device="cuda", dtype=torch.float32).to(dt)
-    t0 = time.perf_counter()
-    plan = pkg.Plan(N, M, prec)
-    plan_s = time.perf_counter() - t0
-    p = pkg.default_params(prec)
-    p.irls_iters = a.max_irls
-    p.pcg_max = ref["maxit"]
-    p.eps = ref["eps"]
-    p.l1_target = target
-    U = torch.empty((N, M), dtype=dt, device="cuda")
-
-    stats = None
-    for i in range(a.warmup):
-        _, stats = plan.unwrap(X, w, params=p, out=U, stats=True)
-        print(f"[bench] warmup {i}: irls={stats['irls_done']} pcg={stats['pcg_total']} "
-              f"hit={stats['target_hit']}", file=sys.stderr, flush=True)
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(s)
-    runs = []
-    for i in range(a.steps):
-        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
-        runs.append(st)
-        print(f"[bench] step {i}: irls={st['irls_done']} pcg={st['pcg_total']} "
-              f"hit={st['target_hit']}", file=sys.stderr, flush=True)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
-    hit = all(r["target_hit"] for r in runs)
-    last = runs[-1]
+    primary = measure(pkg, torch, N, M, prec, a.form, X, w, ref, target, a)
+    plan = primary["plan"]
+    # the MFMA route (dense cosine-basis contractions, folded when the sides
+    # are even) measured on the same workload when the primary form is not it
+    mfma = None
+    if plan.form == "fast" and not a.no_mfma_form:
+        plan.close()
+        form = "folded" if (N % 2 == 0 and M % 2 == 0) else "dense"
+        sec = measure(pkg, torch, N, M, prec, form, X, w, ref, target, a)
+        mfma = {"form": form, "value": round(N * M / 1e6 / (sec["ms"] * 1e-3), 4),
+                "ms_per_step": round(sec["ms"], 3), "target_hit": sec["hit"],
+                "irls_iters": sec["last"]["irls_done"], "pcg_iters": sec["last"]["pcg_total"],
+                "ms_per_pcg_iter": round(sec["ms"] / max(1, sec["last"]["pcg_total"]), 4),
+                "roofline": sec["roof"], "precond_ms": sec["precond_ms"]}
+        sec["plan"].close()
+    ms, hit, last, roof, kern = (primary["ms"], primary["hit"], primary["last"], primary["roof"],
+                                 primary["kern"])
     L1_reached = last["history"][last["irls_done"]]["L1"] if hit else last["L1_final"]
-
-    # per-launch HIP-event timing of one preconditioner application on the
-    # launch stream, and the stencil; the dominant kernel is the one with
-    # the largest time per PCG iteration
-    rr = torch.randn((plan.Np, plan.ld), dtype=plan.dtype, device=plan.device)
-    rr[N:, :] = 0
-    rr[:, M:] = 0
-    plan.precond_timed(rr, reps=1)
-    launches = plan.precond_timed(rr, reps=5)
-    ms_st = time_stencil(plan, torch)
-    kern = kernel_table(plan, launches, ms_st, prec, N, M)
-    roof = roofline(kern, prec)
-
     pcg_per_step = last["pcg_total"]
+    form_used = primary["form"]
     line = {
         "metric": "Mpixel/s unwrapped (8192^2 to 1e-3 rel. L1 gap), mixed vs FP64-plain; HBM GB/s",
         "value": round(N * M / 1e6 / (ms * 1e-3), 4),
@@ -307,25 +373,27 @@ def main(argv=None):
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16": "bf16-mfma/f32-vectors/f64-scalars", "f16": "f16-mfma/f32-vectors/f64-scalars",
-                  "f32": "f32", "f64": "f64"}[prec],
+        "dtype": dtype_label(prec, form_used),
         "data": "synthetic",
         "config": {"workload": f"{a.config} seed {a.seed}: {N}x{M} {cfg['desc']}",
                    "precision": prec, "L1_target_rel_gap": a.gap, "L1_ref": L1_ref,
                    "L1_reached": L1_reached, "target_hit": hit,
                    "irls_iters": last["irls_done"], "pcg_iters": pcg_per_step,
                    "ms_per_pcg_iter": round(ms / max(1, pcg_per_step), 4),
-                   "plan_create_s": round(plan_s, 3)},
+                   "plan_create_s": round(primary["plan_s"], 3)},
         "roofline": roof,
         "kernels": kern,
-        "precond_form": plan.form,
-        "precond_ms": round(sum(ms for _, ms in launches), 4),
+        "precond_form": form_used,
+        "precond_ms": primary["precond_ms"],
+        "iteration_ms_recorded": primary["iter_ms"],
+        "mfma_form": mfma,
     }
     if not a.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(field, ref, target)
     print(json.dumps(line), flush=True)
-    plan.close()
+    if mfma is None:
+        plan.close()
     return 0
 
 

@@ -291,7 +291,7 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
 irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
                            void* workspace, size_t workspace_bytes, void* stream);
 
-/* Kinds of launch reported by irlsu_precond_timed. */
+/* Kinds of launch reported by irlsu_precond_timed and irlsu_profile_result. */
 #define IRLSU_MAX_LAUNCHES 32
 enum {
   IRLSU_LK_PRODUCT = 0,    /* MFMA product with the cosine basis (dense / folded) */
@@ -302,7 +302,10 @@ enum {
   IRLSU_LK_BUTTERFLY = 5,  /* folded form: sum / difference pass */
   IRLSU_LK_DOTS = 6,       /* z.r, z.q, sum z pass (with the recombination when folded) */
   IRLSU_LK_PROLOGUE = 7,   /* convergence test and input scale */
-  IRLSU_LK_PARTIALS = 8    /* fold of per-block partial sums */
+  IRLSU_LK_PARTIALS = 8,   /* fold of per-block partial sums */
+  IRLSU_LK_STENCIL = 9,    /* p = z + beta p, q = D^T Omega D p, p.q (PCG loop form) */
+  IRLSU_LK_AXPY = 10,      /* alpha, d += alpha p, r -= alpha q, ||r||^2 */
+  IRLSU_LK_RESIDUAL = 11   /* true-residual refresh r = b - A (u + d) */
 };
 
 /* Timing of the preconditioner of Section 3.3 (the products named there as
@@ -318,6 +321,21 @@ irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
                                  void* workspace, size_t workspace_bytes, int32_t reps,
                                  double* ms_launch, int32_t* kind, int32_t* n_launches,
                                  void* stream);
+
+/* Timing aid for one iteration of Algorithm 2 inside irlsu_unwrap: arms the
+ * plan so that the next irlsu_unwrap records a HIP event on its stream after
+ * every launch of PCG iteration pcg_l of IRLS iteration irls_k (operator,
+ * axpy, true-residual refresh if due, preconditioner passes).  A negative
+ * index disarms.  The recording stays with the plan until the next arm.
+ * Errors: ERR_INVALID_ARG (null plan), ERR_OOM, ERR_HIP. */
+irlsu_status irlsu_profile_arm(irlsu_plan* plan, int32_t irls_k, int32_t pcg_l);
+
+/* Durations (ms) and IRLSU_LK_* kinds of the launches recorded for the armed
+ * iteration, in launch order (at most IRLSU_MAX_LAUNCHES); *n_launches = 0
+ * when the iteration was not reached.  Waits for the recorded events.
+ * Errors: ERR_INVALID_ARG (null argument), ERR_HIP. */
+irlsu_status irlsu_profile_result(irlsu_plan* plan, double* ms_launch, int32_t* kind,
+                                  int32_t* n_launches);
 
 #ifdef __cplusplus
 }

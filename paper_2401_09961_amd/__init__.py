@@ -31,7 +31,8 @@ DECLARED_SYMBOLS = (
     "irlsu_status_string", "irlsu_params_default", "irlsu_plan_create",
     "irlsu_plan_create_ex", "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
     "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
-    "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_batch_create", "irlsu_batch_destroy",
+    "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_profile_arm",
+    "irlsu_profile_result", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
 )
 
@@ -102,7 +103,8 @@ class PlanDesc(ctypes.Structure):
 PLAN_FORMS = {"auto": 0, "dense": 1, "folded": 2, "fast": 3}
 IRLSU_MAX_LAUNCHES = 32
 LAUNCH_KINDS = {0: "product", 1: "rows_dct2", 2: "transpose", 3: "cols", 4: "rows_dct3",
-                5: "butterfly", 6: "dots", 7: "prologue", 8: "partials"}
+                5: "butterfly", 6: "dots", 7: "prologue", 8: "partials", 9: "stencil",
+                10: "axpy", 11: "residual"}
 
 
 _lib = None
@@ -145,6 +147,9 @@ def load_library():
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
         "irlsu_precond_timed": (I32, [P, P, P, P, SZ, I32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
+        "irlsu_profile_arm": (I32, [P, I32, I32]),
+        "irlsu_profile_result": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
+                                       ctypes.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -322,6 +327,20 @@ class Plan:
                                       _ptr(self.workspace), self.workspace.numel(), _stream()),
                "precond")
         return z, rz
+
+    def profile_arm(self, irls_k, pcg_l):
+        """Record per-launch events for PCG iteration pcg_l of IRLS
+        iteration irls_k during the next unwrap (negative: disarm)."""
+        _check(self.lib.irlsu_profile_arm(self.handle, int(irls_k), int(pcg_l)), "profile_arm")
+
+    def profile_result(self):
+        """[(kind, ms)] of the launches recorded for the armed iteration."""
+        ms = (ctypes.c_double * IRLSU_MAX_LAUNCHES)()
+        kind = (ctypes.c_int32 * IRLSU_MAX_LAUNCHES)()
+        n = ctypes.c_int32()
+        _check(self.lib.irlsu_profile_result(self.handle, ms, kind, ctypes.byref(n)),
+               "profile_result")
+        return [(LAUNCH_KINDS[kind[i]], ms[i]) for i in range(n.value)]
 
     def precond_timed(self, r, reps=5):
         """Per-launch HIP-event timing of the preconditioner: a list of

@@ -307,7 +307,7 @@ struct Vec16 {
 // LDS <- rows (even-up / odd-down order), as CT
 template <class CT, class TI, int H>
 __device__ __forceinline__ void stage_in(const TI* __restrict__ in, int64_t ld, int64_t row0,
-                                         CT* v) {
+                                         CT* v, CT scale = (CT)1) {
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   using V = typename Vec16<TI>::type;
   constexpr int W = Vec16<TI>::W;
@@ -325,7 +325,7 @@ __device__ __forceinline__ void stage_in(const TI* __restrict__ in, int64_t ld, 
     const int e0 = (threadIdx.x + i * kThreads) * W;
     const int row = e0 / N, c = e0 % N;
 #pragma unroll
-    for (int t = 0; t < W; ++t) v[pr(row * N + perm<N>(c + t))] = (CT)d[i][t];
+    for (int t = 0; t < W; ++t) v[pr(row * N + perm<N>(c + t))] = (CT)d[i][t] * scale;
   }
 }
 
@@ -339,11 +339,12 @@ __device__ __forceinline__ CT inv_value(const CT* v, int row, int c, CT inv_h) {
 }
 
 // ---- pass 1: DCT-II along rows ------------------------------------------
-template <class CT, class TI, int H>
+template <class CT, class TI, class TO, int H>
 __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __restrict__ in,
-                                                               int64_t ld, CT* __restrict__ out,
+                                                               int64_t ld, TO* __restrict__ out,
                                                                const void* twp,
-                                                               const int32_t* done) {
+                                                               const int32_t* done,
+                                                               const double* dscale) {
   if (*done) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
   const Tw<CT> tw = tw_of<CT, H>(twp);
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  stage_in<CT, TI, H>(in, ld, row0, v);
+  stage_in<CT, TI, H>(in, ld, row0, v, dscale ? (CT)*dscale : (CT)1);
   __syncthreads();
   fft_rows<CT, H, ROWS>(buf, tw.fft);
   const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
@@ -363,12 +364,12 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
       const int row = p / NP, k = p % NP;
       Cx<CT> ck, cp;
       post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
-      CT* o = out + (row0 + row) * ld;
-      o[k] = ck.x * (k == 0 ? s0 : s1);
-      if (k > 0) o[N - k] = -ck.y * s1;
+      TO* o = out + (row0 + row) * ld;
+      o[k] = (TO)(ck.x * (k == 0 ? s0 : s1));
+      if (k > 0) o[N - k] = (TO)(-ck.y * s1);
       if (H - k != k) {
-        o[H - k] = cp.x * s1;
-        if (k > 0) o[H + k] = -cp.y * s1;
+        o[H - k] = (TO)(cp.x * s1);
+        if (k > 0) o[H + k] = (TO)(-cp.y * s1);
       }
     }
   }
@@ -376,8 +377,8 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
 
 // ---- pass 3: DCT-II, spectral division, DCT-III along rows of the
 // transposed intermediate (the columns of the image) ----------------------
-template <class CT, int H>
-__global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io, int64_t ld,
+template <class CT, class ST, int H>
+__global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io, int64_t ld,
                                                            const void* twp,
                                                            const double* __restrict__ eig_k,
                                                            const double* __restrict__ eig_l,
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io,
   const Tw<CT> tw = tw_of<CT, H>(twp);
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  stage_in<CT, CT, H>(io, ld, row0, v);
+  stage_in<CT, ST, H>(io, ld, row0, v);
   __syncthreads();
   fft_rows<CT, H, ROWS>(buf, tw.fft);
   // forward post-processing, division and inverse pre-processing of pair
@@ -420,8 +421,8 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io,
   __syncthreads();
   fft_rows<CT, H, ROWS>(buf, tw.fft);
   const CT inv_h = (CT)(1.0 / H);
-  using V = typename Vec16<CT>::type;
-  constexpr int W = Vec16<CT>::W;
+  using V = typename Vec16<ST>::type;
+  constexpr int W = Vec16<ST>::W;
   constexpr int NCH = ROWS * N / W / kThreads;
 #pragma unroll
   for (int i = 0; i < NCH; ++i) {
@@ -429,16 +430,16 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(CT* __restrict__ io,
     const int row = e0 / N, c = e0 % N;
     V o;
 #pragma unroll
-    for (int t = 0; t < W; ++t) o[t] = inv_value<CT, N>(v, row, c + t, inv_h);
+    for (int t = 0; t < W; ++t) o[t] = (ST)inv_value<CT, N>(v, row, c + t, inv_h);
     *reinterpret_cast<V*>(io + (row0 + row) * ld + c) = o;
   }
 }
 
 // ---- pass 5: DCT-III along rows, z.r, z.q, sum z -------------------------
-template <class CT, class TO, int H>
+template <class CT, class SI, class TO, int H>
 __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
-    const CT* __restrict__ in, int64_t ld, TO* __restrict__ z, const TO* __restrict__ r,
-    const TO* __restrict__ q, const void* twp, DevState st) {
+    const SI* __restrict__ in, int64_t ld, TO* __restrict__ z, const TO* __restrict__ r,
+    const TO* __restrict__ q, const void* twp, DevState st, int use_scale) {
   if (st.fl[FL_DONE]) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
@@ -446,7 +447,9 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
   CT* v = reinterpret_cast<CT*>(buf);
-  const CT inv_h = (CT)(1.0 / H);
+  // output scale: 1/h of the inverse FFT, undoing the input scale of the
+  // first pass when the intermediates are FP16
+  const CT inv_h = (CT)(1.0 / H) / (use_scale ? (CT)st.sc[SC_SCALE] : (CT)1);
   const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
 #pragma unroll
@@ -454,11 +457,11 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
     const int p = threadIdx.x + qq * kThreads;
     if (p < ROWS * NP) {
       const int row = p / NP, k = p % NP;
-      const CT* x = in + (row0 + row) * ld;
-      const CT xk = x[k] * (k == 0 ? is0 : is1);
-      const CT xnk = k > 0 ? x[N - k] * is1 : (CT)0;
-      const CT xp = x[H - k] * is1;
-      const CT xnp = x[H + k] * is1;
+      const SI* x = in + (row0 + row) * ld;
+      const CT xk = (CT)x[k] * (k == 0 ? is0 : is1);
+      const CT xnk = k > 0 ? (CT)x[N - k] * is1 : (CT)0;
+      const CT xp = (CT)x[H - k] * is1;
+      const CT xnp = (CT)x[H + k] * is1;
       pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf, row * H);
     }
   }
@@ -514,21 +517,32 @@ __global__ __launch_bounds__(kFoldThreads) void fct_fold_partials_kernel(DevStat
   }
 }
 
-// ---- transpose (64 x 64 tiles through LDS) -------------------------------
+// ---- transpose (square tiles through LDS) -------------------------------
 // 16-byte loads along the input rows and 16-byte stores along the output
-// rows; every load of a thread is issued before its first LDS write.
+// rows; every load of a thread is issued before its first LDS write.  Tiles
+// are 64 x 64 for 4- and 8-byte elements, 128 x 128 for 16-bit ones (32 KB
+// of LDS either way).
+template <class T>
+constexpr int transpose_tile() {
+  return sizeof(T) == 2 ? 128 : 64;
+}
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, int64_t ldin,
                                                             T* __restrict__ out, int64_t ldout,
                                                             const int32_t* done) {
   if (*done) return;
   using V = typename Vec16<T>::type;
+  constexpr int TL = transpose_tile<T>();
   constexpr int W = Vec16<T>::W;
-  constexpr int CPR = 64 / W;            // chunks per tile row
+  constexpr int CPR = TL / W;            // chunks per tile row
   constexpr int RPP = kThreads / CPR;    // tile rows per pass
-  constexpr int NPASS = 64 / RPP;
-  __shared__ T tile[64][64 + 1];
-  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  constexpr int NPASS = TL / RPP;
+  // row pitch TL + 2 elements: 16-bit tiles keep the column reads of a wave
+  // on distinct 4-byte banks
+  constexpr int PITCH = TL + (sizeof(T) == 2 ? 2 : 1);
+  __shared__ T tile[TL][PITCH];
+  const int64_t r0 = (int64_t)blockIdx.y * TL, c0 = (int64_t)blockIdx.x * TL;
   const int cq = threadIdx.x % CPR, rr = threadIdx.x / CPR;
   V d[NPASS];
 #pragma unroll
@@ -547,6 +561,14 @@ __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict
     for (int t = 0; t < W; ++t) o[t] = tile[cq * W + t][jrow];
     *reinterpret_cast<V*>(out + (c0 + jrow) * ldout + r0 + cq * W) = o;
   }
+}
+
+template <class T>
+static void launch_transpose(const T* in, int64_t rows, int64_t cols, T* out,
+                             const int32_t* done, hipStream_t s) {
+  constexpr int TL = transpose_tile<T>();
+  hipLaunchKernelGGL(transpose_kernel<T>, dim3((unsigned)(cols / TL), (unsigned)(rows / TL)),
+                     dim3(kThreads), 0, s, in, cols, out, rows, done);
 }
 
 // ---- tables -----------------------------------------------------------------
@@ -605,44 +627,47 @@ static void with_h(int64_t h, F&& f) {
   }
 }
 
-template <class CT>
+// CT: transform arithmetic; T: vector type (r, z, q); ST: storage of the
+// two N x M intermediates (the plan's operand type: 16-bit for mixed plans,
+// with the FP16 input scale of the prologue)
+template <class CT, class T, class ST>
 static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   const int64_t N = a.N, M = a.M;
-  const CT* r = static_cast<const CT*>(a.r);
-  CT* z = static_cast<CT*>(a.z);
-  const CT* q = static_cast<const CT*>(a.q);
-  CT* T1 = static_cast<CT*>(a.T1);
-  CT* T2 = static_cast<CT*>(a.T2);
+  const T* r = static_cast<const T*>(a.r);
+  T* z = static_cast<T*>(a.z);
+  const T* q = static_cast<const T*>(a.q);
+  ST* T1 = static_cast<ST*>(a.T1);
+  ST* T2 = static_cast<ST*>(a.T2);
   const int32_t* done = a.st.fl + FL_DONE;
+  const int f16 = std::is_same<ST, _Float16>::value ? 1 : 0;
   LaunchLog* L = a.log;
   log_start(L, s);
-  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, 0, N * M, s);
+  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
   log_mark(L, IRLSU_LK_PROLOGUE, s);
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
-    hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, CT, H>), dim3((unsigned)(N / rows_per_block<H>())),
-                       dim3(kThreads), 0, s, r, M, T1, a.twM, done);
+    hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, T, ST, H>),
+                       dim3((unsigned)(N / rows_per_block<H>())), dim3(kThreads), 0, s, r, M, T1,
+                       a.twM, done, f16 ? a.st.sc + SC_SCALE : nullptr);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT2, s);
-  hipLaunchKernelGGL(transpose_kernel<CT>, dim3((unsigned)(M / 64), (unsigned)(N / 64)),
-                     dim3(kThreads), 0, s, T1, M, T2, N, done);
+  launch_transpose<ST>(T1, N, M, T2, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
   with_h(N / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
-    hipLaunchKernelGGL((fct_cols_kernel<CT, H>), dim3((unsigned)(M / rows_per_block<H>())),
+    hipLaunchKernelGGL((fct_cols_kernel<CT, ST, H>), dim3((unsigned)(M / rows_per_block<H>())),
                        dim3(kThreads), 0, s, T2, N, a.twN, static_cast<const double*>(a.eigN),
                        static_cast<const double*>(a.eigM), done);
   });
   log_mark(L, IRLSU_LK_COLS, s);
-  hipLaunchKernelGGL(transpose_kernel<CT>, dim3((unsigned)(N / 64), (unsigned)(M / 64)),
-                     dim3(kThreads), 0, s, T2, N, T1, M, done);
+  launch_transpose<ST>(T2, M, N, T1, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
   int nb = 0;
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
     nb = (int)(N / rows_per_block<H>());
-    hipLaunchKernelGGL((fct_rows_inv_kernel<CT, CT, H>), dim3((unsigned)nb), dim3(kThreads), 0, s,
-                       T1, M, z, r, q, a.twM, a.st);
+    hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H>), dim3((unsigned)nb), dim3(kThreads), 0,
+                       s, T1, M, z, r, q, a.twM, a.st, f16);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT3, s);
   hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, a.st, nb);
@@ -651,8 +676,13 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
 }
 
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s) {
-  if (a.kind == OK_F64) return fast_impl<double>(a, s);
-  return fast_impl<float>(a, s);
+  switch (a.kind) {
+    case OK_F64: return fast_impl<double, double, double>(a, s);
+    case OK_F32: return fast_impl<float, float, float>(a, s);
+    case OK_BF16: return fast_impl<float, float, __bf16>(a, s);
+    case OK_F16: return fast_impl<float, float, _Float16>(a, s);
+  }
+  return 0;
 }
 
 }  // namespace irlsu

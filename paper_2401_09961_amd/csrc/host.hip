@@ -41,6 +41,9 @@ struct irlsu_plan {
   // fast preconditioner (power-of-two N and M): twiddle tables
   int fast = 0;
   void *twN = nullptr, *twM = nullptr;
+  // timing aid: events of one armed PCG iteration (irlsu_profile_arm)
+  int prof_k = -1, prof_l = -1;
+  LaunchLog* prof = nullptr;
   // folded preconditioner (even N and M)
   int folded = 0;
   int64_t hNp = 0, hMp = 0;
@@ -101,7 +104,7 @@ Layout layout(const irlsu_plan* p) {
   // ping-pong buffers of 2 hNp x 2 hMp and an Np x 2 hMp vector-type buffer
   // (fast form: two N x M buffers of the vector type)
   const size_t inter = p->folded ? (size_t)(2 * p->hNp) * (size_t)(2 * p->hMp) : npx;
-  const size_t isz = p->fast ? p->elem : p->opsz;
+  const size_t isz = p->opsz;
   L.t1 = off;
   off = align_up(off + inter * isz);
   L.t2 = off;
@@ -240,7 +243,7 @@ irlsu_status read_back(irlsu_plan* pl, const Ws<T>& W, hipStream_t s) {
 template <class T>
 irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
                        const irlsu_params& prm, int flexible, int* iters_out, double* relres_out,
-                       irlsu_status* solve_st, hipStream_t s) {
+                       irlsu_status* solve_st, hipStream_t s, int irls_k = -1) {
   DevState st = W.st;
   const size_t npx = (size_t)pl->Np * (size_t)pl->Mp;
   const int nvec = stencil_blocks(pl);
@@ -260,6 +263,11 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
                                    nvec);
   const int nprec = launch_precond(pa, s);
   for (int l = 0; l < prm.pcg_max; ++l) {
+    LaunchLog* L = (pl->prof && irls_k == pl->prof_k && l == pl->prof_l) ? pl->prof : nullptr;
+    if (L) {
+      L->n = 0;
+      log_start(L, s);
+    }
     StencilArgs<T> fa = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
     fa.z = W.v[V_Z];
     fa.p_in = P[(l + 1) & 1];
@@ -271,6 +279,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     fa.nparts_res = nvec;
     fa.check_done = 1;
     const int npq = launch_stencil<T>(ST_FUSED, fa, s);
+    log_mark(L, IRLSU_LK_STENCIL, s);
     AxpyArgs<T> xa;
     xa.u = x;
     xa.d = d;
@@ -282,11 +291,17 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     xa.iter = l;
     xa.st = st;
     launch_axpy<T>(xa, s, nvec);
+    log_mark(L, IRLSU_LK_AXPY, s);
     if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max) {
       ra.check_done = 1;
       launch_stencil<T>(ST_RESID, ra, s);
+      log_mark(L, IRLSU_LK_RESIDUAL, s);
     }
-    if (l + 1 < prm.pcg_max) launch_precond(pa, s);
+    if (l + 1 < prm.pcg_max) {
+      PrecondArgs pl_args = pa;
+      pl_args.log = L;
+      launch_precond(pl_args, s);
+    }
     if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
     if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
       HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -389,7 +404,7 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
     int iters = 0;
     double relres = 0.0;
     irlsu_status solve_st = IRLSU_OK;
-    rs = pcg_solve<T>(pl, W, W.U, W.v[V_B], prm, flexible, &iters, &relres, &solve_st, s);
+    rs = pcg_solve<T>(pl, W, W.U, W.v[V_B], prm, flexible, &iters, &relres, &solve_st, s, k);
     if (rs != IRLSU_OK) return rs;
     if (stats && k < IRLSU_MAX_IRLS) {
       stats->iter[k].pcg_iters = iters;
@@ -901,6 +916,10 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
 
 irlsu_status irlsu_plan_destroy(irlsu_plan* p) {
   if (!p) return IRLSU_OK;
+  if (p->prof) {
+    for (int i = 0; i <= LaunchLog::kMax; ++i) (void)hipEventDestroy(p->prof->ev[i]);
+    delete p->prof;
+  }
   const bool fshare = p->PeM == p->PeN;
   void* fold_n[] = {p->PeN, p->PeNt, p->PoN, p->PoNt, p->eigNf};
   void* fold_m[] = {p->PeM, p->PeMt, p->PoM, p->PoMt, p->eigMf};
@@ -1152,6 +1171,7 @@ irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
       PrecondArgs a = precond_args<T>(plan, W, static_cast<const T*>(r), static_cast<T*>(z),
                                       nullptr, 0, nrr);
       a.log = &L;
+      L.n = 0;
       launch_precond(a, s);
       HIP_OK(hipEventSynchronize(L.ev[L.n]));
       *n_launches = L.n;
@@ -1168,6 +1188,48 @@ irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
   destroy();
   if (st != IRLSU_OK) return st;
   return last_launch();
+}
+
+irlsu_status irlsu_profile_arm(irlsu_plan* plan, int32_t irls_k, int32_t pcg_l) {
+  if (!plan) return IRLSU_ERR_INVALID_ARG;
+  plan->prof_k = irls_k;
+  plan->prof_l = pcg_l;
+  if (irls_k < 0 || pcg_l < 0) {
+    plan->prof_k = plan->prof_l = -1;
+    return IRLSU_OK;
+  }
+  if (!plan->prof) {
+    LaunchLog* L = new (std::nothrow) LaunchLog;
+    if (!L) return IRLSU_ERR_OOM;
+    int created = 0;
+    for (; created <= LaunchLog::kMax; ++created)
+      if (hipEventCreate(&L->ev[created]) != hipSuccess) break;
+    if (created <= LaunchLog::kMax) {
+      for (int i = 0; i < created; ++i) (void)hipEventDestroy(L->ev[i]);
+      delete L;
+      return IRLSU_ERR_HIP;
+    }
+    plan->prof = L;
+  }
+  plan->prof->n = 0;
+  return IRLSU_OK;
+}
+
+irlsu_status irlsu_profile_result(irlsu_plan* plan, double* ms_launch, int32_t* kind,
+                                  int32_t* n_launches) {
+  if (!plan || !ms_launch || !kind || !n_launches) return IRLSU_ERR_INVALID_ARG;
+  *n_launches = 0;
+  LaunchLog* L = plan->prof;
+  if (!L || L->n == 0) return IRLSU_OK;
+  HIP_OK(hipEventSynchronize(L->ev[L->n]));
+  for (int i = 0; i < L->n; ++i) {
+    float ms = 0.0f;
+    HIP_OK(hipEventElapsedTime(&ms, L->ev[i], L->ev[i + 1]));
+    ms_launch[i] = ms;
+    kind[i] = L->cls[i];
+  }
+  *n_launches = L->n;
+  return IRLSU_OK;
 }
 
 irlsu_status irlsu_batch_destroy(irlsu_batch* b) {

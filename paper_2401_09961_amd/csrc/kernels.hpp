@@ -180,11 +180,10 @@ struct LaunchLog {
   int cls[kMax];
   int n = 0;
 };
+// Opens the log (first event) unless launches are already recorded in it,
+// so a caller can time a sequence that contains a preconditioner.
 inline void log_start(LaunchLog* L, hipStream_t s) {
-  if (L) {
-    L->n = 0;
-    (void)hipEventRecord(L->ev[0], s);
-  }
+  if (L && L->n == 0) (void)hipEventRecord(L->ev[0], s);
 }
 inline void log_mark(LaunchLog* L, int kind, hipStream_t s) {
   if (L && L->n < LaunchLog::kMax) {

@@ -185,3 +185,33 @@ def test_deterministic_and_warm_start():
     _, s2 = plan.unwrap(X, w, U0=U1, params=p, stats=True)
     assert s2["H_final"] <= s1["H_final"] * (1 + 1e-6)
     plan.close()
+
+
+@pytest.mark.parametrize("form", ["fast", "folded", "dense"])
+def test_profile_records_one_pcg_iteration(form):
+    """The armed iteration's launches are the operator, the axpy and the
+    preconditioner's passes of that form, in order, with positive times;
+    the unwrap result is unchanged by the recording."""
+    f = synth.field_c2(6, 256, 256)
+    p = pkg.default_params("f32")
+    p.irls_iters, p.pcg_max = 2, 40
+    X = torch.from_numpy(f.X.astype(np.float32)).cuda()
+    w = torch.from_numpy(f.w.astype(np.float32)).cuda()
+    plan = pkg.Plan(256, 256, "f32", form=form)
+    U0 = plan.unwrap(X, w, params=p)
+    plan.profile_arm(1, 5)
+    U1 = plan.unwrap(X, w, params=p)
+    rec = plan.profile_result()
+    plan.profile_arm(-1, -1)
+    torch.cuda.synchronize()
+    kinds = [k for k, _ in rec]
+    assert kinds[:2] == ["stencil", "axpy"]
+    expect = {"fast": ["prologue", "rows_dct2", "transpose", "cols", "transpose", "rows_dct3",
+                       "partials"],
+              "folded": ["prologue", "butterfly"] + ["product"] * 2 + ["butterfly"]
+              + ["product"] * 4 + ["butterfly"] + ["product"] * 2 + ["dots"],
+              "dense": ["product"] * 4}[form]
+    assert kinds[2:] == expect
+    assert all(ms > 0 for _, ms in rec)
+    assert torch.equal(U0, U1)
+    plan.close()
