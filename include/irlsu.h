@@ -79,8 +79,22 @@ typedef struct irlsu_params {
   int32_t poll_every;      /* host reads the device convergence flag every this many PCG iterations. 4 */
   int32_t flexible;        /* CG beta: 0 = rho_new / rho (Algorithm 2), 1 = flexible
                               (z_new . (r_new - r_old) / rho), -1 = flexible for mixed plans */
-  int32_t reserved[7];
+  int32_t cg_schedule;     /* IRLSU_CG_FIXED (pcg_max per solve) or IRLSU_CG_ADAPTIVE */
+  int32_t cg_m0;           /* adaptive: iteration cap of the first solve, m_CG(0). 5 */
+  int32_t reserved_;
+  double cg_eps_tol;       /* adaptive: significance threshold of Delta. 1e-3 */
+  double cg_alpha;         /* adaptive: cap growth factor. 1.7 */
 } irlsu_params;
+
+/* CG iteration schedules (irlsu_params.cg_schedule).  The adaptive one is
+ * Section 4.3: before solve k >= 1 the relative improvement Delta of the
+ * IRLS model at U^k between the previous and the new weights,
+ *   Delta = (S(U^k, Omega^{k-1}) - S(U^k, Omega^k)) / S(U^k, Omega^{k-1}),
+ *   S(U, Omega) = sum Omega r^2 / 2 + C^2 / (2 Omega), r = DU - G,
+ * keeps the cap (Delta > cg_eps_tol), stops the IRLS loop and returns U^k
+ * (Delta <= cg_eps_tol right after a raise), or raises the cap to
+ * ceil(cg_alpha * cap).  The missing m_CG(-1) is taken equal to m_CG(0). */
+enum { IRLSU_CG_FIXED = 0, IRLSU_CG_ADAPTIVE = 1 };
 
 #define IRLSU_MAX_IRLS 256
 
@@ -90,6 +104,9 @@ typedef struct irlsu_iter_stats {
   double relres;      /* ||r|| / ||b|| of the recursive residual when solve k stopped */
   int32_t pcg_iters;  /* PCG iterations of solve k */
   int32_t status;     /* irlsu_status of solve k */
+  double delta;       /* adaptive schedule: Delta before solve k (k >= 1), else 0 */
+  int32_t pcg_cap;    /* iteration cap of solve k */
+  int32_t reserved_;
 } irlsu_iter_stats;
 
 typedef struct irlsu_stats {
@@ -99,6 +116,8 @@ typedef struct irlsu_stats {
   int32_t status;         /* overall status */
   double L1_final;        /* L1 of the returned U */
   double H_final;         /* Huber objective of the returned U */
+  int32_t schedule_stop;  /* 1 if the adaptive schedule ended the IRLS loop */
+  int32_t reserved_;
   irlsu_iter_stats iter[IRLSU_MAX_IRLS];
 } irlsu_stats;
 

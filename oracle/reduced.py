@@ -152,6 +152,17 @@ def weight_step(U, Gv, Gh, Cv, Ch, eps):
     return Ov, Oh, b, L1, H
 
 
+def surrogate(U, Gv, Gh, Cv, Ch, Ov, Oh):
+    """The quadratic IRLS model at fixed edge weights Omega = C omega, the
+    reduced analogue of the function H(U, W) minimised by the alternating
+    scheme (Section 3.1): sum Omega r^2 / 2 + C^2 / (2 Omega), r = DU - G.
+    Minimised over omega <= 1/eps at omega = 1/max(|r|, eps), where it equals
+    sum C (h_eps(r) + eps/2)."""
+    rv, rh = residuals(U, Gv, Gh)
+    return float(np.sum(Ov * rv * rv / 2.0 + Cv * Cv / (2.0 * Ov))
+                 + np.sum(Oh * rh * rh / 2.0 + Ch * Ch / (2.0 * Oh)))
+
+
 # ----------------------------------------------------------------------------
 # Preconditioner: eigendecomposition of the Neumann Laplacian (Section 3.3)
 # ----------------------------------------------------------------------------
@@ -249,11 +260,17 @@ def pcg(A, Minv, b, x0, tol, maxit):
 # ----------------------------------------------------------------------------
 def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, eps=1e-3, iters=20,
          tol=1e-8, maxit=100, U0=None, precond="dct", workers=None,
-         callback=None):
+         callback=None, schedule=None):
     """Unwrap X (or given gradients G = (Gv, Gh)); return (U, history).
 
     history[k] holds L1 and H_eps at U^k (before solve k) and the solve
     statistics; history[iters] holds L1 and H_eps of the returned U.
+
+    ``schedule`` (an ``oracle.schedule.CgSchedule``) replaces the fixed
+    ``maxit`` by the Section 4.3 rules: before solve k >= 1 the relative
+    improvement Delta of the surrogate at U^k between the previous and the
+    new weights picks the solve's iteration cap, or stops the loop (the
+    returned history then ends with that U's entry, marked stopped=True).
     """
     if G is None:
         Gv, Gh = wrapped_gradients(X)
@@ -271,11 +288,26 @@ def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, eps=1e-3, iters=20,
         raise ValueError(precond)
     U = np.zeros((N, M)) if U0 is None else np.array(U0, np.float64, copy=True)
     hist = []
+    prev = None
     for k in range(iters):
         Ov, Oh, b, L1, H = weight_step(U, Gv, Gh, Cv, Ch, eps)
-        U, info = pcg(lambda p: apply_A(Ov, Oh, p), Minv, b, U, tol, maxit)
+        m, extra = maxit, {}
+        if schedule is not None:
+            m = schedule.current()
+            if prev is not None:
+                s_old = surrogate(U, Gv, Gh, Cv, Ch, *prev)
+                s_new = surrogate(U, Gv, Gh, Cv, Ch, Ov, Oh)
+                delta = (s_old - s_new) / s_old
+                m = schedule.update(delta)
+                extra = dict(delta=delta)
+                if m is None:
+                    hist.append(dict(k=k, L1=L1, H=H, stopped=True, **extra))
+                    return U, hist
+            extra["cap"] = m
+        U, info = pcg(lambda p: apply_A(Ov, Oh, p), Minv, b, U, tol, m)
         U = U - U.mean()
-        rec = dict(k=k, L1=L1, H=H, **info)
+        prev = (Ov, Oh)
+        rec = dict(k=k, L1=L1, H=H, **info, **extra)
         hist.append(rec)
         if callback is not None:
             callback(rec, U)

@@ -56,14 +56,20 @@ class Params(ctypes.Structure):
         ("l1_target", ctypes.c_double), ("irls_iters", ctypes.c_int32),
         ("pcg_max", ctypes.c_int32), ("true_res_every", ctypes.c_int32),
         ("poll_every", ctypes.c_int32), ("flexible", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("cg_schedule", ctypes.c_int32), ("cg_m0", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32), ("cg_eps_tol", ctypes.c_double),
+        ("cg_alpha", ctypes.c_double),
     ]
+
+
+CG_SCHEDULES = {"fixed": 0, "adaptive": 1}
 
 
 class IterStats(ctypes.Structure):
     _fields_ = [("L1", ctypes.c_double), ("H", ctypes.c_double),
                 ("relres", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("delta", ctypes.c_double),
+                ("pcg_cap", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -71,6 +77,7 @@ class Stats(ctypes.Structure):
         ("irls_done", ctypes.c_int32), ("pcg_total", ctypes.c_int32),
         ("target_hit", ctypes.c_int32), ("status", ctypes.c_int32),
         ("L1_final", ctypes.c_double), ("H_final", ctypes.c_double),
+        ("schedule_stop", ctypes.c_int32), ("reserved_", ctypes.c_int32),
         ("iter", IterStats * IRLSU_MAX_IRLS),
     ]
 
@@ -78,10 +85,12 @@ class Stats(ctypes.Structure):
         n = self.irls_done
         hist = [dict(k=k, L1=self.iter[k].L1, H=self.iter[k].H,
                      relres=self.iter[k].relres, iters=self.iter[k].pcg_iters,
-                     status=self.iter[k].status) for k in range(min(n + 1, IRLSU_MAX_IRLS))]
+                     status=self.iter[k].status, delta=self.iter[k].delta,
+                     cap=self.iter[k].pcg_cap) for k in range(min(n + 1, IRLSU_MAX_IRLS))]
         return dict(irls_done=n, pcg_total=self.pcg_total,
                     target_hit=bool(self.target_hit), status=self.status,
-                    L1_final=self.L1_final, H_final=self.H_final, history=hist)
+                    L1_final=self.L1_final, H_final=self.H_final,
+                    schedule_stop=bool(self.schedule_stop), history=hist)
 
 
 class Tile(ctypes.Structure):

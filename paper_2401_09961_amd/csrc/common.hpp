@@ -27,6 +27,8 @@ enum Scalar : int {
   SC_TOL2 = 11,    // pcg_rtol^2
   SC_ZSUM = 12,
   SC_SCALE = 13,   // FP16 preconditioner input scale
+  SC_SOLD = 14,    // IRLS model at U^k with the previous weights
+  SC_SNEW = 15,    // IRLS model at U^k with the new weights
   SC_COUNT = 32
 };
 

@@ -366,7 +366,12 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
 
   const int flexible = prm.flexible < 0 ? (is_mixed(pl->prec) ? 1 : 0) : prm.flexible;
   const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
-  const bool want_obj = stats != nullptr || prm.l1_target > 0.0;
+  const bool adaptive = prm.cg_schedule == IRLSU_CG_ADAPTIVE;
+  const bool want_obj = stats != nullptr || prm.l1_target > 0.0 || adaptive;
+  // iteration caps: fixed, or the Section 4.3 schedule (m_CG(-1) = m_CG(0))
+  int cap = adaptive ? prm.cg_m0 : prm.pcg_max;
+  int cap_prev = cap, cap_prev2 = cap;
+  bool schedule_stop = false;
 
   WeightsArgs<T> wa;
   wa.U = W.U;
@@ -386,8 +391,10 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
   int pcg_total = 0, done_iters = 0;
   bool target_hit = false;
   for (int k = 0; k < prm.irls_iters; ++k) {
+    wa.want_model = (adaptive && k > 0) ? 1 : 0;
     const int nw = launch_weights<T>(wa, s);
-    launch_finalize_weights(st, nw, nullptr, tol2, s);
+    launch_finalize_weights(st, nw, nullptr, tol2, s, wa.want_model);
+    wa.want_model = 0;
     if (want_obj) {
       rs = read_back(pl, W, s);
       if (rs != IRLSU_OK) return rs;
@@ -400,11 +407,29 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
         break;
       }
     }
+    if (adaptive && k > 0) {
+      const double s_old = pl->h_sc[SC_SOLD], s_new = pl->h_sc[SC_SNEW];
+      const double delta = s_old > 0.0 ? (s_old - s_new) / s_old : 0.0;
+      if (stats && k < IRLSU_MAX_IRLS) stats->iter[k].delta = delta;
+      if (delta > prm.cg_eps_tol) {
+        cap = cap_prev;
+      } else if (cap_prev != cap_prev2) {
+        schedule_stop = true;
+        break;
+      } else {
+        cap = (int)std::ceil(prm.cg_alpha * (double)cap_prev);
+      }
+    }
+    if (stats && k < IRLSU_MAX_IRLS) stats->iter[k].pcg_cap = cap;
     // ---- PCG (Algorithm 2), warm start from the current U ----
     int iters = 0;
     double relres = 0.0;
     irlsu_status solve_st = IRLSU_OK;
-    rs = pcg_solve<T>(pl, W, W.U, W.v[V_B], prm, flexible, &iters, &relres, &solve_st, s, k);
+    irlsu_params pk = prm;
+    pk.pcg_max = cap;
+    rs = pcg_solve<T>(pl, W, W.U, W.v[V_B], pk, flexible, &iters, &relres, &solve_st, s, k);
+    cap_prev2 = cap_prev;
+    cap_prev = cap;
     if (rs != IRLSU_OK) return rs;
     if (stats && k < IRLSU_MAX_IRLS) {
       stats->iter[k].pcg_iters = iters;
@@ -431,6 +456,7 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
     stats->L1_final = pl->h_sc[SC_L1];
     stats->H_final = pl->h_sc[SC_H];
     stats->status = overall;
+    stats->schedule_stop = schedule_stop ? 1 : 0;
     if (done_iters < IRLSU_MAX_IRLS) {
       stats->iter[done_iters].L1 = pl->h_sc[SC_L1];
       stats->iter[done_iters].H = pl->h_sc[SC_H];
@@ -787,6 +813,10 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec) {
   p->true_res_every = 32;
   p->poll_every = 4;
   p->flexible = -1;
+  p->cg_schedule = IRLSU_CG_FIXED;
+  p->cg_m0 = 5;
+  p->cg_eps_tol = 1e-3;
+  p->cg_alpha = 1.7;
   return IRLSU_OK;
 }
 
@@ -978,6 +1008,10 @@ irlsu_status irlsu_unwrap(irlsu_plan* plan, const void* X, int64_t ldx, const vo
   }
   if (!(prm.eps > 0.0) || !(prm.pcg_rtol >= 0.0) || prm.irls_iters < 0 || prm.pcg_max < 1 ||
       prm.true_res_every < 0 || prm.poll_every < 0)
+    return IRLSU_ERR_INVALID_ARG;
+  if (prm.cg_schedule != IRLSU_CG_FIXED &&
+      (prm.cg_schedule != IRLSU_CG_ADAPTIVE || prm.cg_m0 < 1 || !(prm.cg_alpha >= 1.0) ||
+       !(prm.cg_eps_tol >= 0.0)))
     return IRLSU_ERR_INVALID_ARG;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -26,6 +26,7 @@ struct WeightsArgs {
   double eps;
   int64_t Np, ld;
   DevState st;
+  int want_model = 0;   // also sum the IRLS model at U with the previous and new weights
 };
 
 template <class T>
@@ -101,7 +102,8 @@ struct StencilArgs;
 
 template <class T> void launch_setup(const SetupArgs<T>& a, hipStream_t s);
 template <class T> int launch_weights(const WeightsArgs<T>& a, hipStream_t s);
-void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s);
+void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s,
+                             int want_model = 0);
 template <class T> int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks);
 // u += d (FP64) over n elements: the end of a solve
 template <class T> void launch_commit(double* u, const T* d, int64_t n, hipStream_t s);

@@ -95,7 +95,7 @@ __device__ __forceinline__ double edge_omega(double c, double r, double eps) {
 template <class T>
 __global__ __launch_bounds__(kThreads) void weights_kernel(WeightsArgs<T> a, int rows_per_block) {
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_block;
   int64_t i1 = i0 + rows_per_block;
   if (i1 > a.Np) i1 = a.Np;
@@ -122,6 +122,15 @@ __global__ __launch_bounds__(kThreads) void weights_kernel(WeightsArgs<T> a, int
         const double ghl = (double)a.Gh[o - 1], chl = (double)a.Ch[o - 1];
         bsum += edge_omega(chl, u - a.U[o - 1] - ghl, eps) * ghl;
       }
+      if (a.want_model) {
+        // S(U, Omega) = sum Omega r^2 / 2 + C^2 / (2 Omega) over the edges
+        // present (C > 0): previous weights (as stored) and new weights
+        auto model = [](double c, double om, double r) {
+          return c > 0.0 ? 0.5 * om * r * r + 0.5 * c * c / om : 0.0;
+        };
+        acc[3] += model(cv, (double)a.Ov[o], rv) + model(ch, (double)a.Oh[o], rh);
+        acc[4] += model(cv, ov, rv) + model(ch, oh, rh);
+      }
       a.Ov[o] = (T)ov;
       a.Oh[o] = (T)oh;
       a.b[o] = (T)bsum;
@@ -133,18 +142,22 @@ __global__ __launch_bounds__(kThreads) void weights_kernel(WeightsArgs<T> a, int
       acc[2] += bt * bt;
     }
   }
-  const int slots[3] = {PR_L1, PR_H, PR_BB};
-  write_partials<3>(a.st, slots, acc, linear_block());
+  const int slots[5] = {PR_L1, PR_H, PR_BB, PT_D, PR_ZQ};
+  write_partials<5>(a.st, slots, acc, linear_block());
 }
 
 // Finalise the weight step: objectives and ||b||^2 into scalars (and an
 // optional user array), reset the PCG flags for the next solve.
 __global__ __launch_bounds__(kThreads) void finalize_weights_kernel(
-    DevState st, int nparts, double* out, double tol2) {
+    DevState st, int nparts, double* out, double tol2, int want_model) {
   const double l1 = reduce_slot(st, PR_L1, nparts);
   const double h = reduce_slot(st, PR_H, nparts);
   const double bb = reduce_slot(st, PR_BB, nparts);
+  const double s_old = want_model ? reduce_slot(st, PT_D, nparts) : 0.0;
+  const double s_new = want_model ? reduce_slot(st, PR_ZQ, nparts) : 0.0;
   if (threadIdx.x == 0) {
+    st.sc[SC_SOLD] = s_old;
+    st.sc[SC_SNEW] = s_new;
     st.sc[SC_L1] = l1;
     st.sc[SC_H] = h;
     st.sc[SC_BB] = bb;
@@ -365,8 +378,10 @@ int launch_weights(const WeightsArgs<T>& a, hipStream_t s) {
   return (int)(grid.x * grid.y);
 }
 
-void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_weights_kernel, dim3(1), dim3(kThreads), 0, s, st, nparts, out, tol2);
+void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s,
+                             int want_model) {
+  hipLaunchKernelGGL(finalize_weights_kernel, dim3(1), dim3(kThreads), 0, s, st, nparts, out, tol2,
+                     want_model);
 }
 
 int elementwise_blocks(int64_t n) {

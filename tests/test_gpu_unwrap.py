@@ -215,3 +215,39 @@ def test_profile_records_one_pcg_iteration(form):
     assert all(ms > 0 for _, ms in rec)
     assert torch.equal(U0, U1)
     plan.close()
+
+
+def test_adaptive_cg_schedule_section_4_3():
+    """Section 4.3 schedule on the GPU (FP64): the caps follow the three
+    rules from the recorded Delta values, Delta >= 0 (the model at the new
+    weights is the minimum over weights), the first Deltas equal the
+    oracle's on the same input (same capped solves in FP64), and a stop
+    comes only right after a raise."""
+    from oracle import schedule as SCH
+    f = synth.field_c3(2, 48, 40)
+    N, M = f.X.shape
+    p = pkg.default_params("f64")
+    p.irls_iters, p.pcg_max, p.pcg_rtol = 60, 100, 1e-12
+    p.cg_schedule = pkg.CG_SCHEDULES["adaptive"]
+    plan = pkg.Plan(N, M, "f64")
+    U, st = plan.unwrap(torch.from_numpy(f.X).cuda(), torch.from_numpy(f.w).cuda(), params=p,
+                        stats=True)
+    plan.close()
+    hist = st["history"]
+    n = st["irls_done"]
+    caps = [hist[k]["cap"] for k in range(n)]
+    deltas = [hist[k]["delta"] for k in range(1, n + (1 if st["schedule_stop"] else 0))]
+    assert caps[0] == 5
+    assert all(d >= -1e-12 for d in deltas)
+    replay = SCH.CgSchedule(5, 1e-3, 1.7)
+    for k in range(1, n):
+        assert replay.update(hist[k]["delta"]) == caps[k], (k, caps)
+    if st["schedule_stop"]:
+        assert replay.update(hist[n]["delta"]) is None
+    assert all(hist[k]["iters"] <= caps[k] for k in range(n))
+    _, ho = R.irls(f.X, w=f.w, iters=60, tol=1e-12, maxit=100,
+                   schedule=SCH.CgSchedule(5, 1e-3, 1.7))
+    for k in range(1, 6):
+        assert abs(hist[k]["delta"] - ho[k]["delta"]) <= 1e-9 * abs(ho[k]["delta"]) + 1e-13, k
+        assert caps[k] == ho[k]["cap"]
+    print(f"adaptive: caps {caps} stop {st['schedule_stop']} L1 {st['L1_final']:.6g}")

@@ -436,6 +436,52 @@ def test_schedule_rules_with_paper_parameters():
     assert s2.update(1e-3) == 9        # Delta == eps_tol counts as not significant
 
 
+def test_surrogate_majorises_huber_and_touches_at_own_weights():
+    """The reduced IRLS model: at its own weights it equals H_eps + eps/2
+    sum C (closed form of the minimum over omega <= 1/eps), at any other
+    positive weights it is larger (so Delta >= 0)."""
+    rng = np.random.default_rng(21)
+    N, M, eps = 9, 7, 1e-2
+    Gv, Gh = rng.uniform(-3, 3, (N - 1, M)), rng.uniform(-3, 3, (N, M - 1))
+    Cv, Ch = rng.uniform(0.2, 2, (N - 1, M)), rng.uniform(0.2, 2, (N, M - 1))
+    U = rng.normal(size=(N, M))
+    U[0, :3] = U[1, :3] + Gv[0, :3] + 1e-3          # a few edges inside the Huber corner
+    rv, rh = R.residuals(U, Gv, Gh)
+    Ov, Oh = Cv / np.maximum(np.abs(rv), eps), Ch / np.maximum(np.abs(rh), eps)
+    s_own = R.surrogate(U, Gv, Gh, Cv, Ch, Ov, Oh)
+    closed = R.huber_objective(U, Gv, Gh, Cv, Ch, eps) + eps / 2 * (Cv.sum() + Ch.sum())
+    assert abs(s_own - closed) <= 1e-12 * closed
+    for _ in range(20):
+        Pv, Ph = Ov * rng.uniform(0.2, 5, Ov.shape), Oh * rng.uniform(0.2, 5, Oh.shape)
+        Pv, Ph = np.minimum(Pv, Cv / eps), np.minimum(Ph, Ch / eps)
+        assert R.surrogate(U, Gv, Gh, Cv, Ch, Pv, Ph) >= s_own * (1 - 1e-14)
+
+
+def test_scheduled_irls_follows_section_4_3_rules():
+    """The schedule-driven oracle: caps follow the rules from the recorded
+    Delta values, every Delta >= 0, the stop comes only after a raise, and
+    the solves use the cap (never more iterations)."""
+    f = synth.field_c3(2, 48, 40)
+    sch = SCH.CgSchedule(5, 1e-3, 1.7)
+    U, hist = R.irls(f.X, w=f.w, iters=60, tol=1e-12, maxit=100, schedule=sch)
+    caps = [h["cap"] for h in hist if "cap" in h]
+    assert caps[0] == 5
+    deltas = [h["delta"] for h in hist if "delta" in h]
+    assert all(d >= -1e-14 for d in deltas)
+    replay = SCH.CgSchedule(5, 1e-3, 1.7)
+    expect = [5]
+    for d in deltas:
+        m = replay.update(d)
+        if m is None:
+            break
+        expect.append(m)
+    assert caps == expect[:len(caps)]
+    assert all(h["iters"] <= h["cap"] for h in hist if "cap" in h and "iters" in h)
+    if hist[-1].get("stopped"):
+        assert caps[-1] != caps[-2] if len(caps) >= 2 else True
+        assert hist[-1]["delta"] <= 1e-3
+
+
 # ---------------------------------------------------------------------------
 # Adjoint of the frozen-weight map against FP64 central differences
 # ---------------------------------------------------------------------------
