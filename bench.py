@@ -188,8 +188,10 @@ def profiled_traffic(config, N, prec, form):
 
 def roofline(kern, prec, traffic=None):
     """Roofline object of the dominant kernel (largest time per iteration)."""
-    name, ent = max(((k, v) for k, v in kern.items() if v["bound"] != "other"),
-                    key=lambda kv: kv[1]["ms"])
+    cand = [(k, v) for k, v in kern.items() if v["bound"] != "other"]
+    if not cand:
+        return None
+    name, ent = max(cand, key=lambda kv: kv[1]["ms"])
     ms_launch = ent["ms"] / ent["launches"]
     if ent["bound"] == "mfma":
         # the folded form executes half of the dense-equivalent flops
@@ -218,22 +220,26 @@ def dtype_label(prec, form):
     return f"{prec}-mfma/f32-vectors/f64-scalars"
 
 
-def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a):
+def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, steps=None,
+            max_irls=None):
     """Warm-up and timed unwraps with one plan form, then the per-kernel
     table of one PCG iteration."""
     t0 = time.perf_counter()
     plan = pkg.Plan(N, M, prec, form=form)
     plan_s = time.perf_counter() - t0
     p = pkg.default_params(prec)
-    p.irls_iters = a.max_irls
+    p.irls_iters = max_irls or a.max_irls
     p.pcg_max = ref["maxit"]
     p.eps = ref["eps"]
     p.l1_target = target
+    if adaptive:
+        p.cg_schedule = pkg.CG_SCHEDULES["adaptive"]
+    steps = steps or a.steps
     dt = torch.float64 if prec == "f64" else torch.float32
     U = torch.empty((N, M), dtype=dt, device="cuda")
     # per-launch events of one PCG iteration (mid-solve of the second IRLS
     # iteration) recorded inside the first warm-up unwrap
-    plan.profile_arm(1, min(50, p.pcg_max - 2))
+    plan.profile_arm(1, 2 if adaptive else min(50, p.pcg_max - 2))
     for i in range(a.warmup):
         _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
         if i == 0:
@@ -251,14 +257,14 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a):
     torch.cuda.synchronize()
     e0.record(s)
     runs = []
-    for i in range(a.steps):
+    for i in range(steps):
         _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
         runs.append(st)
         print(f"[bench] {plan.form} step {i}: irls={st['irls_done']} pcg={st['pcg_total']} "
               f"hit={st['target_hit']}", file=sys.stderr, flush=True)
     e1.record(s)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
+    ms = e0.elapsed_time(e1) / steps
     flexible = prec in ("bf16", "f16")
     kern = kernel_table(launches, prec, plan.form, N, M, flexible)
     pre = ("stencil", "axpy", "residual")
@@ -305,6 +311,8 @@ def main(argv=None):
     ap.add_argument("--gap", type=float, default=1e-3)
     ap.add_argument("--max-irls", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the measurement with the Section 4.3 adaptive CG schedule")
     ap.add_argument("--no-mfma-form", action="store_true",
                     help="skip the second measurement with the MFMA preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -348,6 +356,7 @@ def main(argv=None):
     w = torch.from_numpy(field.w).to(device="cuda", dtype=torch.float32).to(dt)
     primary = measure(pkg, torch, N, M, prec, a.form, X, w, ref, target, a)
     plan = primary["plan"]
+    form_primary = plan.form
     # the MFMA route (dense cosine-basis contractions, folded when the sides
     # are even) measured on the same workload when the primary form is not it
     mfma = None
@@ -360,6 +369,20 @@ def main(argv=None):
                 "irls_iters": sec["last"]["irls_done"], "pcg_iters": sec["last"]["pcg_total"],
                 "ms_per_pcg_iter": round(sec["ms"] / max(1, sec["last"]["pcg_total"]), 4),
                 "roofline": sec["roof"], "precond_ms": sec["precond_ms"]}
+        sec["plan"].close()
+    # the Section 4.3 adaptive CG schedule on the primary form: time to the
+    # same L1 target, or to the IRLS stop of its rule
+    adapt = None
+    if not a.no_adaptive:
+        sec = measure(pkg, torch, N, M, prec, form_primary, X, w, ref, target, a, adaptive=True,
+                      steps=1, max_irls=200)
+        lst = sec["last"]
+        l1 = (lst["history"][lst["irls_done"]]["L1"] if sec["hit"] else lst["L1_final"])
+        adapt = {"value": round(N * M / 1e6 / (sec["ms"] * 1e-3), 4),
+                 "ms_per_step": round(sec["ms"], 3), "target_hit": sec["hit"],
+                 "schedule_stop": lst["schedule_stop"], "irls_iters": lst["irls_done"],
+                 "pcg_iters": lst["pcg_total"], "L1_reached": l1,
+                 "caps": [h["cap"] for h in lst["history"][:lst["irls_done"]]]}
         sec["plan"].close()
     ms, hit, last, roof, kern = (primary["ms"], primary["hit"], primary["last"], primary["roof"],
                                  primary["kern"])
@@ -387,6 +410,7 @@ def main(argv=None):
         "precond_ms": primary["precond_ms"],
         "iteration_ms_recorded": primary["iter_ms"],
         "mfma_form": mfma,
+        "cg_adaptive": adapt,
     }
     if not a.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
