@@ -234,6 +234,7 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, 
     p.l1_target = target
     if adaptive:
         p.cg_schedule = pkg.CG_SCHEDULES["adaptive"]
+    p.flexible = a.flexible
     steps = steps or a.steps
     dt = torch.float64 if prec == "f64" else torch.float32
     U = torch.empty((N, M), dtype=dt, device="cuda")
@@ -265,7 +266,8 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, 
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    flexible = prec in ("bf16", "f16")
+    flexible = a.flexible == 1 or (a.flexible < 0 and prec in ("bf16", "f16")
+                                   and plan.form != "fast")
     kern = kernel_table(launches, prec, plan.form, N, M, flexible)
     pre = ("stencil", "axpy", "residual")
     return {"plan": plan, "plan_s": plan_s, "form": plan.form, "ms": ms,
@@ -311,6 +313,8 @@ def main(argv=None):
     ap.add_argument("--gap", type=float, default=1e-3)
     ap.add_argument("--max-irls", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--flexible", type=int, choices=[-1, 0, 1], default=-1,
+                    help="CG beta: 0 plain, 1 flexible, -1 the plan's default")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the measurement with the Section 4.3 adaptive CG schedule")
     ap.add_argument("--no-mfma-form", action="store_true",

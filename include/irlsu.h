@@ -78,7 +78,9 @@ typedef struct irlsu_params {
   int32_t true_res_every;  /* recompute r = b - A u every this many PCG iterations; 0 = never. 32 */
   int32_t poll_every;      /* host reads the device convergence flag every this many PCG iterations. 4 */
   int32_t flexible;        /* CG beta: 0 = rho_new / rho (Algorithm 2), 1 = flexible
-                              (z_new . (r_new - r_old) / rho), -1 = flexible for mixed plans */
+                              (z_new . (r_new - r_old) / rho), -1 = flexible for mixed plans
+                              whose preconditioner runs MFMA products (dense / folded), plain
+                              otherwise */
   int32_t cg_schedule;     /* IRLSU_CG_FIXED (pcg_max per solve) or IRLSU_CG_ADAPTIVE */
   int32_t cg_m0;           /* adaptive: iteration cap of the first solve, m_CG(0). 5 */
   int32_t reserved_;

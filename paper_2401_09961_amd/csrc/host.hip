@@ -240,6 +240,15 @@ irlsu_status read_back(irlsu_plan* pl, const Ws<T>& W, hipStream_t s) {
 // PCG (Algorithm 2) on D^T Omega D x = rhs with the Omega currently in the
 // workspace, warm-started at x (FP64).  ||rhs||^2 and tol^2 must already be in
 // SC_BB / SC_TOL2 and the flags cleared (finalize_weights / adjoint rhs).
+// Default CG beta: flexible where 16-bit operands enter the MFMA products
+// (dense / folded mixed plans: a preconditioner that is not quite linear or
+// symmetric); plain for FP32 / FP64 plans and the fast form, whose
+// transforms run in FP32 (its FP16 storage leaves the map close enough to
+// linear that plain beta follows the flexible trajectory).
+static int default_flexible(const irlsu_plan* pl) {
+  return (is_mixed(pl->prec) && !pl->fast) ? 1 : 0;
+}
+
 template <class T>
 irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
                        const irlsu_params& prm, int flexible, int* iters_out, double* relres_out,
@@ -364,7 +373,7 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
   if (pl->h_flags[FL_INPUT] & 1) return IRLSU_ERR_NONFINITE;
   if (pl->h_flags[FL_INPUT] & 2) return IRLSU_ERR_BAD_WEIGHTS;
 
-  const int flexible = prm.flexible < 0 ? (is_mixed(pl->prec) ? 1 : 0) : prm.flexible;
+  const int flexible = prm.flexible < 0 ? default_flexible(pl) : prm.flexible;
   const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
   const bool adaptive = prm.cg_schedule == IRLSU_CG_ADAPTIVE;
   const bool want_obj = stats != nullptr || prm.l1_target > 0.0 || adaptive;
@@ -494,7 +503,7 @@ irlsu_status adjoint_impl(irlsu_plan* pl, const T* gU, int64_t ldg, const irlsu_
   launch_weights<T>(wa, s);
   launch_adjoint_rhs<T>(gU, ldg, N, M, Np, ld, W.v[V_B], st, prm.pcg_rtol * prm.pcg_rtol, s);
   HIP_OK(hipMemsetAsync(W.lam, 0, npx * sizeof(double), s));
-  const int flexible = prm.flexible < 0 ? (is_mixed(pl->prec) ? 1 : 0) : prm.flexible;
+  const int flexible = prm.flexible < 0 ? default_flexible(pl) : prm.flexible;
   int iters = 0;
   double relres = 0.0;
   irlsu_status solve_st = IRLSU_OK;
