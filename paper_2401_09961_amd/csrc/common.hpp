@@ -167,6 +167,22 @@ __device__ __forceinline__ void st4(T* p, const V4<T>& r) {
   }
 }
 
+// Streaming store (non-temporal hint): for data written once per pass and
+// not read again by the same kernel.
+template <class T>
+__device__ __forceinline__ void st4_nt(T* p, const V4<T>& r) {
+  if constexpr (sizeof(T) == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 v = {r.v[0], r.v[1], r.v[2], r.v[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+  } else {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 a = {r.v[0], r.v[1]}, b = {r.v[2], r.v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<d2*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<d2*>(p + 2));
+  }
+}
+
 template <class T>
 __device__ __forceinline__ V4<T> zero4() {
   V4<T> r;

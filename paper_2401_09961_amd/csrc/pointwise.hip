@@ -200,7 +200,8 @@ __device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) 
   const T al = (T)alpha;
   double acc[2] = {0.0, 0.0};
   const int64_t n4 = a.n / 4;
-  // two 4-element chunks per thread in flight; 16-byte accesses
+  // two 4-element chunks per thread in flight; 16-byte accesses; r and d
+  // are written once per pass (streaming stores)
   constexpr int UN = 2;
   const int64_t stride = (int64_t)nb * kThreads;
   for (int64_t k0 = (int64_t)lb * kThreads + threadIdx.x; k0 < n4; k0 += UN * stride) {
@@ -229,8 +230,8 @@ __device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) 
           if (a.d) d[c].v[e] = d[c].v[e] + al * p[c].v[e];
           else u[c].v[e] += alpha * (double)p[c].v[e];
         }
-        st4(a.r + 4 * k, r[c]);
-        if (a.d) st4(a.d + 4 * k, d[c]);
+        st4_nt(a.r + 4 * k, r[c]);
+        if (a.d) st4_nt(a.d + 4 * k, d[c]);
         else st4(a.u + 4 * k, u[c]);
       }
     }
