@@ -312,6 +312,17 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
 irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* Rounded output ("rounded IRLS" of the experiments, Section 4): writes
+ * out = X + 2 pi rint((U + c - X) / 2 pi) with c = arg sum exp(i (X - U)),
+ * i.e. U (defined up to a constant) aligned with X modulo 2 pi and rounded
+ * to the nearest image that is 2 pi-congruent to X.  X, U and out are
+ * N x M device arrays of the plan's element type (row strides ldx, ldu,
+ * ldo >= M, elements); out may alias U.  Uses the workspace's reduction
+ * slots.  Errors: ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP. */
+irlsu_status irlsu_round_congruent(const irlsu_plan* plan, const void* X, int64_t ldx,
+                                   const void* U, int64_t ldu, void* out, int64_t ldo,
+                                   void* workspace, size_t workspace_bytes, void* stream);
+
 /* Kinds of launch reported by irlsu_precond_timed and irlsu_profile_result. */
 #define IRLSU_MAX_LAUNCHES 32
 enum {

@@ -317,6 +317,25 @@ def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, eps=1e-3, iters=20,
 
 
 # ----------------------------------------------------------------------------
+# Rounded output (Section 4, "rounded IRLS"): the unwrapped U made
+# 2 pi-congruent to the input.  U is defined up to a constant; the constant c
+# aligning U with X modulo 2 pi is the circular mean of X - U.
+# ----------------------------------------------------------------------------
+def congruent_shift(U, X):
+    """c = arg sum exp(i (X - U))."""
+    d = np.asarray(X, np.float64) - np.asarray(U, np.float64)
+    return math.atan2(float(np.sum(np.sin(d))), float(np.sum(np.cos(d))))
+
+
+def rounded(U, X):
+    """X + 2 pi k with k = round((U + c - X) / 2 pi) (ties to even), and k."""
+    X = np.asarray(X, np.float64)
+    c = congruent_shift(U, X)
+    k = np.rint((np.asarray(U, np.float64) + c - X) / TWO_PI)
+    return X + TWO_PI * k, k
+
+
+# ----------------------------------------------------------------------------
 # Adjoint of the converged (frozen-weight) least-squares map
 # ----------------------------------------------------------------------------
 def frozen_weights(U, Gv, Gh, eps):

@@ -32,7 +32,7 @@ DECLARED_SYMBOLS = (
     "irlsu_plan_create_ex", "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
     "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
     "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_profile_arm",
-    "irlsu_profile_result", "irlsu_batch_create", "irlsu_batch_destroy",
+    "irlsu_profile_result", "irlsu_round_congruent", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
 )
 
@@ -157,6 +157,7 @@ def load_library():
         "irlsu_precond_timed": (I32, [P, P, P, P, SZ, I32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "irlsu_profile_arm": (I32, [P, I32, I32]),
+        "irlsu_round_congruent": (I32, [P, P, I64, P, I64, P, I64, P, SZ, P]),
         "irlsu_profile_result": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
                                        ctypes.POINTER(I32)]),
     }
@@ -336,6 +337,19 @@ class Plan:
                                       _ptr(self.workspace), self.workspace.numel(), _stream()),
                "precond")
         return z, rz
+
+    def round_congruent(self, X, U, out=None):
+        """X + 2 pi rint((U + c - X) / 2 pi), c = arg sum exp(i (X - U)):
+        U made 2 pi-congruent to X (the rounded output of Section 4)."""
+        import torch
+        X = _mat(X, self.dtype)
+        U = _mat(U, self.dtype)
+        out = torch.empty_like(U) if out is None else out
+        _check(self.lib.irlsu_round_congruent(self.handle, _ptr(X), X.stride(0), _ptr(U),
+                                              U.stride(0), _ptr(out), out.stride(0),
+                                              _ptr(self.workspace), self.workspace.numel(),
+                                              _stream()), "round_congruent")
+        return out
 
     def profile_arm(self, irls_k, pcg_l):
         """Record per-launch events for PCG iteration pcg_l of IRLS

@@ -1275,6 +1275,26 @@ irlsu_status irlsu_profile_result(irlsu_plan* plan, double* ms_launch, int32_t* 
   return IRLSU_OK;
 }
 
+irlsu_status irlsu_round_congruent(const irlsu_plan* plan, const void* X, int64_t ldx,
+                                   const void* U, int64_t ldu, void* out, int64_t ldo,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan || !X || !U || !out || ldx < plan->M || ldu < plan->M || ldo < plan->M)
+    return IRLSU_ERR_INVALID_ARG;
+  irlsu_status st = check_ws(plan, workspace, workspace_bytes);
+  if (st != IRLSU_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->elem == 8) {
+    const Ws<double> W = carve<double>(plan, workspace);
+    launch_congruent<double>(static_cast<const double*>(X), ldx, static_cast<const double*>(U),
+                             ldu, static_cast<double*>(out), ldo, plan->N, plan->M, W.st, s);
+  } else {
+    const Ws<float> W = carve<float>(plan, workspace);
+    launch_congruent<float>(static_cast<const float*>(X), ldx, static_cast<const float*>(U), ldu,
+                            static_cast<float*>(out), ldo, plan->N, plan->M, W.st, s);
+  }
+  return last_launch();
+}
+
 irlsu_status irlsu_batch_destroy(irlsu_batch* b) {
   if (!b) return IRLSU_OK;
   for (void* p : b->P) if (p) (void)hipFree(p);

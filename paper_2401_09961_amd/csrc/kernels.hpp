@@ -105,6 +105,10 @@ template <class T> int launch_weights(const WeightsArgs<T>& a, hipStream_t s);
 void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s,
                              int want_model = 0);
 template <class T> int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks);
+// out = X + 2 pi rint((U + c - X) / 2 pi), c = arg sum exp(i (X - U))
+template <class T>
+void launch_congruent(const T* X, int64_t ldx, const T* U, int64_t ldu, T* out, int64_t ldo,
+                      int64_t N, int64_t M, DevState st, hipStream_t s);
 // u += d (FP64) over n elements: the end of a solve
 template <class T> void launch_commit(double* u, const T* d, int64_t n, hipStream_t s);
 void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s);

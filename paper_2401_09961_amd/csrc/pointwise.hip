@@ -318,6 +318,64 @@ void launch_commit(double* u, const T* d, int64_t n, hipStream_t s) {
 template void launch_commit<float>(double*, const float*, int64_t, hipStream_t);
 template void launch_commit<double>(double*, const double*, int64_t, hipStream_t);
 
+// ----------------------------------------------------------------------------
+// Rounded output (Section 4, "rounded IRLS"): U made 2 pi-congruent to X.
+// c = arg sum exp(i (X - U)) aligns the constant of U with X; then
+// out = X + 2 pi rint((U + c - X) / 2 pi), every step in FP64 with explicit
+// rounding so the integer decision is the one an FP64 evaluation takes.
+// ----------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kThreads) void congruent_sum_kernel(const T* X, int64_t ldx,
+                                                                const T* U, int64_t ldu, int64_t N,
+                                                                int64_t M, DevState st) {
+  double acc[2] = {0.0, 0.0};
+  const int64_t n = N * M;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = k / M, j = k % M;
+    const double d = __dsub_rn((double)X[i * ldx + j], (double)U[i * ldu + j]);
+    double sn, cs;
+    sincos(d, &sn, &cs);
+    acc[0] += sn;
+    acc[1] += cs;
+  }
+  const int slots[2] = {PT_A, PT_B};
+  write_partials<2>(st, slots, acc, (int)blockIdx.x);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void congruent_apply_kernel(const T* X, int64_t ldx,
+                                                                  const T* U, int64_t ldu, T* out,
+                                                                  int64_t ldo, int64_t N, int64_t M,
+                                                                  DevState st, int nparts) {
+  const double sn = reduce_slot(st, PT_A, nparts);
+  const double cs = reduce_slot(st, PT_B, nparts);
+  const double c = atan2(sn, cs);
+  const double two_pi = 6.283185307179586;
+  const int64_t n = N * M;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = k / M, j = k % M;
+    const double x = (double)X[i * ldx + j];
+    const double t = __ddiv_rn(__dsub_rn(__dadd_rn((double)U[i * ldu + j], c), x), two_pi);
+    out[i * ldo + j] = (T)__dadd_rn(x, __dmul_rn(two_pi, rint(t)));
+  }
+}
+
+template <class T>
+void launch_congruent(const T* X, int64_t ldx, const T* U, int64_t ldu, T* out, int64_t ldo,
+                      int64_t N, int64_t M, DevState st, hipStream_t s) {
+  const int nb = elementwise_blocks(N * M);
+  hipLaunchKernelGGL(congruent_sum_kernel<T>, dim3(nb), dim3(kThreads), 0, s, X, ldx, U, ldu, N,
+                     M, st);
+  hipLaunchKernelGGL(congruent_apply_kernel<T>, dim3(nb), dim3(kThreads), 0, s, X, ldx, U, ldu,
+                     out, ldo, N, M, st, nb);
+}
+template void launch_congruent<float>(const float*, int64_t, const float*, int64_t, float*,
+                                      int64_t, int64_t, int64_t, DevState, hipStream_t);
+template void launch_congruent<double>(const double*, int64_t, const double*, int64_t, double*,
+                                       int64_t, int64_t, int64_t, DevState, hipStream_t);
+
 // Copy the (mean-zero) internal U to the caller's N x M buffer.
 template <class T>
 __global__ __launch_bounds__(kThreads) void copy_out_kernel(const double* u, int64_t ld, T* out,

@@ -255,3 +255,43 @@ def test_adaptive_cg_schedule_section_4_3():
         assert abs(hist[k]["delta"] - ho[k]["delta"]) <= 1e-7 * abs(ho[k]["delta"]), k
         assert caps[k] == ho[k]["cap"]
     print(f"adaptive: caps {caps} stop {st['schedule_stop']} L1 {st['L1_final']:.6g}")
+
+
+def test_rounded_output_itoh_gives_back_phi():
+    """Itoh case (c1, FP64): the rounded output equals phi up to one common
+    multiple of 2 pi."""
+    f = synth.field_c1(0, 256, 256)
+    plan = pkg.Plan(256, 256, "f64")
+    p = pkg.default_params("f64")
+    p.irls_iters, p.pcg_rtol = 4, 1e-10
+    X = torch.from_numpy(f.X).cuda()
+    U = plan.unwrap(X, params=p)
+    Ur = plan.round_congruent(X, U).cpu().numpy()
+    plan.close()
+    m = (Ur - f.phi) / (2 * np.pi)
+    assert np.abs(m - np.round(m[0, 0])).max() < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_rounded_output_matches_oracle_integers(prec):
+    """Residue field: the GPU's integers k = (U_r - X) / 2 pi equal the
+    oracle's on the same U and X (both decide in FP64), except where
+    (U + c - X) / 2 pi lies within 1e-9 of a half-integer (either choice is
+    correct there); the output is congruent to X."""
+    f = synth.field_c2(7, 200, 168)
+    dt = npdt(prec)
+    X = torch.from_numpy(f.X.astype(dt)).cuda()
+    plan = pkg.Plan(200, 168, prec)
+    p = pkg.default_params(prec)
+    p.irls_iters = 4
+    U = plan.unwrap(X, torch.from_numpy(f.w.astype(dt)).cuda(), params=p)
+    Ur = plan.round_congruent(X, U)
+    torch.cuda.synchronize()
+    plan.close()
+    Xn, Un, Urn = (t.double().cpu().numpy() for t in (X, U, Ur))
+    _, ko = R.rounded(Un, Xn)
+    kg = np.rint((Urn - Xn) / R.TWO_PI)
+    assert np.abs((Urn - Xn) / R.TWO_PI - kg).max() < (1e-12 if prec == "f64" else 1e-5)
+    t = (Un + R.congruent_shift(Un, Xn) - Xn) / R.TWO_PI
+    near_half = np.abs(np.abs(t - np.floor(t)) - 0.5) < 1e-9
+    assert np.array_equal(kg[~near_half], ko[~near_half])

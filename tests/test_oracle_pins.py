@@ -483,6 +483,45 @@ def test_scheduled_irls_follows_section_4_3_rules():
 
 
 # ---------------------------------------------------------------------------
+# Rounded (2 pi-congruent) output
+# ---------------------------------------------------------------------------
+def test_rounded_output_is_congruent_and_recovers_itoh_phase():
+    """Itoh case: the IRLS U is phi - mean(phi); rounding it gives back phi
+    up to one multiple of 2 pi, and the output minus X is an exact integer
+    multiple of 2 pi pixel by pixel."""
+    f = synth.smooth_field(3, 40, 36)
+    U, _ = R.irls(f.X, iters=3, tol=1e-12, maxit=500)
+    Ur, k = R.rounded(U, f.X)
+    assert np.array_equal(Ur, f.X + R.TWO_PI * k)
+    m = (Ur - f.phi) / R.TWO_PI
+    assert np.abs(m - np.round(m[0, 0])).max() < 1e-9
+
+
+def test_rounded_output_is_invariant_to_the_constant_of_u():
+    """U is defined up to a constant: rounding U + t gives the same output
+    (the aligning constant absorbs t), for t off the rounding boundaries."""
+    rng = np.random.default_rng(31)
+    X = rng.uniform(-np.pi, np.pi, (30, 20))
+    U = X + R.TWO_PI * rng.integers(-3, 4, X.shape) + rng.normal(0, 0.3, X.shape)
+    Ur, k = R.rounded(U, X)
+    for t in (0.7, -2.1, 10.0):
+        Ur2, k2 = R.rounded(U + t, X)
+        d = (Ur2 - Ur) / R.TWO_PI
+        assert np.abs(d - np.round(d)).max() < 1e-12 and np.ptp(np.round(d)) == 0
+
+
+def test_rounded_output_of_a_congruent_u_keeps_its_integers():
+    """A U that already differs from X by 2 pi k (plus a constant) is
+    returned as X + 2 pi k (up to one common multiple of 2 pi)."""
+    rng = np.random.default_rng(32)
+    X = rng.uniform(-np.pi, np.pi, (17, 23))
+    K = rng.integers(-5, 6, X.shape)
+    Ur, k = R.rounded(X + R.TWO_PI * K - 1.234, X)
+    s = k - K
+    assert np.ptp(s) == 0
+
+
+# ---------------------------------------------------------------------------
 # Adjoint of the frozen-weight map against FP64 central differences
 # ---------------------------------------------------------------------------
 def dense_frozen_solve(Cv, Ch, Gv, Gh, wv, wh):
