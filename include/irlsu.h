@@ -312,6 +312,27 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
 irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* The paper's augmented form (Algorithm 1 in (U, V^v, V^h) with tau and
+ * delta): closed-form weights W = sqrt(C^2 V^2 + delta^2), then Algorithm 2
+ * on the symmetric system of Proposition 1 preconditioned by the block
+ * diagonal of Section 3.3 (tau L^+ on U, (C^2/W + 1/tau)^-1 on V), warm
+ * started, then mean removal of U.  U^0 = 0, V^0 = D U^0 - G.  Inputs and
+ * output as irlsu_unwrap (no warm start); params as irlsu_unwrap (eps and
+ * the schedule fields are not used; l1_target stops at the first U^k with
+ * L1 <= l1_target).  stats: iter[k].L1 = L1(U^k), iter[k].H =
+ * F_delta(U^k, V^k) (the objective of the smoothed problem).  The
+ * workspace (irlsu_augmented_workspace_bytes) is larger than irlsu_unwrap's.
+ * Errors: ERR_INVALID_ARG (tau or delta <= 0, strides, nulls),
+ * ERR_WORKSPACE, ERR_NONFINITE, ERR_BAD_WEIGHTS, ERR_BREAKDOWN, ERR_HIP;
+ * NOT_CONVERGED as irlsu_unwrap. */
+size_t irlsu_augmented_workspace_bytes(const irlsu_plan* plan);
+irlsu_status irlsu_unwrap_augmented(irlsu_plan* plan, const void* X, int64_t ldx,
+                                    const void* w, const void* Cv, int64_t ldcv,
+                                    const void* Ch, int64_t ldch, const irlsu_params* params,
+                                    double tau, double delta, void* U, int64_t ldu,
+                                    void* workspace, size_t workspace_bytes,
+                                    irlsu_stats* stats, void* stream);
+
 /* Rounded output ("rounded IRLS" of the experiments, Section 4): writes
  * out = X + 2 pi rint((U + c - X) / 2 pi) with c = arg sum exp(i (X - U)),
  * i.e. U (defined up to a constant) aligned with X modulo 2 pi and rounded

@@ -32,7 +32,8 @@ DECLARED_SYMBOLS = (
     "irlsu_plan_create_ex", "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
     "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
     "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_profile_arm",
-    "irlsu_profile_result", "irlsu_round_congruent", "irlsu_batch_create", "irlsu_batch_destroy",
+    "irlsu_profile_result", "irlsu_round_congruent", "irlsu_augmented_workspace_bytes",
+    "irlsu_unwrap_augmented", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
 )
 
@@ -158,6 +159,9 @@ def load_library():
                                       ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "irlsu_profile_arm": (I32, [P, I32, I32]),
         "irlsu_round_congruent": (I32, [P, P, I64, P, I64, P, I64, P, SZ, P]),
+        "irlsu_augmented_workspace_bytes": (SZ, [P]),
+        "irlsu_unwrap_augmented": (I32, [P, P, I64, P, P, I64, P, I64, P, D, D, P, I64, P, SZ,
+                                         P, P]),
         "irlsu_profile_result": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32),
                                        ctypes.POINTER(I32)]),
     }
@@ -337,6 +341,29 @@ class Plan:
                                       _ptr(self.workspace), self.workspace.numel(), _stream()),
                "precond")
         return z, rz
+
+    def unwrap_augmented(self, X, weights=None, *, tau=1e-2, delta=1e-6,
+                         params: Optional[Params] = None, stats: bool = False):
+        """The paper's augmented form (U, V^v, V^h) with tau, delta: returns
+        U (and the stats dict; history H holds F_delta)."""
+        import torch
+        X = _mat(X, self.dtype)
+        w = None if weights is None else _mat(weights, self.dtype, like=X)
+        nbytes = self.lib.irlsu_augmented_workspace_bytes(self.handle)
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        U = torch.empty((self.N, self.M), dtype=self.dtype, device=self.device)
+        st = Stats() if stats else None
+        code = self.lib.irlsu_unwrap_augmented(
+            self.handle, _ptr(X), X.stride(0), _ptr(w), None, 0, None, 0,
+            ctypes.byref(params) if params is not None else None, float(tau), float(delta),
+            _ptr(U), U.stride(0), _ptr(ws), ws.numel(),
+            ctypes.byref(st) if st is not None else None, _stream())
+        _check(code, "unwrap_augmented")
+        if stats:
+            d = st.to_dict()
+            d["code"] = code
+            return U, d
+        return U
 
     def round_congruent(self, X, U, out=None):
         """X + 2 pi rint((U + c - X) / 2 pi), c = arg sum exp(i (X - U)):

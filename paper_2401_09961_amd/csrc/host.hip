@@ -791,6 +791,168 @@ irlsu_status check_ws(const irlsu_plan* pl, const void* ws, size_t bytes) {
 
 }  // namespace
 
+// ---- augmented form (Algorithm 1 in (U, V^v, V^h)) --------------------------
+// Workspace: the plan's layout (setup outputs, preconditioner buffers,
+// partial sums, scalars, flags) followed by 13 vectors: x (3), and the slack
+// blocks of r, z, p, q, b (the U blocks reuse r, z, p0, q, b of the layout).
+static constexpr int kAugExtra = 13;
+
+static size_t aug_bytes(const irlsu_plan* p) {
+  const size_t vec = align_up((size_t)p->Np * (size_t)p->Mp * p->elem);
+  return layout(p).total + kAugExtra * vec;
+}
+
+template <class T>
+irlsu_status aug_unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, const T* Cv,
+                             int64_t ldcv, const T* Ch, int64_t ldch, const irlsu_params& prm,
+                             double tau, double delta, T* Uout, int64_t ldu, void* ws,
+                             irlsu_stats* stats, hipStream_t s) {
+  const Ws<T> W = carve<T>(pl, ws);
+  const int64_t N = pl->N, M = pl->M, Np = pl->Np, ld = pl->Mp;
+  const size_t npx = (size_t)Np * (size_t)ld;
+  const size_t vec = align_up(npx * pl->elem);
+  char* extra = static_cast<char*>(ws) + layout(pl).total;
+  T* ev[kAugExtra];
+  for (int i = 0; i < kAugExtra; ++i) ev[i] = reinterpret_cast<T*>(extra + i * vec);
+  DevState st = W.st;
+  HIP_OK(hipMemsetAsync(st.fl, 0, FL_COUNT * sizeof(int32_t), s));
+  HIP_OK(hipMemsetAsync(st.sc, 0, SC_COUNT * sizeof(double), s));
+  for (int v = 0; v < V_COUNT; ++v) HIP_OK(hipMemsetAsync(W.v[v], 0, npx * sizeof(T), s));
+  for (int i = 0; i < kAugExtra; ++i) HIP_OK(hipMemsetAsync(ev[i], 0, npx * sizeof(T), s));
+
+  SetupArgs<T> sa;
+  sa.X = X;
+  sa.ldx = ldx;
+  sa.w = w;
+  sa.Cv = Cv;
+  sa.ldcv = ldcv;
+  sa.Ch = Ch;
+  sa.ldch = ldch;
+  sa.U0 = nullptr;
+  sa.ldu0 = 0;
+  sa.N = N;
+  sa.M = M;
+  sa.Np = Np;
+  sa.ld = ld;
+  sa.Gv = W.v[V_GV];
+  sa.Gh = W.v[V_GH];
+  sa.Cv_out = W.v[V_CV];
+  sa.Ch_out = W.v[V_CH];
+  sa.U = W.U;
+  sa.flags = st.fl + FL_INPUT;
+  launch_setup<T>(sa, s);
+  if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+  irlsu_status rs = read_back(pl, W, s);
+  if (rs != IRLSU_OK) return rs;
+  if (pl->h_flags[FL_INPUT] & 1) return IRLSU_ERR_NONFINITE;
+  if (pl->h_flags[FL_INPUT] & 2) return IRLSU_ERR_BAD_WEIGHTS;
+
+  AugArgs<T> a;
+  a.N = N;
+  a.M = M;
+  a.Np = Np;
+  a.ld = ld;
+  a.tau = tau;
+  a.delta = delta;
+  a.Gv = W.v[V_GV];
+  a.Gh = W.v[V_GH];
+  a.Cv = W.v[V_CV];
+  a.Ch = W.v[V_CH];
+  a.dv = W.v[V_OV];
+  a.dh = W.v[V_OH];
+  a.st = st;
+  const AugVec<T> x{ev[0], ev[1], ev[2]};
+  const AugVec<T> r{W.v[V_R], ev[3], ev[4]};
+  const AugVec<T> z{W.v[V_Z], ev[5], ev[6]};
+  const AugVec<T> p{W.v[V_P0], ev[7], ev[8]};
+  const AugVec<T> q{W.v[V_Q], ev[9], ev[10]};
+  const AugVec<T> b{W.v[V_B], ev[11], ev[12]};
+  const AugVec<T> none{nullptr, nullptr, nullptr};
+  const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
+  // right-hand side (fixed by G) and the start U^0 = 0, V^0 = -G
+  aug_launch<T>(AUG_RHS, a, x, b, none, none, 1, 0, 0, tol2, s);
+
+  int pcg_total = 0, done_iters = 0;
+  irlsu_status overall = IRLSU_OK;
+  bool target_hit = false;
+  for (int k = 0; k < prm.irls_iters; ++k) {
+    aug_launch<T>(AUG_WEIGHTS, a, x, none, none, none, 0, 0, 0, 0.0, s);
+    rs = read_back(pl, W, s);
+    if (rs != IRLSU_OK) return rs;
+    if (stats && k < IRLSU_MAX_IRLS) {
+      stats->iter[k].L1 = pl->h_sc[SC_L1];
+      stats->iter[k].H = pl->h_sc[SC_H];
+      stats->iter[k].pcg_cap = prm.pcg_max;
+    }
+    if (prm.l1_target > 0.0 && pl->h_sc[SC_L1] <= prm.l1_target) {
+      target_hit = true;
+      break;
+    }
+    // ---- Algorithm 2 on the augmented system, warm start from (U, V) ----
+    aug_launch<T>(AUG_START, a, none, none, none, none, 0, 0, 0, tol2, s);
+    const int nvec = aug_launch<T>(AUG_RESID, a, x, b, r, none, 0, 0, 0, 0.0, s);
+    PrecondArgs pa = precond_args<T>(pl, W, r.u, z.u, nullptr, 1, nvec);
+    int nzu = launch_precond(pa, s);
+    int nzv = aug_launch<T>(AUG_VPRECOND, a, r, z, none, none, 0, 0, 0, 0.0, s);
+    for (int l = 0; l < prm.pcg_max; ++l) {
+      aug_launch<T>(AUG_PUPDATE, a, z, p, none, none, l, nzu, nzv, 0.0, s);
+      const int npq = aug_launch<T>(AUG_APPLY, a, p, q, none, none, 0, 0, 0, 0.0, s);
+      aug_launch<T>(AUG_AXPY, a, x, r, p, q, l, npq, 0, 0.0, s);
+      if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max)
+        aug_launch<T>(AUG_RESID, a, x, b, r, none, 1, 0, 0, 0.0, s);
+      if (l + 1 < prm.pcg_max) {
+        nzu = launch_precond(pa, s);
+        nzv = aug_launch<T>(AUG_VPRECOND, a, r, z, none, none, 0, 0, 0, 0.0, s);
+      }
+      if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+      if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
+        HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (pl->h_flags[FL_DONE]) break;
+      }
+    }
+    launch_finalize_rr(st, nvec, s);
+    rs = read_back(pl, W, s);
+    if (rs != IRLSU_OK) return rs;
+    const int iters = pl->h_flags[FL_ITERS];
+    irlsu_status solve_st = IRLSU_OK;
+    if (pl->h_flags[FL_STATUS] & 1) solve_st = IRLSU_ERR_BREAKDOWN;
+    else if (!pl->h_flags[FL_DONE] && iters >= prm.pcg_max) solve_st = IRLSU_NOT_CONVERGED;
+    if (stats && k < IRLSU_MAX_IRLS) {
+      stats->iter[k].pcg_iters = iters;
+      stats->iter[k].status = solve_st;
+      const double bb = pl->h_sc[SC_BB];
+      stats->iter[k].relres = bb > 0 ? std::sqrt(pl->h_sc[SC_RR] / bb) : 0.0;
+    }
+    pcg_total += iters;
+    done_iters = k + 1;
+    if (solve_st == IRLSU_ERR_BREAKDOWN) return IRLSU_ERR_BREAKDOWN;
+    if (solve_st == IRLSU_NOT_CONVERGED) overall = IRLSU_NOT_CONVERGED;
+    aug_launch<T>(AUG_CENTER, a, x, none, none, none, 0, 0, 0, 0.0, s);
+  }
+  aug_launch<T>(AUG_WEIGHTS, a, x, none, none, none, 0, 0, 0, 0.0, s);
+  rs = read_back(pl, W, s);
+  if (rs != IRLSU_OK) return rs;
+  if (prm.l1_target > 0.0 && pl->h_sc[SC_L1] <= prm.l1_target) target_hit = true;
+  if (stats) {
+    stats->irls_done = done_iters;
+    stats->pcg_total = pcg_total;
+    stats->target_hit = target_hit ? 1 : 0;
+    stats->L1_final = pl->h_sc[SC_L1];
+    stats->H_final = pl->h_sc[SC_H];
+    stats->status = overall;
+    if (done_iters < IRLSU_MAX_IRLS) {
+      stats->iter[done_iters].L1 = pl->h_sc[SC_L1];
+      stats->iter[done_iters].H = pl->h_sc[SC_H];
+    }
+  }
+  HIP_OK(hipMemcpy2DAsync(Uout, (size_t)ldu * sizeof(T), x.u, (size_t)ld * sizeof(T),
+                          (size_t)M * sizeof(T), (size_t)N, hipMemcpyDeviceToDevice, s));
+  if (stats) HIP_OK(hipStreamSynchronize(s));
+  return overall;
+}
+
 extern "C" {
 
 const char* irlsu_status_string(irlsu_status st) {
@@ -1293,6 +1455,42 @@ irlsu_status irlsu_round_congruent(const irlsu_plan* plan, const void* X, int64_
                             static_cast<float*>(out), ldo, plan->N, plan->M, W.st, s);
   }
   return last_launch();
+}
+
+size_t irlsu_augmented_workspace_bytes(const irlsu_plan* plan) {
+  return plan ? aug_bytes(plan) : 0;
+}
+
+irlsu_status irlsu_unwrap_augmented(irlsu_plan* plan, const void* X, int64_t ldx, const void* w,
+                                    const void* Cv, int64_t ldcv, const void* Ch, int64_t ldch,
+                                    const irlsu_params* params, double tau, double delta,
+                                    void* U, int64_t ldu, void* workspace,
+                                    size_t workspace_bytes, irlsu_stats* stats, void* stream) {
+  if (!plan || !X || !U || !workspace || ldx < plan->M || ldu < plan->M) return IRLSU_ERR_INVALID_ARG;
+  if ((Cv == nullptr) != (Ch == nullptr)) return IRLSU_ERR_INVALID_ARG;
+  if (Cv && (ldcv < plan->M || ldch < plan->M - 1)) return IRLSU_ERR_INVALID_ARG;
+  if (!(tau > 0.0) || !(delta > 0.0)) return IRLSU_ERR_INVALID_ARG;
+  if (workspace_bytes < aug_bytes(plan)) return IRLSU_ERR_WORKSPACE;
+  irlsu_params prm;
+  if (params) {
+    prm = *params;
+  } else {
+    irlsu_params_default(&prm, plan->prec);
+  }
+  if (prm.irls_iters < 0 || prm.pcg_max < 1 || prm.true_res_every < 0 || prm.poll_every < 0 ||
+      !(prm.pcg_rtol >= 0.0))
+    return IRLSU_ERR_INVALID_ARG;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->elem == 8)
+    return aug_unwrap_impl<double>(plan, static_cast<const double*>(X), ldx,
+                                   static_cast<const double*>(w), static_cast<const double*>(Cv),
+                                   ldcv, static_cast<const double*>(Ch), ldch, prm, tau, delta,
+                                   static_cast<double*>(U), ldu, workspace, stats, s);
+  return aug_unwrap_impl<float>(plan, static_cast<const float*>(X), ldx,
+                                static_cast<const float*>(w), static_cast<const float*>(Cv), ldcv,
+                                static_cast<const float*>(Ch), ldch, prm, tau, delta,
+                                static_cast<float*>(U), ldu, workspace, stats, s);
 }
 
 irlsu_status irlsu_batch_destroy(irlsu_batch* b) {

@@ -229,6 +229,35 @@ struct PrecondArgs {
   LaunchLog* log = nullptr;   // nullable: per-launch events
 };
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s);
+
+// ---- augmented (U, V^v, V^h) solve ------------------------------------------
+template <class T>
+struct AugVec {
+  T* u; T* v; T* h;   // U block and the two slack blocks, Np x ld each
+};
+template <class T>
+struct AugArgs {
+  int64_t N, M, Np, ld;
+  double tau, delta;
+  const T* Gv; const T* Gh; const T* Cv; const T* Ch;
+  T* dv; T* dh;       // C^2 / W on every edge (0 where no edge)
+  DevState st;
+};
+enum AugOp : int {
+  AUG_WEIGHTS = 0,    // x: weights, F_delta and L1 into SC_H, SC_L1
+  AUG_RHS = 1,        // x = start (i0 = init), y = b; ||b||^2, tolerance d0
+  AUG_START = 2,      // ||b||^2 over i0 partials, tolerance d0
+  AUG_RESID = 3,      // x, y = b -> z = r; i0 = check_done
+  AUG_VPRECOND = 4,   // x = r -> y = z (slack blocks)
+  AUG_PUPDATE = 5,    // x = z, y = p; i0 = iter, i1 / i2 = partials of z.r (U / slack)
+  AUG_APPLY = 6,      // x = p -> y = q
+  AUG_AXPY = 7,       // x, y = r, z = p, w = q; i0 = iter, i1 = p.q partials
+  AUG_CENTER = 8      // x.u -= mean
+};
+template <class T>
+int aug_launch(int op, const AugArgs<T>& a, const AugVec<T>& x, const AugVec<T>& y,
+               const AugVec<T>& z, const AugVec<T>& w, int i0, int i1, int i2, double d0,
+               hipStream_t s);
 bool fct_supported(int64_t n);
 size_t fct_table_bytes(int64_t n, int elem);
 void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s);

@@ -1,0 +1,83 @@
+"""The paper's augmented form (U, V^v, V^h) on the GPU against the oracle's
+Algorithm 1 (oracle/paper_form.py), which takes the same steps in FP64:
+closed-form weights, Algorithm 2 on the system of Proposition 1 with the
+block-diagonal preconditioner, mean removal.
+
+Bars: FP64 with solves converged to 1e-12 -- the F_delta and L1 histories
+agree to 1e-8 (only summation order differs; converged solves do not
+amplify it, unlike capped ones); FP32 / mixed plans on a residue field --
+the final F_delta within 1e-4 (FP32 vectors, pcg_rtol 1e-6); the Itoh case
+gives plain integration.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2401_09961_amd as pkg
+from oracle import paper_form as PF
+
+pytestmark = pytest.mark.gpu
+TAU, DELTA = 1e-2, 1e-6
+
+
+def run_gpu(f, prec, iters, tol, maxit, weights=True):
+    dt = np.float64 if prec == "f64" else np.float32
+    N, M = f.X.shape
+    plan = pkg.Plan(N, M, prec)
+    p = pkg.default_params(prec)
+    p.irls_iters, p.pcg_rtol, p.pcg_max = iters, tol, maxit
+    w = torch.from_numpy(f.w.astype(dt)).cuda() if (weights and f.w is not None) else None
+    U, st = plan.unwrap_augmented(torch.from_numpy(f.X.astype(dt)).cuda(), w, tau=TAU,
+                                  delta=DELTA, params=p, stats=True)
+    torch.cuda.synchronize()
+    plan.close()
+    return U.double().cpu().numpy(), st
+
+
+@pytest.mark.parametrize("gen,shape", [("c2", (48, 40)), ("c3", (37, 52))])
+def test_fp64_history_matches_paper_form_oracle(gen, shape):
+    f = getattr(synth, "field_" + gen)(4, *shape)
+    K = 4
+    Ug, st = run_gpu(f, "f64", K, 1e-12, 3000)
+    Uo, Vv, Vh, hist = PF.irls(f.X, w=f.w, tau=TAU, delta=DELTA, iters=K, tol=1e-12, maxit=3000)
+    for k in range(K):
+        a, b = st["history"][k + 1]["H"], hist[k]["F_delta"]
+        print(f"{gen} k={k}: GPU F_delta {a:.12g} oracle {b:.12g}")
+        assert abs(a - b) <= 1e-8 * abs(b), k
+        a, b = st["history"][k + 1]["L1"], hist[k]["L1"]
+        assert abs(a - b) <= 1e-8 * abs(b), k
+        assert st["history"][k]["relres"] <= 1e-12
+    assert abs(Ug.mean()) < 1e-10
+    F = [st["history"][k]["H"] for k in range(1, K + 1)]
+    assert all(F[k + 1] <= F[k] * (1 + 1e-12) for k in range(K - 1))
+
+
+def test_itoh_case_is_plain_integration():
+    f = synth.field_c1(1, 64, 48)
+    Ug, st = run_gpu(f, "f64", 6, 1e-12, 3000, weights=False)
+    truth = f.phi - f.phi.mean()
+    assert np.abs(Ug - truth).max() < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_reduced_precision_final_objective(prec):
+    f = synth.field_c3(5, 128, 128)
+    K = 4
+    Ug, st = run_gpu(f, prec, K, 1e-6, 3000)
+    _, _, _, hist = PF.irls(f.X.astype(np.float32).astype(np.float64),
+                            w=f.w.astype(np.float32).astype(np.float64), tau=TAU, delta=DELTA,
+                            iters=K, tol=1e-6, maxit=3000)
+    a, b = st["H_final"], hist[-1]["F_delta"]
+    print(f"{prec}: GPU F_delta {a:.10g} oracle {b:.10g} gap {abs(a - b) / b:.2e}")
+    assert abs(a - b) <= 1e-4 * abs(b)
+
+
+def test_invalid_arguments():
+    plan = pkg.Plan(16, 16, "f64")
+    X = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(pkg.IrlsuError):
+        plan.unwrap_augmented(X, tau=0.0)
+    with pytest.raises(pkg.IrlsuError):
+        plan.unwrap_augmented(X, delta=-1.0)
+    plan.close()
