@@ -221,7 +221,7 @@ def dtype_label(prec, form):
 
 
 def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, steps=None,
-            max_irls=None):
+            max_irls=None, augmented=False):
     """Warm-up and timed unwraps with one plan form, then the per-kernel
     table of one PCG iteration."""
     t0 = time.perf_counter()
@@ -238,11 +238,16 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, 
     steps = steps or a.steps
     dt = torch.float64 if prec == "f64" else torch.float32
     U = torch.empty((N, M), dtype=dt, device="cuda")
+    def run():
+        if augmented:
+            return plan.unwrap_augmented(X, w, tau=1e-2, delta=1e-6, params=p, stats=True)
+        return plan.unwrap(X, w, params=p, out=U, stats=True)
+
     # per-launch events of one PCG iteration (mid-solve of the second IRLS
     # iteration) recorded inside the first warm-up unwrap
     plan.profile_arm(1, 2 if adaptive else min(50, p.pcg_max - 2))
     for i in range(a.warmup):
-        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+        _, st = run()
         if i == 0:
             launches = plan.profile_result()
             plan.profile_arm(-1, -1)
@@ -259,7 +264,7 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, 
     e0.record(s)
     runs = []
     for i in range(steps):
-        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+        _, st = run()
         runs.append(st)
         print(f"[bench] {plan.form} step {i}: irls={st['irls_done']} pcg={st['pcg_total']} "
               f"hit={st['target_hit']}", file=sys.stderr, flush=True)
@@ -315,6 +320,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flexible", type=int, choices=[-1, 0, 1], default=-1,
                     help="CG beta: 0 plain, 1 flexible, -1 the plan's default")
+    ap.add_argument("--no-augmented", action="store_true",
+                    help="skip the measurement of the paper's augmented (U, V) form")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the measurement with the Section 4.3 adaptive CG schedule")
     ap.add_argument("--no-mfma-form", action="store_true",
@@ -388,6 +395,21 @@ def main(argv=None):
                  "pcg_iters": lst["pcg_total"], "L1_reached": l1,
                  "caps": [h["cap"] for h in lst["history"][:lst["irls_done"]]]}
         sec["plan"].close()
+    # the paper's augmented form (U, V^v, V^h), tau = 1e-2, delta = 1e-6, with
+    # the primary form's preconditioner on its U block: time and iterations
+    # to the same L1 target
+    aug = None
+    if not a.no_augmented:
+        sec = measure(pkg, torch, N, M, prec, form_primary, X, w, ref, target, a, steps=1,
+                      augmented=True)
+        lst = sec["last"]
+        l1 = (lst["history"][lst["irls_done"]]["L1"] if sec["hit"] else lst["L1_final"])
+        aug = {"value": round(N * M / 1e6 / (sec["ms"] * 1e-3), 4),
+               "ms_per_step": round(sec["ms"], 3), "target_hit": sec["hit"],
+               "irls_iters": lst["irls_done"], "pcg_iters": lst["pcg_total"], "L1_reached": l1,
+               "ms_per_pcg_iter": round(sec["ms"] / max(1, lst["pcg_total"]), 4),
+               "tau": 1e-2, "delta": 1e-6}
+        sec["plan"].close()
     ms, hit, last, roof, kern = (primary["ms"], primary["hit"], primary["last"], primary["roof"],
                                  primary["kern"])
     L1_reached = last["history"][last["irls_done"]]["L1"] if hit else last["L1_final"]
@@ -415,6 +437,7 @@ def main(argv=None):
         "iteration_ms_recorded": primary["iter_ms"],
         "mfma_form": mfma,
         "cg_adaptive": adapt,
+        "augmented_form": aug,
     }
     if not a.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
