@@ -282,6 +282,41 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, 
             "precond_ms": round(sum(t for k, t in launches if k not in pre), 4)}
 
 
+def paper_shapes(pkg, torch, synth, a, prec):
+    """4000 x M unwraps with the fixed schedule (20 IRLS x 100 PCG): time per
+    unwrap with X and w resident in HBM, HIP events, after one warm-up."""
+    torch.cuda.set_device(0)
+    rows = []
+    for M in (2000, 4000, 8000, 12000, 16000):
+        N = 4000
+        print(f"[bench] paper shape {N}x{M}", file=sys.stderr, flush=True)
+        f = synth.field_c2(a.seed, N, M)
+        X = torch.from_numpy(f.X).to(device="cuda", dtype=torch.float32)
+        w = torch.from_numpy(f.w).to(device="cuda", dtype=torch.float32)
+        plan = pkg.Plan(N, M, prec)
+        p = pkg.default_params(prec)
+        p.irls_iters, p.pcg_max = 20, 100
+        U = torch.empty((N, M), dtype=torch.float32, device="cuda")
+        plan.unwrap(X, w, params=p, out=U)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rows.append({"N": N, "M": M, "form": plan.form, "ms_per_unwrap": round(ms, 2),
+                     "Mpixel_per_s": round(N * M / 1e6 / (ms * 1e-3), 3),
+                     "pcg_iters": st["pcg_total"], "L1_final": st["L1_final"]})
+        plan.close()
+        del X, w, U
+    line = {"metric": "seconds per unwrap of 4000 x M (20 IRLS x 100 PCG)", "unit": "ms",
+            "precision": prec, "data": "synthetic (c2-type fields)", "paper_shapes": rows}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def kernels_only(pkg, torch, N, M, prec):
     """Fixed launch sequence for counter runs (no unwrap, no oracle)."""
     torch.cuda.set_device(0)
@@ -328,6 +363,9 @@ def main(argv=None):
                     help="skip the second measurement with the MFMA preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="3 device copies of 256 MiB first (hardware-counter byte calibration)")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="the running-time study of the paper: 4000 x M, M = 2000..16000, "
+                         "c2-type fields, fixed 20 x 100 schedule; one JSON line")
     ap.add_argument("--kernels-only", action="store_true",
                     help="a short fixed launch sequence for hardware-counter runs: "
                          "3 preconditioner applications, 3 stencil applications and 3 "
@@ -348,6 +386,8 @@ def main(argv=None):
     N = M = cfg["N"]
     if a.kernels_only:
         return kernels_only(pkg, torch, N, M, prec)
+    if a.paper_shapes:
+        return paper_shapes(pkg, torch, synth, a, a.precision or "f16")
     if a.copy_calibration:
         torch.cuda.set_device(0)
         xc = torch.empty((256 << 20) // 4, dtype=torch.float32, device="cuda").uniform_()
