@@ -260,22 +260,26 @@ def measure(pkg, torch, N, M, prec, form, X, w, ref, target, a, adaptive=False, 
                   flush=True)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     e0.record(s)
+    ev[0].record(s)
     runs = []
     for i in range(steps):
         _, st = run()
+        ev[i + 1].record(s)
         runs.append(st)
         print(f"[bench] {plan.form} step {i}: irls={st['irls_done']} pcg={st['pcg_total']} "
               f"hit={st['target_hit']}", file=sys.stderr, flush=True)
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     flexible = a.flexible == 1 or (a.flexible < 0 and prec in ("bf16", "f16")
                                    and plan.form != "fast")
     kern = kernel_table(launches, prec, plan.form, N, M, flexible)
     pre = ("stencil", "axpy", "residual")
-    return {"plan": plan, "plan_s": plan_s, "form": plan.form, "ms": ms,
+    return {"plan": plan, "plan_s": plan_s, "form": plan.form, "ms": ms, "step_ms": step_ms,
             "hit": all(r["target_hit"] for r in runs), "last": runs[-1], "kern": kern,
             "roof": roofline(kern, prec, profiled_traffic(a.config, N, prec, plan.form)),
             "iter_ms": round(sum(t for _, t in launches), 4),
@@ -313,6 +317,60 @@ def paper_shapes(pkg, torch, synth, a, prec):
         del X, w, U
     line = {"metric": "seconds per unwrap of 4000 x M (20 IRLS x 100 PCG)", "unit": "ms",
             "precision": prec, "data": "synthetic (c2-type fields)", "paper_shapes": rows}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def batched(pkg, torch, synth, a):
+    """64 uneven tiles (c1-generator fields, seeds 1000 + t) unwrapped as one
+    batch (mixed BF16, one grouped launch per PCG phase) and one plan per
+    tile in FP32, same schedule (20 IRLS x 100 PCG, pcg_rtol 1e-6); HIP
+    events, inputs resident, one warm-up each."""
+    torch.cuda.set_device(0)
+    shapes = [tuple(int(v) for v in sh) for sh in synth.tile_shapes_c4(0)]
+    print(f"[bench] generating {len(shapes)} tiles", file=sys.stderr, flush=True)
+    Xs = [torch.from_numpy(synth.field_c4_tile(t, n, m).X).to(device="cuda", dtype=torch.float32)
+          for t, (n, m) in enumerate(shapes)]
+    px = sum(n * m for n, m in shapes)
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        out = fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    pb = pkg.default_params("bf16")
+    batch = pkg.Batch(shapes, "bf16")
+    ms_b, (Ub, stb) = timed(lambda: batch.unwrap(Xs, params=pb, stats=True))
+    batch.close()
+    plans = [pkg.Plan(n, m, "f32") for n, m in shapes]
+    pf = pkg.default_params("f32")
+    ms_l, res = timed(lambda: [pl.unwrap(X, params=pf, stats=True) for pl, X in zip(plans, Xs)])
+    forms = sorted({pl.form for pl in plans})
+    for pl in plans:
+        pl.close()
+    edges = [(n - 1) * m + n * (m - 1) for n, m in shapes]
+    l1b = [st["L1_final"] / e for st, e in zip(stb, edges)]
+    l1l = [r[1]["L1_final"] / e for r, e in zip(res, edges)]
+    du = max(float((ub - ub.mean() - (r[0] - r[0].mean())).abs().max()) for ub, r in zip(Ub, res))
+    line = {"metric": "Mpixel/s, 64 uneven tiles (sides 512..3072) unwrapped, 20 IRLS x 100 PCG",
+            "unit": "Mpixel/s", "tiles": len(shapes), "pixels": px,
+            "batched": {"precision": "bf16", "value": round(px / 1e6 / (ms_b * 1e-3), 3),
+                        "ms": round(ms_b, 1), "pcg_total": sum(st["pcg_total"] for st in stb)},
+            "looped_single_tile": {"precision": "f32", "forms": forms,
+                                   "value": round(px / 1e6 / (ms_l * 1e-3), 3),
+                                   "ms": round(ms_l, 1),
+                                   "pcg_total": sum(r[1]["pcg_total"] for r in res)},
+            "speedup": round(ms_l / ms_b, 3),
+            "equal_accuracy": {"L1_per_edge_max_batched": max(l1b),
+                               "L1_per_edge_max_looped": max(l1l),
+                               "max_abs_U_difference": du},
+            "data": "synthetic (c1-generator tiles)"}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -355,6 +413,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flexible", type=int, choices=[-1, 0, 1], default=-1,
                     help="CG beta: 0 plain, 1 flexible, -1 the plan's default")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the other precisions (bf16 / f16 / f32 / f64) on the same workload")
+    ap.add_argument("--batched", action="store_true",
+                    help="the batched case: 64 uneven tiles (sides 512..3072) in one batch "
+                         "against looped single-tile FP32 plans; one JSON line")
     ap.add_argument("--no-augmented", action="store_true",
                     help="skip the measurement of the paper's augmented (U, V) form")
     ap.add_argument("--no-adaptive", action="store_true",
@@ -388,6 +451,8 @@ def main(argv=None):
         return kernels_only(pkg, torch, N, M, prec)
     if a.paper_shapes:
         return paper_shapes(pkg, torch, synth, a, a.precision or "f16")
+    if a.batched:
+        return batched(pkg, torch, synth, a)
     if a.copy_calibration:
         torch.cuda.set_device(0)
         xc = torch.empty((256 << 20) // 4, dtype=torch.float32, device="cuda").uniform_()
@@ -450,6 +515,21 @@ def main(argv=None):
                "ms_per_pcg_iter": round(sec["ms"] / max(1, lst["pcg_total"]), 4),
                "tau": 1e-2, "delta": 1e-6}
         sec["plan"].close()
+    # the other precisions on the same workload (one timed step each)
+    precs = {}
+    if not a.no_precisions:
+        for pr in ("bf16", "f16", "f32", "f64"):
+            if pr == prec:
+                continue
+            dtp = torch.float64 if pr == "f64" else torch.float32
+            sec = measure(pkg, torch, N, M, pr, "auto", X.to(dtp), w.to(dtp), ref, target, a,
+                          steps=1)
+            lst = sec["last"]
+            precs[pr] = {"value": round(N * M / 1e6 / (sec["ms"] * 1e-3), 4),
+                         "target_hit": sec["hit"], "irls_iters": lst["irls_done"],
+                         "ms_per_pcg_iter": round(sec["ms"] / max(1, lst["pcg_total"]), 4),
+                         "form": sec["form"], "dtype": dtype_label(pr, sec["form"])}
+            sec["plan"].close()
     ms, hit, last, roof, kern = (primary["ms"], primary["hit"], primary["last"], primary["roof"],
                                  primary["kern"])
     L1_reached = last["history"][last["irls_done"]]["L1"] if hit else last["L1_final"]
@@ -461,6 +541,7 @@ def main(argv=None):
         "unit": "Mpixel/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms, 3),
+        "ms_per_step_median": round(float(np.median(primary["step_ms"])), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype_label(prec, form_used),
         "data": "synthetic",
@@ -478,6 +559,7 @@ def main(argv=None):
         "mfma_form": mfma,
         "cg_adaptive": adapt,
         "augmented_form": aug,
+        "precisions": precs,
     }
     if not a.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)

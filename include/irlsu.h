@@ -159,8 +159,7 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec);
  * bases P_N, P_M and the Laplacian eigenvalues 2 - 2 cos(pi k / n) on the
  * current HIP device (Section 3.3, eq:eigendecompositions: computed once,
  * reused by every PCG iteration).  Synchronises the stream before returning.
- * Sizes: 2 <= N, M <= 32768 and (ceil(N/128) * ceil(M/128)) <= 16384 (the
- * 64 x 64 tile count of the padded image must fit the partial-sum table).
+ * Sizes: 2 <= N, M <= 32768.
  * Errors: ERR_INVALID_ARG (out null), ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM,
  * ERR_HIP.  On error *out is NULL and nothing is leaked. */
 irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M,

@@ -9,7 +9,7 @@
 namespace irlsu {
 
 constexpr int kThreads = 256;          // every kernel runs 4 wave64s per block
-constexpr int kMaxPartials = 65536;    // per-block partial sums per quantity (all tiles)
+constexpr int kMaxPartials = 262144;   // per-block partial sums per quantity (all tiles)
 constexpr int kTilePad = 128;          // internal rows / row stride multiple
 constexpr int64_t kMaxSide = 32768;    // largest N or M (2-D grids index rows in y)
 

@@ -1541,10 +1541,9 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
     int gb[4];
     precond_blocks(b->kind, Np, Mp, gb);
     b->g4_nparts.push_back((int32_t)(g.x * g.y));
-    const int64_t bw = ((Mp + kThreads - 1) / kThreads);
-    int64_t wrows = 1;
-    while (bw * ((Np + wrows - 1) / wrows) > kMaxPartials / 2) wrows *= 2;
-    const int32_t wblocks = (int32_t)(bw * ((Np + wrows - 1) / wrows));
+    int wrows = 1;
+    const dim3 wg = weights_grid(Np, Mp, &wrows);
+    const int32_t wblocks = (int32_t)(wg.x * wg.y);
     const int32_t need = std::max({(int32_t)(g.x * g.y), gb[3], wblocks,
                                    (int32_t)elementwise_blocks(Np * Mp)});
     b->part_off.push_back(part);

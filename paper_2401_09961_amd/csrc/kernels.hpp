@@ -118,6 +118,7 @@ void launch_copy_out(const double* u, int64_t ld, T* out, int64_t ldo, int64_t N
 void launch_finalize_rr(DevState st, int nparts, hipStream_t s);
 void launch_reduce_to(DevState st, int slot, int nparts, double* out, hipStream_t s);
 int elementwise_blocks(int64_t n);
+dim3 weights_grid(int64_t Np, int64_t ld, int* rows_out);
 template <class T> int launch_sumsq(const T* x, int64_t n, DevState st, hipStream_t s);
 
 template <class T> int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s);

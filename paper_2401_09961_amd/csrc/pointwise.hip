@@ -429,11 +429,9 @@ void launch_setup(const SetupArgs<T>& a, hipStream_t s) {
 
 template <class T>
 int launch_weights(const WeightsArgs<T>& a, hipStream_t s) {
-  const int64_t bx = (a.ld + kThreads - 1) / kThreads;
-  int64_t rows = 1;
-  while (bx * ((a.Np + rows - 1) / rows) > kMaxPartials / 2) rows *= 2;
-  const dim3 grid((unsigned)bx, (unsigned)((a.Np + rows - 1) / rows));
-  hipLaunchKernelGGL(weights_kernel<T>, grid, dim3(kThreads), 0, s, a, (int)rows);
+  int rows = 1;
+  const dim3 grid = weights_grid(a.Np, a.ld, &rows);
+  hipLaunchKernelGGL(weights_kernel<T>, grid, dim3(kThreads), 0, s, a, rows);
   return (int)(grid.x * grid.y);
 }
 
@@ -441,6 +439,16 @@ void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, 
                              int want_model) {
   hipLaunchKernelGGL(finalize_weights_kernel, dim3(1), dim3(kThreads), 0, s, st, nparts, out, tol2,
                      want_model);
+}
+
+// Weight-step grid: 256 columns per block, rows per block doubled until at
+// most 2048 blocks (a batch reserves that many partial sums per tile).
+dim3 weights_grid(int64_t Np, int64_t ld, int* rows_out) {
+  const int64_t bx = (ld + kThreads - 1) / kThreads;
+  int64_t rows = 1;
+  while (bx * ((Np + rows - 1) / rows) > 2048) rows *= 2;
+  *rows_out = (int)rows;
+  return dim3((unsigned)bx, (unsigned)((Np + rows - 1) / rows));
 }
 
 int elementwise_blocks(int64_t n) {
