@@ -2,18 +2,27 @@
 within 1e-3 relative L1 of the FP64 oracle's result, on one MI355X.
 
 A step is one complete unwrap (setup, IRLS weight updates, PCG solves with
-the DCT preconditioner, mean removal) of one 8192 x 8192 field, timed with
-HIP events from X resident in HBM to U resident in HBM; the clock stops at
-the first IRLS iterate whose L1 is within 1e-3 of the stored oracle value.
+the cosine-basis preconditioner, mean removal) of one 8192 x 8192 field
+(mixed FP16 by default), timed with HIP events from X resident in HBM to U
+resident in HBM; the clock stops at the first IRLS iterate whose L1 is
+within 1e-3 of the stored oracle value.
 
 Also reported on the same JSON line:
-* roofline of the dominant kernel (the MFMA cosine-basis products of the
-  preconditioner), each launch timed live with HIP events on the launch
-  stream; flops are the dense-equivalent 4NM(N+M) per application (the
-  folded even/odd form executes half of them, reported beside);
-* the stencil's achieved HBM bandwidth (algorithmic 24 B/px, fused form);
+* kernels: every launch of one PCG iteration recorded with HIP events
+  inside the first warm-up unwrap, with its algorithmic bytes (HBM-bound
+  kernels) or dense-equivalent flops 4NM(N+M) per application (MFMA
+  products); roofline: the dominant one, with HBM traffic from the
+  committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload;
+* mfma_form: the same workload with the folded MFMA preconditioner;
+* cg_adaptive / augmented_form: the Section 4.3 schedule and the paper's
+  (U, V) form on the same workload;
+* precisions: the other plan precisions on the same workload;
 * cpu_baseline: the FP64 oracle on a bounded sample of the same workload,
   scaled by its recorded iteration counts to the same target.
+
+Other modes (one JSON line each): --batched (64 uneven tiles, batch vs
+looped single-tile plans), --paper-shapes (4000 x M), --kernels-only (a
+fixed launch sequence for counter runs).
 """
 from __future__ import annotations
 
