@@ -83,7 +83,8 @@ typedef struct irlsu_params {
                               otherwise */
   int32_t cg_schedule;     /* IRLSU_CG_FIXED (pcg_max per solve) or IRLSU_CG_ADAPTIVE */
   int32_t cg_m0;           /* adaptive: iteration cap of the first solve, m_CG(0). 5 */
-  int32_t reserved_;
+  int32_t sd_guard;        /* augmented form only (IRLSU_GUARD_*): sufficient-decrease
+                              condition of Theorem 3. IRLSU_GUARD_CHECK */
   double cg_eps_tol;       /* adaptive: significance threshold of Delta. 1e-3 */
   double cg_alpha;         /* adaptive: cap growth factor. 1.7 */
 } irlsu_params;
@@ -98,6 +99,16 @@ typedef struct irlsu_params {
  * ceil(cg_alpha * cap).  The missing m_CG(-1) is taken equal to m_CG(0). */
 enum { IRLSU_CG_FIXED = 0, IRLSU_CG_ADAPTIVE = 1 };
 
+/* Sufficient-decrease guard of the augmented form (irlsu_params.sd_guard).
+ * Theorem 3 bounds the convergence rate of Algorithm 1 when each solve ends
+ * at a point whose (prob:alt1) objective, at the weights W^k of that
+ * iteration, is no larger than at the candidate gradient step
+ *   x~ = x^k - grad / L,  L = 12 / tau + C_max^2 / delta,
+ * (eq:candidate-gd-step).  CHECK evaluates both after every solve and takes
+ * x~ when the solve did worse; CANDIDATE_ONLY takes x~ and runs no CG (the
+ * variant of the remark after Theorem 3, which converges far more slowly). */
+enum { IRLSU_GUARD_OFF = 0, IRLSU_GUARD_CHECK = 1, IRLSU_GUARD_CANDIDATE_ONLY = 2 };
+
 #define IRLSU_MAX_IRLS 256
 
 typedef struct irlsu_iter_stats {
@@ -108,7 +119,8 @@ typedef struct irlsu_iter_stats {
   int32_t status;     /* irlsu_status of solve k */
   double delta;       /* adaptive schedule: Delta before solve k (k >= 1), else 0 */
   int32_t pcg_cap;    /* iteration cap of solve k */
-  int32_t reserved_;
+  int32_t guard;      /* augmented form: 0 condition not checked, 1 it held after solve k,
+                         2 the candidate step of Theorem 3 replaced the solve's result */
 } irlsu_iter_stats;
 
 typedef struct irlsu_stats {
@@ -318,10 +330,13 @@ irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, doubl
  * started, then mean removal of U.  U^0 = 0, V^0 = D U^0 - G.  Inputs and
  * output as irlsu_unwrap (no warm start); params as irlsu_unwrap (eps and
  * the schedule fields are not used; l1_target stops at the first U^k with
- * L1 <= l1_target).  stats: iter[k].L1 = L1(U^k), iter[k].H =
- * F_delta(U^k, V^k) (the objective of the smoothed problem).  The
- * workspace (irlsu_augmented_workspace_bytes) is larger than irlsu_unwrap's.
- * Errors: ERR_INVALID_ARG (tau or delta <= 0, strides, nulls),
+ * L1 <= l1_target; sd_guard selects the Theorem 3 guard, IRLSU_GUARD_*).
+ * stats: iter[k].L1 = L1(U^k), iter[k].H = F_delta(U^k, V^k) (the
+ * objective of the smoothed problem), iter[k].guard the guard's outcome of
+ * solve k.  The workspace (irlsu_augmented_workspace_bytes) is larger than
+ * irlsu_unwrap's (three more vectors of each block hold the candidate).
+ * Errors: ERR_INVALID_ARG (tau or delta <= 0, sd_guard outside 0..2,
+ * strides, nulls),
  * ERR_WORKSPACE, ERR_NONFINITE, ERR_BAD_WEIGHTS, ERR_BREAKDOWN, ERR_HIP;
  * NOT_CONVERGED as irlsu_unwrap. */
 size_t irlsu_augmented_workspace_bytes(const irlsu_plan* plan);

@@ -96,12 +96,36 @@ class Augmented:
                          rc / (self.Dh + 1.0 / t))
 
 
+def candidate_step(U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch, tau, delta):
+    """The gradient step of Theorem 3 (eq:candidate-gd-step) from (U, V) at
+    the weights W: each block moves by -1/L times the partial gradient of the
+    (prob:alt1) objective at fixed W, with L of Theorem 3.
+
+    grad_U = (S^T (S U - G^v - V^v) + (U T - G^h - V^h) T^T) / tau
+    grad_V = C^2 V / W + (V - (D U - G)) / tau   (each slack block)
+    """
+    L = lipschitz_L(Cv, Ch, tau, delta)
+    ev = R.diff_v(U) - Gv - Vv
+    eh = R.diff_h(U) - Gh - Vh
+    gU = R.div(ev, eh) / tau
+    gVv = Cv * Cv * Vv / Wv - ev / tau
+    gVh = Ch * Ch * Vh / Wh - eh / tau
+    return U - gU / L, Vv - gVv / L, Vh - gVh / L
+
+
 def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, tau=1e-2, delta=1e-6,
-         iters=20, tol=1e-8, maxit=100, max_cg=None):
+         iters=20, tol=1e-8, maxit=100, max_cg=None, guard=0):
     """Algorithm 1 verbatim; returns (U, Vv, Vh, history).
 
     ``max_cg`` (callable k -> int) overrides ``maxit`` per IRLS iteration,
     which is how the Section 4.3 schedule drives it.
+
+    ``guard`` -- the sufficient-decrease condition of Theorem 3
+    (eq:sufficient-decrease): 0 does not check it; 1 checks it after each CG
+    solve (the paper reports it always held) and takes the candidate step
+    when it fails; 2 takes only the candidate steps, no CG (the variant of
+    the remark after Theorem 3).  history[k]['guard'] is 0 (not checked),
+    1 (held) or 2 (candidate taken).
     """
     if G is None:
         Gv, Gh = R.wrapped_gradients(X)
@@ -115,13 +139,27 @@ def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, tau=1e-2, delta=1e-6,
     for k in range(iters):
         Wv, Wh = closed_form_weights(Vv, Vh, Cv, Ch, delta)
         sysk = Augmented(Gv, Gh, Cv, Ch, Wv, Wh, tau)
-        x0 = sysk.join(U, Vv, Vh)
-        m = maxit if max_cg is None else max_cg(k)
-        x, info = R.pcg(sysk.A, sysk.precond, sysk.rhs(), x0, tol, m)
-        U, Vv, Vh = sysk.split(x)
+        cand = None
+        if guard:
+            cand = candidate_step(U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch, tau, delta)
+        if guard == 2:
+            U, Vv, Vh = cand
+            info, g = dict(iters=0), 2
+        else:
+            x0 = sysk.join(U, Vv, Vh)
+            m = maxit if max_cg is None else max_cg(k)
+            x, info = R.pcg(sysk.A, sysk.precond, sysk.rhs(), x0, tol, m)
+            U, Vv, Vh = sysk.split(x)
+            g = 0
+            if guard == 1:
+                h_new = h_delta(U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch, tau, delta)
+                h_cand = h_delta(*cand, Wv, Wh, Gv, Gh, Cv, Ch, tau, delta)
+                g = 1 if h_new <= h_cand else 2
+                if g == 2:
+                    U, Vv, Vh = cand
         U = U - U.mean()
         hist.append(dict(k=k, F_delta=f_delta(U, Vv, Vh, Gv, Gh, Cv, Ch, tau, delta),
-                         L1=R.l1_objective(U, Gv, Gh, Cv, Ch), **info))
+                         L1=R.l1_objective(U, Gv, Gh, Cv, Ch), guard=g, **info))
     return U, Vv, Vh, hist
 
 
@@ -151,5 +189,5 @@ def lipschitz_L(Cv, Ch, tau, delta):
     return 12.0 / tau + cmax * cmax / delta
 
 
-__all__ = ["f_delta", "closed_form_weights", "Augmented", "irls",
+__all__ = ["f_delta", "closed_form_weights", "Augmented", "irls", "candidate_step",
            "schur_solve", "smoothing_gap_bound", "lipschitz_L", "h_delta"]

@@ -58,19 +58,21 @@ class Params(ctypes.Structure):
         ("pcg_max", ctypes.c_int32), ("true_res_every", ctypes.c_int32),
         ("poll_every", ctypes.c_int32), ("flexible", ctypes.c_int32),
         ("cg_schedule", ctypes.c_int32), ("cg_m0", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32), ("cg_eps_tol", ctypes.c_double),
+        ("sd_guard", ctypes.c_int32), ("cg_eps_tol", ctypes.c_double),
         ("cg_alpha", ctypes.c_double),
     ]
 
 
 CG_SCHEDULES = {"fixed": 0, "adaptive": 1}
+# Sufficient-decrease guard of the augmented form (Theorem 3)
+SD_GUARDS = {"off": 0, "check": 1, "candidate_only": 2}
 
 
 class IterStats(ctypes.Structure):
     _fields_ = [("L1", ctypes.c_double), ("H", ctypes.c_double),
                 ("relres", ctypes.c_double), ("pcg_iters", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("delta", ctypes.c_double),
-                ("pcg_cap", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("pcg_cap", ctypes.c_int32), ("guard", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -87,7 +89,8 @@ class Stats(ctypes.Structure):
         hist = [dict(k=k, L1=self.iter[k].L1, H=self.iter[k].H,
                      relres=self.iter[k].relres, iters=self.iter[k].pcg_iters,
                      status=self.iter[k].status, delta=self.iter[k].delta,
-                     cap=self.iter[k].pcg_cap) for k in range(min(n + 1, IRLSU_MAX_IRLS))]
+                     cap=self.iter[k].pcg_cap, guard=self.iter[k].guard)
+                for k in range(min(n + 1, IRLSU_MAX_IRLS))]
         return dict(irls_done=n, pcg_total=self.pcg_total,
                     target_hit=bool(self.target_hit), status=self.status,
                     L1_final=self.L1_final, H_final=self.H_final,

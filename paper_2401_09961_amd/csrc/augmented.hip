@@ -278,6 +278,139 @@ __global__ __launch_bounds__(kThreads) void aug_center_kernel(AugArgs<T> a, T* u
     if (k % a.ld < a.M) u[k] = (T)((double)u[k] - mean);
 }
 
+// ---- sufficient-decrease guard of Theorem 3 ---------------------------------
+// DU - G - V on the vertical / horizontal edge at (i, j); 0 off the grid.
+template <class T>
+__device__ __forceinline__ double gev_at(const AugArgs<T>& a, const AugVec<T>& x,
+                                         const EdgeIdx<T>& g, int64_t i, int64_t j) {
+  return g.vert(i, j) ? ev_at(x, g, i, j) - (double)a.Gv[i * g.ld + j] : 0.0;
+}
+template <class T>
+__device__ __forceinline__ double geh_at(const AugArgs<T>& a, const AugVec<T>& x,
+                                         const EdgeIdx<T>& g, int64_t i, int64_t j) {
+  return g.horz(i, j) ? eh_at(x, g, i, j) - (double)a.Gh[i * g.ld + j] : 0.0;
+}
+
+// Candidate x~ = x - grad / L of (eq:candidate-gd-step), the gradient of the
+// (prob:alt1) objective at the current weights (d = C^2 / W):
+//   grad_U = D^T (DU - G - V) / tau,  grad_V = d V - (DU - G - V) / tau.
+template <class T>
+__global__ __launch_bounds__(kThreads) void aug_cand_kernel(AugArgs<T> a, AugVec<T> x,
+                                                           AugVec<T> c) {
+  const EdgeIdx<T> g{a.N, a.M, a.ld};
+  const int64_t n = a.Np * a.ld;
+  const double it = 1.0 / a.tau, invL = a.st.sc[SC_INVL];
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = k / a.ld, j = k % a.ld;
+    double cu = 0.0, cv = 0.0, ch = 0.0;
+    if (i < a.N && j < a.M) {
+      const double ev = gev_at(a, x, g, i, j), eh = geh_at(a, x, g, i, j);
+      const double gu =
+          (-ev + gev_at(a, x, g, i - 1, j) - eh + geh_at(a, x, g, i, j - 1)) * it;
+      cu = (double)x.u[k] - gu * invL;
+      if (g.vert(i, j)) {
+        const double v = (double)x.v[k];
+        cv = v - ((double)a.dv[k] * v - ev * it) * invL;
+      }
+      if (g.horz(i, j)) {
+        const double h = (double)x.h[k];
+        ch = h - ((double)a.dh[k] * h - eh * it) * invL;
+      }
+    }
+    c.u[k] = (T)cu;
+    c.v[k] = (T)cv;
+    c.h[k] = (T)ch;
+  }
+}
+
+// Block maximum of v over the block's threads (thread 0 returns it).
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double sm[kThreads];
+  sm[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return sm[0];
+}
+
+// C_max of Theorem 3 over the edge weights: one maximum per block as partial.
+template <class T>
+__global__ __launch_bounds__(kThreads) void aug_cmax_kernel(AugArgs<T> a) {
+  const EdgeIdx<T> g{a.N, a.M, a.ld};
+  double m = 0.0;
+  const int64_t n = a.Np * a.ld;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = k / a.ld, j = k % a.ld;
+    if (g.vert(i, j)) m = fmax(m, (double)a.Cv[k]);
+    if (g.horz(i, j)) m = fmax(m, (double)a.Ch[k]);
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) a.st.part[(size_t)PR_AUX * kMaxPartials + a.st.off + blockIdx.x] = m;
+}
+
+// 1 / L, L = 12 / tau + C_max^2 / delta (Theorem 3), into SC_INVL.
+__global__ __launch_bounds__(kThreads) void aug_invl_kernel(DevState st, int nparts, double tau,
+                                                           double delta) {
+  const double* p = st.part + (size_t)PR_AUX * kMaxPartials + st.off;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) m = fmax(m, p[i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) st.sc[SC_INVL] = 1.0 / (12.0 / tau + m * m / delta);
+}
+
+// Partial of the (prob:alt1) objective of x at the current weights,
+// 1/2 sum ((C^2 V^2 + delta^2) / W + W) + sum (DU - G - V)^2 / (2 tau), with
+// W = C^2 / d from the stored d (both guard evaluations use the same W).
+template <class T>
+__global__ __launch_bounds__(kThreads) void aug_hval_kernel(AugArgs<T> a, AugVec<T> x) {
+  const EdgeIdx<T> g{a.N, a.M, a.ld};
+  double acc[1] = {0.0};
+  const int64_t n = a.Np * a.ld;
+  const double dl2 = a.delta * a.delta, h2t = 0.5 / a.tau;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = k / a.ld, j = k % a.ld;
+    if (g.vert(i, j)) {
+      const double c = (double)a.Cv[k], d = (double)a.dv[k], v = (double)x.v[k];
+      const double w = c * c / d, e = gev_at(a, x, g, i, j);
+      acc[0] += 0.5 * (d * v * v + dl2 / w + w) + h2t * e * e;
+    }
+    if (g.horz(i, j)) {
+      const double c = (double)a.Ch[k], d = (double)a.dh[k], v = (double)x.h[k];
+      const double w = c * c / d, e = geh_at(a, x, g, i, j);
+      acc[0] += 0.5 * (d * v * v + dl2 / w + w) + h2t * e * e;
+    }
+  }
+  const int slots[1] = {PR_AUX};
+  write_partials<1>(a.st, slots, acc, (int)blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void aug_store_kernel(DevState st, int nparts, int sc) {
+  const double v = reduce_slot(st, PR_AUX, nparts);
+  if (threadIdx.x == 0) st.sc[sc] = v;
+}
+
+// mode 1: keep the solve's x when its objective is no larger than the
+// candidate's (the condition of Theorem 3), else x = c; mode 2: x = c.
+template <class T>
+__global__ __launch_bounds__(kThreads) void aug_guard_kernel(AugArgs<T> a, AugVec<T> x,
+                                                            AugVec<T> c, int mode) {
+  const bool take = mode == 2 || !(a.st.sc[SC_SNEW] <= a.st.sc[SC_SOLD]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.st.fl[FL_GUARD] = take ? 2 : 1;
+  if (!take) return;
+  const int64_t n = a.Np * a.ld;
+  for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kThreads) {
+    x.u[k] = c.u[k];
+    x.v[k] = c.v[k];
+    x.h[k] = c.h[k];
+  }
+}
+
 // Objectives into scalars: F_delta -> SC_H, L1 -> SC_L1.
 __global__ __launch_bounds__(kThreads) void aug_objectives_kernel(DevState st, int nparts) {
   const double f = reduce_slot(st, PT_A, nparts);
@@ -337,6 +470,20 @@ int aug_launch(int op, const AugArgs<T>& a, const AugVec<T>& x, const AugVec<T>&
     case AUG_CENTER:
       hipLaunchKernelGGL(aug_sum_kernel<T>, g, b, 0, s, a, x.u);
       hipLaunchKernelGGL(aug_center_kernel<T>, g, b, 0, s, a, x.u, nb);
+      break;
+    case AUG_CAND:  // x -> y
+      hipLaunchKernelGGL(aug_cand_kernel<T>, g, b, 0, s, a, x, y);
+      break;
+    case AUG_INVL:
+      hipLaunchKernelGGL(aug_cmax_kernel<T>, g, b, 0, s, a);
+      hipLaunchKernelGGL(aug_invl_kernel, dim3(1), b, 0, s, a.st, nb, a.tau, a.delta);
+      break;
+    case AUG_HVAL:  // x -> sc[i0]
+      hipLaunchKernelGGL(aug_hval_kernel<T>, g, b, 0, s, a, x);
+      hipLaunchKernelGGL(aug_store_kernel, dim3(1), b, 0, s, a.st, nb, i0);
+      break;
+    case AUG_GUARD:  // x, y = candidate; i0 = mode
+      hipLaunchKernelGGL(aug_guard_kernel<T>, g, b, 0, s, a, x, y, i0);
       break;
   }
   return nb;

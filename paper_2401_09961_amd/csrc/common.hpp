@@ -29,6 +29,7 @@ enum Scalar : int {
   SC_SCALE = 13,   // FP16 preconditioner input scale
   SC_SOLD = 14,    // IRLS model at U^k with the previous weights
   SC_SNEW = 15,    // IRLS model at U^k with the new weights
+  SC_INVL = 16,    // augmented form: 1 / L of Theorem 3
   SC_COUNT = 32
 };
 
@@ -38,6 +39,7 @@ enum Flag : int {
   FL_ITERS = 1,    // PCG iterations performed
   FL_STATUS = 2,   // bit 0: breakdown
   FL_INPUT = 3,    // bit 0: non-finite input, bit 1: weight <= 0
+  FL_GUARD = 4,    // augmented form: outcome of the sufficient-decrease guard
   FL_COUNT = 16
 };
 

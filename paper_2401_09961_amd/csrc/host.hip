@@ -793,9 +793,10 @@ irlsu_status check_ws(const irlsu_plan* pl, const void* ws, size_t bytes) {
 
 // ---- augmented form (Algorithm 1 in (U, V^v, V^h)) --------------------------
 // Workspace: the plan's layout (setup outputs, preconditioner buffers,
-// partial sums, scalars, flags) followed by 13 vectors: x (3), and the slack
-// blocks of r, z, p, q, b (the U blocks reuse r, z, p0, q, b of the layout).
-static constexpr int kAugExtra = 13;
+// partial sums, scalars, flags) followed by 16 vectors: x (3), the slack
+// blocks of r, z, p, q, b (the U blocks reuse r, z, p0, q, b of the layout)
+// and the guard's candidate (3).
+static constexpr int kAugExtra = 16;
 
 static size_t aug_bytes(const irlsu_plan* p) {
   const size_t vec = align_up((size_t)p->Np * (size_t)p->Mp * p->elem);
@@ -867,7 +868,11 @@ irlsu_status aug_unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w
   const AugVec<T> p{W.v[V_P0], ev[7], ev[8]};
   const AugVec<T> q{W.v[V_Q], ev[9], ev[10]};
   const AugVec<T> b{W.v[V_B], ev[11], ev[12]};
+  const AugVec<T> cand{ev[13], ev[14], ev[15]};
   const AugVec<T> none{nullptr, nullptr, nullptr};
+  const int guard = prm.sd_guard;
+  if (guard != IRLSU_GUARD_OFF)  // 1 / L of Theorem 3 into SC_INVL
+    aug_launch<T>(AUG_INVL, a, none, none, none, none, 0, 0, 0, 0.0, s);
   const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
   // right-hand side (fixed by G) and the start U^0 = 0, V^0 = -G
   aug_launch<T>(AUG_RHS, a, x, b, none, none, 1, 0, 0, tol2, s);
@@ -887,6 +892,25 @@ irlsu_status aug_unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w
     if (prm.l1_target > 0.0 && pl->h_sc[SC_L1] <= prm.l1_target) {
       target_hit = true;
       break;
+    }
+    if (guard != IRLSU_GUARD_OFF) {
+      aug_launch<T>(AUG_CAND, a, x, cand, none, none, 0, 0, 0, 0.0, s);
+      if (guard == IRLSU_GUARD_CHECK)
+        aug_launch<T>(AUG_HVAL, a, cand, none, none, none, SC_SOLD, 0, 0, 0.0, s);
+    }
+    if (guard == IRLSU_GUARD_CANDIDATE_ONLY) {
+      // the remark after Theorem 3: the candidate step replaces the solve
+      aug_launch<T>(AUG_GUARD, a, x, cand, none, none, IRLSU_GUARD_CANDIDATE_ONLY, 0, 0, 0.0,
+                    s);
+      if (stats && k < IRLSU_MAX_IRLS) {
+        stats->iter[k].pcg_iters = 0;
+        stats->iter[k].status = IRLSU_OK;
+        stats->iter[k].relres = 0.0;
+        stats->iter[k].guard = 2;
+      }
+      done_iters = k + 1;
+      aug_launch<T>(AUG_CENTER, a, x, none, none, none, 0, 0, 0, 0.0, s);
+      continue;
     }
     // ---- Algorithm 2 on the augmented system, warm start from (U, V) ----
     aug_launch<T>(AUG_START, a, none, none, none, none, 0, 0, 0, tol2, s);
@@ -913,6 +937,10 @@ irlsu_status aug_unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w
       }
     }
     launch_finalize_rr(st, nvec, s);
+    if (guard == IRLSU_GUARD_CHECK) {
+      aug_launch<T>(AUG_HVAL, a, x, none, none, none, SC_SNEW, 0, 0, 0.0, s);
+      aug_launch<T>(AUG_GUARD, a, x, cand, none, none, IRLSU_GUARD_CHECK, 0, 0, 0.0, s);
+    }
     rs = read_back(pl, W, s);
     if (rs != IRLSU_OK) return rs;
     const int iters = pl->h_flags[FL_ITERS];
@@ -924,6 +952,7 @@ irlsu_status aug_unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w
       stats->iter[k].status = solve_st;
       const double bb = pl->h_sc[SC_BB];
       stats->iter[k].relres = bb > 0 ? std::sqrt(pl->h_sc[SC_RR] / bb) : 0.0;
+      stats->iter[k].guard = guard == IRLSU_GUARD_CHECK ? pl->h_flags[FL_GUARD] : 0;
     }
     pcg_total += iters;
     done_iters = k + 1;
@@ -988,6 +1017,7 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec) {
   p->cg_m0 = 5;
   p->cg_eps_tol = 1e-3;
   p->cg_alpha = 1.7;
+  p->sd_guard = IRLSU_GUARD_CHECK;
   return IRLSU_OK;
 }
 
@@ -1478,7 +1508,8 @@ irlsu_status irlsu_unwrap_augmented(irlsu_plan* plan, const void* X, int64_t ldx
     irlsu_params_default(&prm, plan->prec);
   }
   if (prm.irls_iters < 0 || prm.pcg_max < 1 || prm.true_res_every < 0 || prm.poll_every < 0 ||
-      !(prm.pcg_rtol >= 0.0))
+      !(prm.pcg_rtol >= 0.0) || prm.sd_guard < IRLSU_GUARD_OFF ||
+      prm.sd_guard > IRLSU_GUARD_CANDIDATE_ONLY)
     return IRLSU_ERR_INVALID_ARG;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -253,7 +253,11 @@ enum AugOp : int {
   AUG_PUPDATE = 5,    // x = z, y = p; i0 = iter, i1 / i2 = partials of z.r (U / slack)
   AUG_APPLY = 6,      // x = p -> y = q
   AUG_AXPY = 7,       // x, y = r, z = p, w = q; i0 = iter, i1 = p.q partials
-  AUG_CENTER = 8      // x.u -= mean
+  AUG_CENTER = 8,     // x.u -= mean
+  AUG_CAND = 9,       // x -> y = candidate step of Theorem 3 (1 / L from SC_INVL)
+  AUG_HVAL = 10,      // (prob:alt1) objective of x at the current weights -> sc[i0]
+  AUG_GUARD = 11,     // x = y when sc[SC_SNEW] > sc[SC_SOLD] or i0 == 2; FL_GUARD
+  AUG_INVL = 12       // 1 / L = 1 / (12 / tau + C_max^2 / delta) into SC_INVL
 };
 template <class T>
 int aug_launch(int op, const AugArgs<T>& a, const AugVec<T>& x, const AugVec<T>& y,

@@ -21,12 +21,14 @@ pytestmark = pytest.mark.gpu
 TAU, DELTA = 1e-2, 1e-6
 
 
-def run_gpu(f, prec, iters, tol, maxit, weights=True):
+def run_gpu(f, prec, iters, tol, maxit, weights=True, guard=None):
     dt = np.float64 if prec == "f64" else np.float32
     N, M = f.X.shape
     plan = pkg.Plan(N, M, prec)
     p = pkg.default_params(prec)
     p.irls_iters, p.pcg_rtol, p.pcg_max = iters, tol, maxit
+    if guard is not None:
+        p.sd_guard = pkg.SD_GUARDS[guard]
     w = torch.from_numpy(f.w.astype(dt)).cuda() if (weights and f.w is not None) else None
     U, st = plan.unwrap_augmented(torch.from_numpy(f.X.astype(dt)).cuda(), w, tau=TAU,
                                   delta=DELTA, params=p, stats=True)
@@ -80,4 +82,56 @@ def test_invalid_arguments():
         plan.unwrap_augmented(X, tau=0.0)
     with pytest.raises(pkg.IrlsuError):
         plan.unwrap_augmented(X, delta=-1.0)
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Theorem 3 guard
+# ---------------------------------------------------------------------------
+def test_guard_holds_after_each_solve_like_the_oracle():
+    """Default check mode: the sufficient-decrease condition holds after
+    every solve (as the paper reports and as the oracle finds on the same
+    field), so the result equals the unguarded run's."""
+    f = synth.field_c2(4, 48, 40)
+    K = 4
+    Ug, st = run_gpu(f, "f64", K, 1e-12, 3000, guard="check")
+    U0, st0 = run_gpu(f, "f64", K, 1e-12, 3000, guard="off")
+    _, _, _, hist = PF.irls(f.X, w=f.w, tau=TAU, delta=DELTA, iters=K, tol=1e-12, maxit=3000,
+                            guard=1)
+    assert [st["history"][k]["guard"] for k in range(K)] == [h["guard"] for h in hist] == [1] * K
+    assert [st0["history"][k]["guard"] for k in range(K)] == [0] * K
+    assert np.array_equal(Ug, U0)
+
+
+@pytest.mark.parametrize("shape", [(33, 20), (64, 48)])
+def test_candidate_only_matches_oracle_elementwise(shape):
+    """Candidate-only mode (the variant of the remark after Theorem 3): no
+    CG, each iteration is the gradient step x - grad / L at the closed-form
+    weights, then mean removal -- pointwise FP64 arithmetic with one
+    reduction (C_max, exact) and the mean, so U agrees to 1e-12 of its
+    size, and F_delta decreases at every iteration."""
+    f = synth.field_c2(6, *shape)
+    K = 5
+    Ug, st = run_gpu(f, "f64", K, 1e-12, 100, guard="candidate_only")
+    Uo, _, _, hist = PF.irls(f.X, w=f.w, tau=TAU, delta=DELTA, iters=K, guard=2)
+    assert [st["history"][k]["guard"] for k in range(K)] == [2] * K
+    assert st["pcg_total"] == 0
+    scale = max(np.abs(Uo).max(), 1e-300)
+    print(f"candidate-only {shape}: max |dU| {np.abs(Ug - Uo).max():.3e} (|U| {scale:.3e})")
+    assert np.abs(Ug - Uo).max() <= 1e-12 * scale
+    for k in range(K):
+        a, b = st["history"][k + 1]["H"], hist[k]["F_delta"]
+        assert abs(a - b) <= 1e-12 * abs(b), k
+    F = [st["history"][k]["H"] for k in range(K + 1)]
+    assert all(F[k + 1] <= F[k] for k in range(K))
+
+
+def test_guard_mode_is_validated():
+    plan = pkg.Plan(16, 16, "f64")
+    X = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    p = pkg.default_params("f64")
+    assert p.sd_guard == pkg.SD_GUARDS["check"]
+    p.sd_guard = 3
+    with pytest.raises(pkg.IrlsuError):
+        plan.unwrap_augmented(X, params=p)
     plan.close()

@@ -423,6 +423,104 @@ def test_paper_form_alg1_monotone_f_delta():
 
 
 # ---------------------------------------------------------------------------
+# Theorem 3: the candidate gradient step and the sufficient-decrease guard
+# ---------------------------------------------------------------------------
+def _thm3_problem(seed, N=6, M=5, delta=0.05):
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((N, M))
+    Gv, Gh = rng.uniform(-PI, PI, (N - 1, M)), rng.uniform(-PI, PI, (N, M - 1))
+    Vv, Vh = rng.standard_normal((N - 1, M)), rng.standard_normal((N, M - 1))
+    Cv, Ch = rng.uniform(0.1, 2, (N - 1, M)), rng.uniform(0.1, 2, (N, M - 1))
+    # weights of the previous iterate (not those of V: the step is taken at W^k)
+    Wv, Wh = PF.closed_form_weights(rng.standard_normal((N - 1, M)),
+                                    rng.standard_normal((N, M - 1)), Cv, Ch, delta)
+    return U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch
+
+
+def _pack(U, Vv, Vh):
+    return np.concatenate([U.ravel(), Vv.ravel(), Vh.ravel()])
+
+
+def _unpack(x, N, M):
+    a, b = N * M, N * M + (N - 1) * M
+    return x[:a].reshape(N, M), x[a:b].reshape(N - 1, M), x[b:].reshape(N, M - 1)
+
+
+def test_thm3_candidate_direction_is_the_gradient_by_finite_differences():
+    """(x - x~) L must equal the gradient of the (prob:alt1) objective at
+    fixed W, here by central differences of h_delta itself."""
+    tau, delta = 0.3, 0.05
+    U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch = _thm3_problem(1, delta=delta)
+    N, M = U.shape
+    L = PF.lipschitz_L(Cv, Ch, tau, delta)
+    x = _pack(U, Vv, Vh)
+    step = (x - _pack(*PF.candidate_step(U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch, tau, delta))) * L
+    h = lambda y: PF.h_delta(*_unpack(y, N, M), Wv, Wh, Gv, Gh, Cv, Ch, tau, delta)
+    eps = 1e-6
+    fd = np.array([(h(x + eps * e) - h(x - eps * e)) / (2 * eps) for e in np.eye(x.size)])
+    assert np.abs(fd - step).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_thm3_L_bounds_the_hessian_and_gives_the_descent_lemma():
+    """L = 12/tau + C_max^2/delta bounds the largest Hessian eigenvalue of
+    the objective at fixed W >= delta (dense eigvalsh), so the step decreases
+    it by at least ||grad||^2 / (2L) (descent lemma)."""
+    tau, delta = 0.2, 0.05
+    for seed in range(5):
+        U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch = _thm3_problem(seed, delta=delta)
+        N, M = U.shape
+        L = PF.lipschitz_L(Cv, Ch, tau, delta)
+        x = _pack(U, Vv, Vh)
+        h = lambda y: PF.h_delta(*_unpack(y, N, M), Wv, Wh, Gv, Gh, Cv, Ch, tau, delta)
+        n = x.size
+        # the objective is quadratic in x at fixed W: Hessian by second differences
+        H = np.zeros((n, n))
+        E = np.eye(n)
+        h0 = h(np.zeros(n))
+        for i in range(n):
+            for j in range(i, n):
+                H[i, j] = H[j, i] = h(E[i] + E[j]) - h(E[i]) - h(E[j]) + h0
+        lam = np.linalg.eigvalsh(H)
+        assert lam[0] > -1e-9 and lam[-1] <= L
+        xc = _pack(*PF.candidate_step(U, Vv, Vh, Wv, Wh, Gv, Gh, Cv, Ch, tau, delta))
+        g = (x - xc) * L
+        assert h(xc) <= h(x) - g @ g / (2 * L) + 1e-12 * abs(h(x))
+
+
+def test_thm3_condition_holds_after_cg_and_candidate_only_is_monotone():
+    """The paper reports the condition always held after CG: so it does in
+    the guarded oracle run, which then equals the unguarded one.  The
+    candidate-only variant decreases F_delta at every iteration (alternating
+    minimisation over W never increases it) but far more slowly."""
+    f = synth.field_c2(2, 16, 14)
+    kw = dict(w=f.w, tau=1e-2, delta=1e-6, iters=6, tol=1e-12, maxit=400)
+    U1, _, _, h1 = PF.irls(f.X, guard=1, **kw)
+    U0, _, _, h0 = PF.irls(f.X, guard=0, **kw)
+    assert all(h["guard"] == 1 for h in h1)
+    assert np.array_equal(U1, U0)
+    U2, _, _, h2 = PF.irls(f.X, guard=2, **kw)
+    F2 = [h["F_delta"] for h in h2]
+    assert all(h["guard"] == 2 for h in h2)
+    assert all(F2[k + 1] <= F2[k] for k in range(len(F2) - 1))
+    assert F2[-1] > h1[-1]["F_delta"] * 1.01
+
+
+def test_thm3_guard_takes_the_candidate_when_cg_does_worse():
+    """Planted on the CPU: a 'solver' that returns a worse point than the
+    start must be replaced by the candidate step."""
+    f = synth.field_c2(3, 12, 10)
+    real = R.pcg
+    try:
+        R.pcg = lambda A, P, b, x0, tol, m: (x0 + 0.5, dict(iters=1))
+        U, _, _, h = PF.irls(f.X, w=f.w, tau=1e-2, delta=1e-6, iters=2, guard=1)
+    finally:
+        R.pcg = real
+    U2, _, _, h2 = PF.irls(f.X, w=f.w, tau=1e-2, delta=1e-6, iters=2, guard=2)
+    assert [x["guard"] for x in h] == [2, 2]
+    assert np.allclose(U, U2, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
 # Section 4.3 schedule rules
 # ---------------------------------------------------------------------------
 def test_schedule_rules_with_paper_parameters():
