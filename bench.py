@@ -410,7 +410,7 @@ def kernels_only(pkg, torch, N, M, prec):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5, help="timed unwraps (the median is reported beside the mean)")
     ap.add_argument("--warmup", type=int, default=1, help="at least 1 (it records the kernel table)")
     ap.add_argument("--config", choices=sorted(CONFIGS), default="c3")
     ap.add_argument("--precision", choices=["f64", "f32", "bf16", "f16"], default=None)

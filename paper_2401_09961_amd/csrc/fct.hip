@@ -68,6 +68,19 @@ template <class CT>
 __device__ __forceinline__ Cx<CT> cscale(Cx<CT> a, CT s) {
   return {a.x * s, a.y * s};
 }
+// 1 / x: correctly rounded in FP64; in FP32 the hardware reciprocal (1 ulp),
+// well inside the FP32 transform's own rounding
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // ---- small forward DFTs in registers (natural order in and out) ----------
 template <class CT>
@@ -79,10 +92,11 @@ __device__ __forceinline__ void dft4(Cx<CT>& a0, Cx<CT>& a1, Cx<CT>& a2, Cx<CT>&
   a3 = csub(t1, t3);
 }
 
-// e^{-2 pi i j / 16}, j = 0..9 (the twiddles of the 4 x 4 split)
+// e^{-2 pi i j / 16}, j = 0..15 (the twiddles of the 4 x 4 split)
 template <class CT>
 __device__ __forceinline__ Cx<CT> w16(int j) {
-  constexpr double c[10] = {1.0,
+  // cos(2 pi j / 16) for j = 0..15; sin is the cosine a quarter turn back
+  constexpr double c[16] = {1.0,
                             0.92387953251128675613,
                             0.70710678118654752440,
                             0.38268343236508977173,
@@ -91,18 +105,42 @@ __device__ __forceinline__ Cx<CT> w16(int j) {
                             -0.70710678118654752440,
                             -0.92387953251128675613,
                             -1.0,
-                            -0.92387953251128675613};
-  constexpr double s[10] = {0.0,
-                            0.38268343236508977173,
-                            0.70710678118654752440,
-                            0.92387953251128675613,
-                            1.0,
-                            0.92387953251128675613,
-                            0.70710678118654752440,
-                            0.38268343236508977173,
+                            -0.92387953251128675613,
+                            -0.70710678118654752440,
+                            -0.38268343236508977173,
                             0.0,
-                            -0.38268343236508977173};
-  return {(CT)c[j], (CT)(-s[j])};
+                            0.38268343236508977173,
+                            0.70710678118654752440,
+                            0.92387953251128675613};
+  return {(CT)c[j & 15], (CT)(-c[(j + 12) & 15])};
+}
+
+// a * e^{-2 pi i J / 16} for a compile-time J: quarter turns by swaps and
+// sign changes, odd eighth turns by one add and one multiply per part, the
+// rest by a complex product with the constant.
+template <class CT, int J>
+__device__ __forceinline__ Cx<CT> mul_w16(Cx<CT> a) {
+  constexpr int j = J & 15;
+  constexpr CT h = (CT)0.70710678118654752440;
+  if constexpr (j == 0) {
+    return a;
+  } else if constexpr (j == 4) {
+    return mul_mi(a);
+  } else if constexpr (j == 8) {
+    return {-a.x, -a.y};
+  } else if constexpr (j == 12) {
+    return mul_i(a);
+  } else if constexpr (j == 2) {   // h (1 - i)
+    return {(a.x + a.y) * h, (a.y - a.x) * h};
+  } else if constexpr (j == 6) {   // h (-1 - i)
+    return {(a.y - a.x) * h, -(a.x + a.y) * h};
+  } else if constexpr (j == 10) {  // h (-1 + i)
+    return {-(a.x + a.y) * h, (a.x - a.y) * h};
+  } else if constexpr (j == 14) {  // h (1 + i)
+    return {(a.x - a.y) * h, (a.x + a.y) * h};
+  } else {
+    return cmul(a, w16<CT>(j));
+  }
 }
 
 template <class CT, int R>
@@ -117,11 +155,11 @@ __device__ __forceinline__ void dft(Cx<CT> (&a)[R]) {
     // n = 4 n1 + n2, k = k1 + 2 k2: length-2 DFTs over n1, twiddle
     // e^{-2 pi i n2 k1 / 8}, length-4 DFTs over n2
     Cx<CT> b0[4], b1[4];
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) {
+    static_for<0, 4>([&](auto c) {
+      constexpr int n2 = decltype(c)::value;
       b0[n2] = cadd(a[n2], a[4 + n2]);
-      b1[n2] = cmul(csub(a[n2], a[4 + n2]), w16<CT>(2 * n2));
-    }
+      b1[n2] = mul_w16<CT, 2 * n2>(csub(a[n2], a[4 + n2]));
+    });
     dft4(b0[0], b0[1], b0[2], b0[3]);
     dft4(b1[0], b1[1], b1[2], b1[3]);
 #pragma unroll
@@ -133,15 +171,15 @@ __device__ __forceinline__ void dft(Cx<CT> (&a)[R]) {
     static_assert(R == 16, "radix");
     // n = 4 n1 + n2, k = k1 + 4 k2
     Cx<CT> b[4][4];
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) {
+    static_for<0, 4>([&](auto c) {
+      constexpr int n2 = decltype(c)::value;
       Cx<CT> c0 = a[n2], c1 = a[4 + n2], c2 = a[8 + n2], c3 = a[12 + n2];
       dft4(c0, c1, c2, c3);
       b[0][n2] = c0;
-      b[1][n2] = cmul(c1, w16<CT>(n2));
-      b[2][n2] = cmul(c2, w16<CT>(2 * n2));
-      b[3][n2] = cmul(c3, w16<CT>(3 * n2));
-    }
+      b[1][n2] = mul_w16<CT, n2>(c1);
+      b[2][n2] = mul_w16<CT, 2 * n2>(c2);
+      b[3][n2] = mul_w16<CT, 3 * n2>(c3);
+    });
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
       dft4(b[k1][0], b[k1][1], b[k1][2], b[k1][3]);
@@ -163,50 +201,77 @@ constexpr int padded() {
 // real element e of the block's rows (two per complex slot)
 __device__ __forceinline__ int pr(int e) { return 2 * pc(e >> 1) + (e & 1); }
 
-// Twiddles w^r, w = e^{-2 pi i step / H}, r = 1..R-1: w, w^2, w^4, w^8 from
-// the table, the others as products of two of them (at most three
-// roundings each).
-template <class CT, int R>
-__device__ __forceinline__ void twiddles(const Cx<CT>* __restrict__ tw, int step, Cx<CT> (&w)[R]) {
-  w[1] = tw[step];
-  if constexpr (R > 2) {
-    w[2] = tw[2 * step];
-    w[3] = cmul(w[1], w[2]);
-  }
-  if constexpr (R > 4) {
-    w[4] = tw[4 * step];
-    w[5] = cmul(w[4], w[1]);
-    w[6] = cmul(w[4], w[2]);
-    w[7] = cmul(w[4], w[3]);
-  }
-  if constexpr (R > 8) {
-    w[8] = tw[8 * step];
+// Twiddles of the stage with span NS and radix R, from its table: entry
+// (NS - 1) + (r - 1) NS + k holds e^{-2 pi i r k / (NS R)}, r = 1..R-1,
+// k = 0..NS-1 (the stages' tables end to end fill h - 1 entries).  Each
+// value is rounded once from FP64, and a load replaces the products that
+// would form it.
+//
+// LOAD_ALL: every power from the table (fewest instructions; for passes bound
+// by arithmetic).  Otherwise w, w^2, w^4, w^8 from the table and the others
+// as products of two of them (at most three roundings; fewer loads, whose
+// waits would also wait for the pass's own HBM traffic).
+template <class CT, int R, int NS, bool LOAD_ALL>
+__device__ __forceinline__ void stage_twiddles(const Cx<CT>* __restrict__ tw, int k,
+                                               Cx<CT> (&w)[R]) {
+  const Cx<CT>* t = tw + (NS - 1) + k;
+  if constexpr (LOAD_ALL) {
 #pragma unroll
-    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    for (int r = 1; r < R; ++r) w[r] = t[(r - 1) * NS];
+  } else {
+    w[1] = t[0];
+    if constexpr (R > 2) {
+      w[2] = t[NS];
+      w[3] = cmul(w[1], w[2]);
+    }
+    if constexpr (R > 4) {
+      w[4] = t[3 * NS];
+      w[5] = cmul(w[4], w[1]);
+      w[6] = cmul(w[4], w[2]);
+      w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (R > 8) {
+      w[8] = t[7 * NS];
+#pragma unroll
+      for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    }
   }
 }
 
 // Stage with span NS and radix R: butterfly j of a row reads points
 // j + r H/R, applies e^{-2 pi i r (j mod NS) / (NS R)}, and writes the
 // R-point DFT to (j / NS) NS R + (j mod NS) + r NS.  In place: every thread
-// holds its butterflies in registers across a barrier.
-template <class CT, int H, int ROWS, int R, int NS>
-__device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict__ tw) {
+// holds its butterflies in registers across a barrier.  With the one-slot
+// pad per 16 points, the R points of a butterfly sit at constant offsets
+// from the first one (H/R and NS multiples of 16, or NS = 1 with R = 16
+// and the first point on a multiple of 16), so one address serves all R.
+template <class CT, int H, int ROWS, int R, int NS, bool LOAD_ALL>
+__device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict__ tw, int tid) {
   constexpr int BPR = H / R;
   constexpr int NB = ROWS * BPR / kThreads;
   static_assert(NB >= 1 && NB * kThreads == ROWS * BPR, "butterflies per thread");
+  constexpr bool RD_CONST = BPR % 16 == 0;
+  constexpr int RD_STRIDE = BPR + BPR / 16;
+  constexpr bool WR_CONST = NS % 16 == 0 || (NS == 1 && R == 16);
+  constexpr int WR_STRIDE = NS == 1 ? 1 : NS + NS / 16;
   Cx<CT> a[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int bi = threadIdx.x + b * kThreads;
+    const int bi = tid + b * kThreads;
     const int row = bi / BPR, j = bi % BPR;
     const int k = j % NS;
     const int src = row * H + j;
+    if constexpr (RD_CONST) {
+      const Cx<CT>* sp = buf + pc(src);
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[b][r] = buf[pc(src + r * BPR)];
+      for (int r = 0; r < R; ++r) a[b][r] = sp[r * RD_STRIDE];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[b][r] = buf[pc(src + r * BPR)];
+    }
     if constexpr (NS > 1) {
       Cx<CT> w[R];
-      twiddles<CT, R>(tw, k * (H / (NS * R)), w);
+      stage_twiddles<CT, R, NS, LOAD_ALL>(tw, k, w);
 #pragma unroll
       for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], w[r]);
     }
@@ -215,23 +280,29 @@ __device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict_
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int bi = threadIdx.x + b * kThreads;
+    const int bi = tid + b * kThreads;
     const int row = bi / BPR, j = bi % BPR;
     const int k = j % NS;
     const int dst = row * H + (j / NS) * NS * R + k;
+    if constexpr (WR_CONST) {
+      Cx<CT>* dp = buf + pc(dst);
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[pc(dst + r * NS)] = a[b][r];
+      for (int r = 0; r < R; ++r) dp[r * WR_STRIDE] = a[b][r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pc(dst + r * NS)] = a[b][r];
+    }
   }
   __syncthreads();
 }
 
-template <class CT, int H, int ROWS, int NS = 1>
-__device__ __forceinline__ void fft_rows(Cx<CT>* buf, const Cx<CT>* __restrict__ tw) {
+template <class CT, int H, int ROWS, bool LOAD_ALL, int NS = 1>
+__device__ __forceinline__ void fft_rows(Cx<CT>* buf, const Cx<CT>* __restrict__ tw, int tid) {
   if constexpr (NS < H) {
     constexpr int REM = H / NS;
     constexpr int R = REM >= 16 ? 16 : REM;
-    fft_stage<CT, H, ROWS, R, NS>(buf, tw);
-    fft_rows<CT, H, ROWS, NS * R>(buf, tw);
+    fft_stage<CT, H, ROWS, R, NS, LOAD_ALL>(buf, tw, tid);
+    fft_rows<CT, H, ROWS, LOAD_ALL, NS * R>(buf, tw, tid);
   }
 }
 
@@ -242,18 +313,21 @@ constexpr int rows_per_block() {
   return H >= 4096 ? 1 : 4096 / H;
 }
 
-// Twiddle tables of one side n = 2h (complex, CT): [0, h) e^{-2 pi i j/h};
-// [h, 2h] e^{-2 pi i k/n}, k = 0..h; [2h+1, 3h+1] e^{-i pi k/(2n)}, k = 0..h.
+// Tables of one side n = 2h (CT): complex [0, h - 1) the FFT stages'
+// twiddles (stage_twiddles), entry h - 1 unused; [h, 2h] e^{-2 pi i k/n},
+// k = 0..h; [2h+1, 3h+1] e^{-i pi k/(2n)}, k = 0..h; then n reals, the
+// eigenvalues 4 sin^2(pi k / 2n) of the side's Neumann second difference.
 template <class CT>
 struct Tw {
   const Cx<CT>* fft;
   const Cx<CT>* tn;
   const Cx<CT>* tq;
+  const CT* eig;
 };
 template <class CT, int H>
 __device__ __forceinline__ Tw<CT> tw_of(const void* p) {
   const Cx<CT>* t = static_cast<const Cx<CT>*>(p);
-  return {t, t + H, t + 2 * H + 1};
+  return {t, t + H, t + 2 * H + 1, reinterpret_cast<const CT*>(t + 3 * H + 2)};
 }
 
 // position of row element e in the even-up / odd-down sequence v
@@ -296,36 +370,102 @@ __device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<C
 
 // ---- row staging ----------------------------------------------------------
 // Every thread moves whole 16-byte chunks of the block's rows; all of a
-// thread's global loads are issued before the first LDS write, so a block
-// waits for memory once per pass rather than once per element.
+// thread's global loads are issued before its first LDS write.
 template <class T>
 struct Vec16 {
   static constexpr int W = 16 / (int)sizeof(T);
   typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
 };
 
-// LDS <- rows (even-up / odd-down order), as CT
-template <class CT, class TI, int H>
-__device__ __forceinline__ void stage_in(const TI* __restrict__ in, int64_t ld, int64_t row0,
-                                         CT* v, CT scale = (CT)1) {
-  constexpr int N = 2 * H, ROWS = rows_per_block<H>();
-  using V = typename Vec16<TI>::type;
-  constexpr int W = Vec16<TI>::W;
-  constexpr int NCH = ROWS * N / W / kThreads;
+template <class TI, int H>
+struct RowChunks {
+  static constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  static constexpr int W = Vec16<TI>::W;
+  static constexpr int NCH = ROWS * N / W / kThreads;
   static_assert(NCH * W * kThreads == ROWS * N, "chunks per thread");
-  V d[NCH];
+  typename Vec16<TI>::type d[NCH];
+};
+
+// registers <- the block's rows row0 .. row0 + ROWS - 1 (natural order)
+template <class TI, int H>
+__device__ __forceinline__ void load_rows(const TI* __restrict__ in, int64_t ld, int64_t row0,
+                                          RowChunks<TI, H>& ch, int tid) {
+  using RC = RowChunks<TI, H>;
+  using V = typename Vec16<TI>::type;
 #pragma unroll
-  for (int i = 0; i < NCH; ++i) {
-    const int e0 = (threadIdx.x + i * kThreads) * W;
-    const int row = e0 / N, c = e0 % N;
-    d[i] = *reinterpret_cast<const V*>(in + (row0 + row) * ld + c);
+  for (int i = 0; i < RC::NCH; ++i) {
+    const int e0 = (tid + i * kThreads) * RC::W;
+    const int row = e0 / RC::N, c = e0 % RC::N;
+    ch.d[i] = *reinterpret_cast<const V*>(in + (row0 + row) * ld + c);
   }
+}
+
+// LDS <- registers, in the even-up / odd-down order, as CT times scale
+template <class CT, class TI, int H>
+__device__ __forceinline__ void put_rows(const RowChunks<TI, H>& ch, CT* v, CT scale, int tid) {
+  using RC = RowChunks<TI, H>;
+  constexpr int N = RC::N, W = RC::W;
 #pragma unroll
-  for (int i = 0; i < NCH; ++i) {
-    const int e0 = (threadIdx.x + i * kThreads) * W;
+  for (int i = 0; i < RC::NCH; ++i) {
+    const int e0 = (tid + i * kThreads) * W;
+    const int row = e0 / N, c = e0 % N;
+    if constexpr (W >= 4) {
+      // a chunk of W elements at c (a multiple of W) fills W / 4 complex
+      // slots from the front (even elements, c/4 + s) and W / 4 from the back
+      // (odd ones, h - 1 - c/4 - s), two elements each
+      Cx<CT>* b = reinterpret_cast<Cx<CT>*>(v);
+#pragma unroll
+      for (int s4 = 0; s4 < W / 4; ++s4) {
+        b[pc(row * H + c / 4 + s4)] = {(CT)ch.d[i][4 * s4] * scale,
+                                       (CT)ch.d[i][4 * s4 + 2] * scale};
+        b[pc(row * H + H - 1 - c / 4 - s4)] = {(CT)ch.d[i][4 * s4 + 3] * scale,
+                                               (CT)ch.d[i][4 * s4 + 1] * scale};
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < W; ++t) v[pr(row * N + perm<N>(c + t))] = (CT)ch.d[i][t] * scale;
+    }
+  }
+}
+
+// LDS <- registers for the inverse pre-processing: element e of a row goes
+// to complex slot e (real part) for e < h and to slot (n - e) mod h
+// (imaginary part) for e >= h, so that slot k holds (x_k, x_{n-k}) and slot
+// h - k holds (x_{h-k}, x_{h+k}) -- the four inputs of pair k sit in the two
+// slots that pair k overwrites (slot 0 holds (x_0, x_h)).
+template <class CT, class TI, int H>
+__device__ __forceinline__ void put_rows_inv(const RowChunks<TI, H>& ch, Cx<CT>* buf, int tid) {
+  using RC = RowChunks<TI, H>;
+  constexpr int N = RC::N;
+  CT* v = reinterpret_cast<CT*>(buf);
+#pragma unroll
+  for (int i = 0; i < RC::NCH; ++i) {
+    const int e0 = (tid + i * kThreads) * RC::W;
     const int row = e0 / N, c = e0 % N;
 #pragma unroll
-    for (int t = 0; t < W; ++t) v[pr(row * N + perm<N>(c + t))] = (CT)d[i][t] * scale;
+    for (int t = 0; t < RC::W; ++t) {
+      const int e = c + t;
+      const int slot = e < H ? e : (N - e) & (H - 1);
+      v[2 * pc(row * H + slot) + (e < H ? 0 : 1)] = (CT)ch.d[i][t];
+    }
+  }
+}
+
+// W output elements at c (a multiple of W, W >= 4) of a row after the
+// inverse FFT, the inverse of put_rows' slot map:
+// w = conj(FFT(conj W)) / h, so odd positions take the negated imaginary part
+template <class CT, int H, int W, class OT>
+__device__ __forceinline__ void inv_chunk(const Cx<CT>* buf, int row, int c, CT inv_h,
+                                          OT (&o)[W]) {
+  static_assert(W >= 4 && W % 4 == 0, "chunk");
+#pragma unroll
+  for (int s4 = 0; s4 < W / 4; ++s4) {
+    const Cx<CT> A = buf[pc(row * H + c / 4 + s4)];
+    const Cx<CT> B = buf[pc(row * H + H - 1 - c / 4 - s4)];
+    o[4 * s4] = (OT)(A.x * inv_h);
+    o[4 * s4 + 1] = (OT)(-B.y * inv_h);
+    o[4 * s4 + 2] = (OT)(-A.y * inv_h);
+    o[4 * s4 + 3] = (OT)(B.x * inv_h);
   }
 }
 
@@ -351,15 +491,20 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
   __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
+  const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  stage_in<CT, TI, H>(in, ld, row0, v, dscale ? (CT)*dscale : (CT)1);
+  {
+    RowChunks<TI, H> ch;
+    load_rows<TI, H>(in, ld, row0, ch, tid);
+    put_rows<CT, TI, H>(ch, v, dscale ? (CT)*dscale : (CT)1, tid);
+  }
   __syncthreads();
-  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
   const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
 #pragma unroll
   for (int qq = 0; qq < PP; ++qq) {
-    const int p = threadIdx.x + qq * kThreads;
+    const int p = tid + qq * kThreads;
     if (p < ROWS * NP) {
       const int row = p / NP, k = p % NP;
       Cx<CT> ck, cp;
@@ -380,7 +525,6 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
 template <class CT, class ST, int H>
 __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io, int64_t ld,
                                                            const void* twp,
-                                                           const double* __restrict__ eig_k,
                                                            const double* __restrict__ eig_l,
                                                            const int32_t* done) {
   if (*done) return;
@@ -389,24 +533,29 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
   __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
+  const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  stage_in<CT, ST, H>(io, ld, row0, v);
+  {
+    RowChunks<ST, H> ch;
+    load_rows<ST, H>(io, ld, row0, ch, tid);
+    put_rows<CT, ST, H>(ch, v, (CT)1, tid);
+  }
   __syncthreads();
-  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  fft_rows<CT, H, ROWS, true>(buf, tw.fft, tid);
   // forward post-processing, division and inverse pre-processing of pair
   // (k, h-k), in place: the pair's two slots are read and written by the
   // same thread only.  With d = 1 / (lambda_k + mu_l), the scaled
   // coefficient divided by s_k is Re(c_k) d_k, and -Im(c_k) d_{n-k} at n-k.
 #pragma unroll
   for (int qq = 0; qq < PP; ++qq) {
-    const int p = threadIdx.x + qq * kThreads;
+    const int p = tid + qq * kThreads;
     if (p < ROWS * NP) {
       const int row = p / NP, k = p % NP;
       const int64_t l = row0 + row;
-      const double mu = eig_l[l];
+      const CT mu = (CT)eig_l[l];
       auto d = [&](int kk) -> CT {
-        return (l == 0 && kk == 0) ? (CT)0 : (CT)(1.0 / (eig_k[kk] + mu));
+        return (l == 0 && kk == 0) ? (CT)0 : recip(tw.eig[kk] + mu);
       };
       Cx<CT> ck, cp;
       post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
@@ -419,24 +568,34 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     }
   }
   __syncthreads();
-  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  fft_rows<CT, H, ROWS, true>(buf, tw.fft, tid);
   const CT inv_h = (CT)(1.0 / H);
   using V = typename Vec16<ST>::type;
   constexpr int W = Vec16<ST>::W;
   constexpr int NCH = ROWS * N / W / kThreads;
 #pragma unroll
   for (int i = 0; i < NCH; ++i) {
-    const int e0 = (threadIdx.x + i * kThreads) * W;
+    const int e0 = (tid + i * kThreads) * W;
     const int row = e0 / N, c = e0 % N;
     V o;
+    if constexpr (W >= 4) {
+      ST ot[W];
+      inv_chunk<CT, H, W, ST>(buf, row, c, inv_h, ot);
 #pragma unroll
-    for (int t = 0; t < W; ++t) o[t] = (ST)inv_value<CT, N>(v, row, c + t, inv_h);
+      for (int t = 0; t < W; ++t) o[t] = ot[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < W; ++t) o[t] = (ST)inv_value<CT, N>(v, row, c + t, inv_h);
+    }
     *reinterpret_cast<V*>(io + (row0 + row) * ld + c) = o;
   }
 }
 
 // ---- pass 5: DCT-III along rows, z.r, z.q, sum z -------------------------
-template <class CT, class SI, class TO, int H>
+// The stored coefficients go to LDS by put_rows_inv, so that each pair's four
+// inputs sit in the two slots the pair overwrites: the pre-processing runs in
+// place with no barrier between its reads and writes.
+template <class CT, class SI, class TO, int H, bool FLEX>
 __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
     const SI* __restrict__ in, int64_t ld, TO* __restrict__ z, const TO* __restrict__ r,
     const TO* __restrict__ q, const void* twp, DevState st, int use_scale) {
@@ -446,27 +605,35 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
   __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
+  const int tid = threadIdx.x;
   CT* v = reinterpret_cast<CT*>(buf);
   // output scale: 1/h of the inverse FFT, undoing the input scale of the
   // first pass when the intermediates are FP16
   const CT inv_h = (CT)(1.0 / H) / (use_scale ? (CT)st.sc[SC_SCALE] : (CT)1);
   const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  {
+    RowChunks<SI, H> ch;
+    load_rows<SI, H>(in, ld, row0, ch, tid);
+    put_rows_inv<CT, SI, H>(ch, buf, tid);
+  }
+  __syncthreads();
 #pragma unroll
   for (int qq = 0; qq < PP; ++qq) {
-    const int p = threadIdx.x + qq * kThreads;
+    const int p = tid + qq * kThreads;
     if (p < ROWS * NP) {
       const int row = p / NP, k = p % NP;
-      const SI* x = in + (row0 + row) * ld;
-      const CT xk = (CT)x[k] * (k == 0 ? is0 : is1);
-      const CT xnk = k > 0 ? (CT)x[N - k] * is1 : (CT)0;
-      const CT xp = (CT)x[H - k] * is1;
-      const CT xnp = (CT)x[H + k] * is1;
+      const Cx<CT> A = buf[pc(row * H + k)];
+      const Cx<CT> B = buf[pc(row * H + ((H - k) & (H - 1)))];
+      const CT xk = A.x * (k == 0 ? is0 : is1);
+      const CT xnk = k > 0 ? A.y * is1 : (CT)0;
+      const CT xp = (k == 0 ? A.y : B.x) * is1;
+      const CT xnp = (k == 0 ? A.y : B.y) * is1;
       pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf, row * H);
     }
   }
   __syncthreads();
-  fft_rows<CT, H, ROWS>(buf, tw.fft);
+  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
   using V = typename Vec16<TO>::type;
   constexpr int W = Vec16<TO>::W;
   constexpr int NCH = ROWS * N / W / kThreads;
@@ -475,26 +642,33 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i0 = 0; i0 < NCH; i0 += BATCH) {
-    V rv[BATCH], qv[BATCH];
+    V rv[BATCH], qv[FLEX ? BATCH : 1];
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
-      const int e0 = (threadIdx.x + (i0 + b) * kThreads) * W;
+      const int e0 = (tid + (i0 + b) * kThreads) * W;
       const int64_t o = (row0 + e0 / N) * ld + e0 % N;
       rv[b] = *reinterpret_cast<const V*>(r + o);
-      if (q) qv[b] = *reinterpret_cast<const V*>(q + o);
+      if constexpr (FLEX) qv[b] = *reinterpret_cast<const V*>(q + o);
     }
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
-      const int e0 = (threadIdx.x + (i0 + b) * kThreads) * W;
+      const int e0 = (tid + (i0 + b) * kThreads) * W;
       const int row = e0 / N, c = e0 % N;
       V zv;
+      TO zo[W];
+      if constexpr (W >= 4) {
+        inv_chunk<CT, H, W, TO>(buf, row, c, inv_h, zo);
+      } else {
+#pragma unroll
+        for (int t = 0; t < W; ++t) zo[t] = (TO)inv_value<CT, N>(v, row, c + t, inv_h);
+      }
 #pragma unroll
       for (int t = 0; t < W; ++t) {
-        const TO zt = (TO)inv_value<CT, N>(v, row, c + t, inv_h);
+        const TO zt = zo[t];
         zv[t] = zt;
         const double zd = (double)zt;
         acc[0] += zd * (double)rv[b][t];
-        if (q) acc[1] += zd * (double)qv[b][t];
+        if constexpr (FLEX) acc[1] += zd * (double)qv[b][t];
         acc[2] += zd;
       }
       *reinterpret_cast<V*>(z + (row0 + row) * ld + c) = zv;
@@ -572,14 +746,32 @@ static void launch_transpose(const T* in, int64_t rows, int64_t cols, T* out,
 }
 
 // ---- tables -----------------------------------------------------------------
+// Thread j: stage-twiddle entry j (j < h - 1), post/pre twiddles j (j <= h),
+// eigenvalue j (j < n), all from FP64.
 template <class CT>
 __global__ __launch_bounds__(kThreads) void fct_tables_kernel(int64_t n, Cx<CT>* tw, double* eig) {
   const int64_t h = n / 2;
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   double s, c;
   if (j < h) {
-    sincospi(2.0 * (double)j / (double)h, &s, &c);
-    tw[j] = {(CT)c, (CT)(-s)};
+    // stage with span ns and radix R holds entries ns - 1 .. ns R - 2
+    int64_t ns = 1, rem = h, R = 1, num = 0;
+    while (rem > 1) {
+      R = rem >= 16 ? 16 : rem;
+      if (j < ns * R - 1) {
+        const int64_t rel = j - (ns - 1);
+        num = (rel / ns + 1) * (rel % ns);   // r k
+        break;
+      }
+      ns *= R;
+      rem /= R;
+    }
+    if (j < h - 1) {
+      sincospi(2.0 * (double)num / (double)(ns * R), &s, &c);
+      tw[j] = {(CT)c, (CT)(-s)};
+    } else {
+      tw[j] = {(CT)0, (CT)0};
+    }
   }
   if (j <= h) {
     sincospi(2.0 * (double)j / (double)n, &s, &c);
@@ -590,11 +782,12 @@ __global__ __launch_bounds__(kThreads) void fct_tables_kernel(int64_t n, Cx<CT>*
   if (j < n) {
     const double sv = sinpi(0.5 * (double)j / (double)n);
     eig[j] = 4.0 * sv * sv;
+    reinterpret_cast<CT*>(tw + 3 * h + 2)[j] = (CT)(4.0 * sv * sv);
   }
 }
 
 size_t fct_table_bytes(int64_t n, int elem) {
-  return (size_t)(3 * (n / 2) + 2) * 2 * (size_t)elem;
+  return (size_t)(3 * (n / 2) + 2) * 2 * (size_t)elem + (size_t)n * (size_t)elem;
 }
 
 void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s) {
@@ -656,8 +849,8 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   with_h(N / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
     hipLaunchKernelGGL((fct_cols_kernel<CT, ST, H>), dim3((unsigned)(M / rows_per_block<H>())),
-                       dim3(kThreads), 0, s, T2, N, a.twN, static_cast<const double*>(a.eigN),
-                       static_cast<const double*>(a.eigM), done);
+                       dim3(kThreads), 0, s, T2, N, a.twN, static_cast<const double*>(a.eigM),
+                       done);
   });
   log_mark(L, IRLSU_LK_COLS, s);
   launch_transpose<ST>(T2, M, N, T1, done, s);
@@ -666,8 +859,12 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
     nb = (int)(N / rows_per_block<H>());
-    hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H>), dim3((unsigned)nb), dim3(kThreads), 0,
-                       s, T1, M, z, r, q, a.twM, a.st, f16);
+    if (q)
+      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, true>), dim3((unsigned)nb),
+                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16);
+    else
+      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, false>), dim3((unsigned)nb),
+                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT3, s);
   hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, a.st, nb);

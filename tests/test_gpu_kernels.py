@@ -228,7 +228,7 @@ def test_precond_folded_is_pseudo_inverse_property_f64():
 
 # powers of two: the fast (cosine-transform) form; one and several rows per
 # block, square and both orientations of rectangles
-FAST_SHAPES = [(128, 128), (128, 512), (1024, 256), (256, 4096)]
+FAST_SHAPES = [(128, 128), (128, 512), (1024, 256), (256, 4096), (2048, 8192), (256, 16384)]
 # FP32 / FP64 plans: transform arithmetic and storage in the plan's type, a
 # few roundings per transform; mixed plans store the two intermediates in
 # BF16 / FP16 (FP32 arithmetic), the bound of the 16-bit products
