@@ -139,12 +139,13 @@ def test_preconditioner_against_oracle_full_size(prec):
 def test_fp64_first_iterates_match_oracle_reference(field, ref):
     """Two IRLS iterations at full size in FP64 (fast form) against the
     oracle's stored history.  Before any solve (k = 0: setup and weights)
-    the objectives agree to 1e-12.  After a solve the bar is 1e-4: each
-    solve stops at the 100-iteration cap with relative residual ~0.17, and
-    two FP64 CG runs that differ only in summation order (and the periodic
-    true-residual refresh) part at that level -- the oracle alone moves by
-    1e-4 under 1e-15 perturbations of its weights within a few capped IRLS
-    iterations.  A wrong operator, preconditioner or weight changes these
+    the objectives agree to 1e-12.  After a solve the bar is 5e-3: each
+    solve stops at the 100-iteration cap with relative residual ~0.17, where
+    the CG iterate is not determined to more digits by FP64 arithmetic --
+    the oracle run twice on this field, with 6 and with 8 FFT threads (only
+    the DCT's summation order differs), gives L1 at k = 1 that differ by
+    1.6e-3; a 1e-15 relative perturbation of its preconditioner moves it by
+    2.5e-5.  A wrong operator, preconditioner or weight changes these
     objectives at order one."""
     X, w = field
     plan = pkg.Plan(N, M, "f64")
@@ -154,7 +155,7 @@ def test_fp64_first_iterates_match_oracle_reference(field, ref):
                         torch.from_numpy(w.astype(np.float64)).cuda(), params=p, stats=True)
     plan.close()
     for k in range(3):
-        bar = 1e-12 if k == 0 else 1e-4
+        bar = 1e-12 if k == 0 else 5e-3
         a, b = st["history"][k]["L1"], ref["history"][k]["L1"]
         print(f"k={k}: GPU L1 {a:.10g} oracle {b:.10g} rel {abs(a - b) / b:.2e}")
         assert abs(a - b) <= bar * b, k
