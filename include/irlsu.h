@@ -282,6 +282,28 @@ irlsu_status irlsu_adjoint(irlsu_plan* plan, const void* gU, int64_t ldg,
                            void* workspace, size_t workspace_bytes,
                            irlsu_stats* stats, void* stream);
 
+/* Full implicit derivative of the Huber minimiser.  The same arguments as
+ * irlsu_adjoint, for the map (C, X) -> U* = argmin over mean-zero U of
+ * sum C h_eps(DU - G(X)) (the problem whose minimiser the IRLS fixed point
+ * is, Section 3 with the reduced weights), differentiated through its
+ * stationarity condition D^T (C h_eps'(DU* - G)) = 0: with r = DU* - G and
+ * the Hessian weights kappa = C / eps on the quadratic zone |r| < eps (0 off
+ * it), lambda solves D^T diag(kappa) D lambda = gU (projected), then
+ *   gC = -h_eps'(r) (D lambda),  gX = D^T (kappa D lambda),
+ * h_eps'(r) = r / eps on the zone, sign(r) off it.  Pixels with no
+ * quadratic-zone edge are left out (the minimiser is not unique there): gU
+ * is taken as zero on them and lambda = 0 there, with lambda of mean zero
+ * over the others.  The remaining pixels must be connected through
+ * quadratic-zone edges; otherwise the solve cannot converge and
+ * NOT_CONVERGED is returned.  The workspace's weight arrays are overwritten
+ * (by kappa). */
+irlsu_status irlsu_adjoint_implicit(irlsu_plan* plan, const void* gU, int64_t ldg,
+                                    const irlsu_params* params,
+                                    void* gCv, int64_t ldgcv, void* gCh, int64_t ldgch,
+                                    void* gX, int64_t ldgx,
+                                    void* workspace, size_t workspace_bytes,
+                                    irlsu_stats* stats, void* stream);
+
 /* ---- Step-level entry points (internal layout, see top of file) -------- */
 
 /* Setup (Section 2): Gv, Gh = wrapped differences W(d) = d - 2 pi

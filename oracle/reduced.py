@@ -317,6 +317,130 @@ def irls(X=None, *, G=None, w=None, Cv=None, Ch=None, eps=1e-3, iters=20,
 
 
 # ----------------------------------------------------------------------------
+# Full implicit derivative of the Huber minimiser (the map whose minimiser the
+# IRLS fixed point is): with r = DU* - G, the quadratic zone Q = {|r| < eps}
+# and Hessian weights kappa = C / eps on Q (0 off Q), the stationarity
+# condition D^T (C h_eps'(r)) = 0 differentiates to
+#   dL/dG = kappa (D lambda),  dL/dC = -h_eps'(r) (D lambda),
+#   dL/dX = D^T dL/dG,         D^T diag(kappa) D lambda = gU (projected).
+# ----------------------------------------------------------------------------
+def incidence(N, M):
+    """Sparse D (rows: the vertical edges then the horizontal ones, each in
+    row-major order of their (N-1) x M and N x (M-1) arrays) acting on the
+    row-major ravel of U: (D u)_e = u[end] - u[start]."""
+    import scipy.sparse as sp
+    idx = np.arange(N * M).reshape(N, M)
+    a = np.concatenate([idx[:-1, :].ravel(), idx[:, :-1].ravel()])
+    b = np.concatenate([idx[1:, :].ravel(), idx[:, 1:].ravel()])
+    ne = a.size
+    rows = np.concatenate([np.arange(ne), np.arange(ne)])
+    cols = np.concatenate([b, a])
+    vals = np.concatenate([np.ones(ne), -np.ones(ne)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(ne, N * M))
+
+
+def _components(N, M, q):
+    """Connected components of the pixel graph whose edges are those with q."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    idx = np.arange(N * M).reshape(N, M)
+    a = np.concatenate([idx[:-1, :].ravel(), idx[:, :-1].ravel()])[q]
+    b = np.concatenate([idx[1:, :].ravel(), idx[:, 1:].ravel()])[q]
+    G = sp.csr_matrix((np.ones(a.size), (a, b)), shape=(N * M, N * M))
+    return connected_components(G, directed=False)
+
+
+def _solve_mean_zero(H, rhs, keep):
+    """Solve H x = rhs on the pixels `keep` with sum(x[keep]) = 0 and
+    x = 0 elsewhere (sparse direct, bordered by the constraint)."""
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import spsolve
+    k = np.flatnonzero(keep)
+    Hk = H[k][:, k]
+    one = sp.csr_matrix(np.ones((k.size, 1)))
+    A = sp.bmat([[Hk, one], [one.T, None]]).tocsc()
+    sol = spsolve(A, np.concatenate([rhs[k], [0.0]]))
+    x = np.zeros(H.shape[0])
+    x[k] = sol[:-1]
+    return x
+
+
+def huber_minimiser(Gv, Gh, Cv, Ch, eps, U0, max_rounds=100):
+    """The exact mean-zero minimiser of sum C h_eps(DU - G), from a start U0
+    near it: with the quadratic zone Q of the current iterate fixed, the
+    stationarity condition is linear,
+        D^T diag(kappa) D U = D^T (kappa G - C s),
+        kappa = C / eps on Q (0 off it),  s = sign(r) off Q (0 on it),
+    and is solved directly; repeated until Q and the signs settle.  Raises
+    when they do not, or when the Q-graph does not connect every pixel (the
+    minimiser is then not unique).  Returns (U, qv, qh)."""
+    N, M = U0.shape
+    D = incidence(N, M)
+    g = np.concatenate([Gv.ravel(), Gh.ravel()])
+    c = np.concatenate([Cv.ravel(), Ch.ravel()])
+    u = (U0 - U0.mean()).ravel()
+    r = D @ u - g
+    q, s = np.abs(r) < eps, np.sign(r)
+    for _ in range(max_rounds):
+        if _components(N, M, q)[0] != 1:
+            raise ValueError("quadratic-zone graph does not connect every pixel")
+        kap = np.where(q, c / eps, 0.0)
+        sl = np.where(q, 0.0, s)
+        H = (D.T @ (D.multiply(kap[:, None]))).tocsr()
+        u = _solve_mean_zero(H, D.T @ (kap * g - c * sl), np.ones(N * M, bool))
+        r = D @ u - g
+        q2, s2 = np.abs(r) < eps, np.sign(r)
+        if np.array_equal(q2, q) and np.array_equal(np.where(q, 0.0, s2), sl):
+            ne = (N - 1) * M
+            return u.reshape(N, M), q[:ne].reshape(N - 1, M), q[ne:].reshape(N, M - 1)
+        q, s = q2, s2
+    raise ValueError("quadratic zone did not settle")
+
+
+def huber_stationarity(U, Gv, Gh, Cv, Ch, eps):
+    """max |D^T (C h_eps'(DU - G))|: zero at the Huber minimiser."""
+    rv, rh = residuals(U, Gv, Gh)
+    dv = np.where(np.abs(rv) <= eps, rv / eps, np.sign(rv))
+    dh = np.where(np.abs(rh) <= eps, rh / eps, np.sign(rh))
+    return float(np.abs(div(Cv * dv, Ch * dh)).max())
+
+
+def adjoint_implicit(U, Gv, Gh, Cv, Ch, eps, gU):
+    """Gradients of a loss with dL/dU = gU through the Huber minimiser U* =
+    U (full implicit derivative, no frozen weights).
+
+    Pixels with no quadratic-zone edge ("isolated": the minimiser is not
+    unique there) are left out: gU is taken as zero on them and lambda = 0
+    there; the remaining pixels must form one Q-component (else ValueError).
+    lambda solves D^T diag(kappa) D lambda = gU - mean(gU) over them."""
+    N, M = U.shape
+    rv, rh = residuals(U, Gv, Gh)
+    qv, qh = np.abs(rv) < eps, np.abs(rh) < eps
+    kv, kh = np.where(qv, Cv / eps, 0.0), np.where(qh, Ch / eps, 0.0)
+    deg = np.zeros((N, M), int)
+    deg[:-1, :] += qv
+    deg[1:, :] += qv
+    deg[:, :-1] += qh
+    deg[:, 1:] += qh
+    iso = deg == 0
+    ncomp, lab = _components(N, M, np.concatenate([qv.ravel(), qh.ravel()]))
+    if ncomp - int(iso.sum()) != 1:
+        raise ValueError("quadratic zone splits the image")
+    g = np.where(iso, 0.0, np.asarray(gU, np.float64))
+    g[~iso] -= g[~iso].mean()
+    D = incidence(N, M)
+    kap = np.concatenate([kv.ravel(), kh.ravel()])
+    H = (D.T @ (D.multiply(kap[:, None]))).tocsr()
+    lam = _solve_mean_zero(H, g.ravel(), ~iso.ravel()).reshape(N, M)
+    dv, dh = diff_v(lam), diff_h(lam)
+    hv = np.where(qv, rv / eps, np.sign(rv))
+    hh = np.where(qh, rh / eps, np.sign(rh))
+    gGv, gGh = kv * dv, kh * dh
+    return dict(lam=lam, gCv=-hv * dv, gCh=-hh * dh, gGv=gGv, gGh=gGh,
+                gX=div(gGv, gGh), isolated=iso, kv=kv, kh=kh)
+
+
+# ----------------------------------------------------------------------------
 # Rounded output (Section 4, "rounded IRLS"): the unwrapped U made
 # 2 pi-congruent to the input.  U is defined up to a constant; the constant c
 # aligning U with X modulo 2 pi is the circular mean of X - U.

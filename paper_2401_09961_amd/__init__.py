@@ -30,7 +30,7 @@ IRLSU_MAX_IRLS = 256
 DECLARED_SYMBOLS = (
     "irlsu_status_string", "irlsu_params_default", "irlsu_plan_create",
     "irlsu_plan_create_ex", "irlsu_plan_destroy", "irlsu_plan_info", "irlsu_workspace_bytes",
-    "irlsu_unwrap", "irlsu_adjoint", "irlsu_setup", "irlsu_weights",
+    "irlsu_unwrap", "irlsu_adjoint", "irlsu_adjoint_implicit", "irlsu_setup", "irlsu_weights",
     "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_profile_arm",
     "irlsu_profile_result", "irlsu_round_congruent", "irlsu_augmented_workspace_bytes",
     "irlsu_unwrap_augmented", "irlsu_batch_create", "irlsu_batch_destroy",
@@ -149,6 +149,8 @@ def load_library():
                                P, I64, P, SZ, ctypes.POINTER(Stats), P]),
         "irlsu_adjoint": (I32, [P, P, I64, ctypes.POINTER(Params), P, I64, P, I64, P, I64,
                                 P, SZ, ctypes.POINTER(Stats), P]),
+        "irlsu_adjoint_implicit": (I32, [P, P, I64, ctypes.POINTER(Params), P, I64, P, I64, P,
+                                         I64, P, SZ, ctypes.POINTER(Stats), P]),
         "irlsu_setup": (I32, [P, P, I64, P, P, I64, P, I64, P, P, P, P, P, P]),
         "irlsu_batch_create": (I32, [ctypes.POINTER(P), ctypes.POINTER(I64), I32, I32, P]),
         "irlsu_batch_destroy": (I32, [P]),
@@ -279,9 +281,12 @@ class Plan:
             return U, d
         return U
 
-    def adjoint(self, gU, *, params: Optional[Params] = None, workspace=None, stats: bool = False):
+    def adjoint(self, gU, *, params: Optional[Params] = None, workspace=None, stats: bool = False,
+                implicit: bool = False):
         """Gradients (gCv, gCh, gX) of a loss with dL/dU = gU through the
-        frozen-weight map at the U of the last unwrap that used `workspace`."""
+        frozen-weight map at the U of the last unwrap that used `workspace`
+        (implicit=True: through the Huber minimiser itself, the full implicit
+        derivative)."""
         import torch
         ws = self.workspace if workspace is None else workspace
         g = _mat(gU, self.dtype)
@@ -289,7 +294,8 @@ class Plan:
         gCh = torch.empty((self.N, self.M - 1), dtype=self.dtype, device=self.device)
         gX = torch.empty((self.N, self.M), dtype=self.dtype, device=self.device)
         st = Stats() if stats else None
-        code = self.lib.irlsu_adjoint(
+        fn = self.lib.irlsu_adjoint_implicit if implicit else self.lib.irlsu_adjoint
+        code = fn(
             self.handle, _ptr(g), g.stride(0), ctypes.byref(params) if params is not None else None,
             _ptr(gCv), gCv.stride(0), _ptr(gCh), gCh.stride(0), _ptr(gX), gX.stride(0),
             _ptr(ws), ws.numel(), ctypes.byref(st) if st is not None else None, _stream())
@@ -505,22 +511,25 @@ def _autograd_function():
 
         forward runs the IRLS + PCG path on a workspace of its own; backward
         runs one extra PCG solve on the converged system with the weights
-        frozen (irlsu_adjoint) and returns gradients for X and the per-edge
-        weights Cv, Ch.
+        frozen (irlsu_adjoint), or through the Huber minimiser itself when
+        implicit is true (irlsu_adjoint_implicit), and returns gradients for
+        X and the per-edge weights Cv, Ch.
         """
 
         @staticmethod
-        def forward(ctx, X, Cv, Ch, plan, params=None, adj_params=None):
+        def forward(ctx, X, Cv, Ch, plan, params=None, adj_params=None, implicit=False):
             ws = plan.new_workspace()
             U = plan.unwrap(X, Cv=Cv, Ch=Ch, params=params, workspace=ws)
             ctx.plan, ctx.ws, ctx.adj_params = plan, ws, adj_params if adj_params is not None else params
+            ctx.implicit = bool(implicit)
             return U
 
         @staticmethod
         def backward(ctx, gU):
-            gCv, gCh, gX = ctx.plan.adjoint(gU.contiguous(), params=ctx.adj_params, workspace=ctx.ws)
+            gCv, gCh, gX = ctx.plan.adjoint(gU.contiguous(), params=ctx.adj_params, workspace=ctx.ws,
+                                            implicit=ctx.implicit)
             ctx.ws = None
-            return gX, gCv, gCh, None, None, None
+            return gX, gCv, gCh, None, None, None, None
 
     return UnwrapFn
 

@@ -479,14 +479,77 @@ irlsu_status unwrap_impl(irlsu_plan* pl, const T* X, int64_t ldx, const T* w, co
 
 // Adjoint solve on the state an irlsu_unwrap call left in the workspace:
 // frozen weights at the final U, one PCG solve, edge gradients.
+// Full implicit derivative of the Huber minimiser (the Hessian weights kappa
+// replace Omega in the workspace; see adjoint.hip).
+template <class T>
+irlsu_status adjoint_implicit_impl(irlsu_plan* pl, const Ws<T>& W, const T* gU, int64_t ldg,
+                                   const irlsu_params& prm, T* gCv, int64_t ldgcv, T* gCh,
+                                   int64_t ldgch, T* gX, int64_t ldgx, irlsu_stats* stats,
+                                   hipStream_t s) {
+  const int64_t N = pl->N, M = pl->M, Np = pl->Np, ld = pl->Mp;
+  const size_t npx = (size_t)Np * (size_t)ld;
+  DevState st = W.st;
+  T* Kv = W.v[V_OV];
+  T* Kh = W.v[V_OH];
+  launch_adjoint_hessian<T>(W.U, W.v[V_GV], W.v[V_GH], W.v[V_CV], W.v[V_CH], prm.eps, N, M, Np,
+                            ld, Kv, Kh, s);
+  launch_adjoint_rhs_implicit<T>(gU, ldg, N, M, Np, ld, Kv, Kh, W.v[V_B], st,
+                                 prm.pcg_rtol * prm.pcg_rtol, s);
+  HIP_OK(hipMemsetAsync(W.lam, 0, npx * sizeof(double), s));
+  const int flexible = prm.flexible < 0 ? default_flexible(pl) : prm.flexible;
+  int iters = 0;
+  double relres = 0.0;
+  irlsu_status solve_st = IRLSU_OK;
+  irlsu_status rs = pcg_solve<T>(pl, W, W.lam, W.v[V_B], prm, flexible, &iters, &relres,
+                                 &solve_st, s);
+  if (rs != IRLSU_OK) return rs;
+  if (solve_st == IRLSU_ERR_BREAKDOWN) return solve_st;
+  launch_adjoint_lam_mean<T>(W.lam, N, M, ld, Kv, Kh, st, s);
+  AdjEdgeArgs<T> ea;
+  ea.U = W.U;
+  ea.lam = W.lam;
+  ea.Gv = W.v[V_GV];
+  ea.Gh = W.v[V_GH];
+  ea.Cv = W.v[V_CV];
+  ea.Ch = W.v[V_CH];
+  ea.eps = prm.eps;
+  ea.N = N;
+  ea.M = M;
+  ea.ld = ld;
+  ea.gCv = gCv;
+  ea.ldgcv = ldgcv;
+  ea.gCh = gCh;
+  ea.ldgch = ldgch;
+  ea.gX = gX;
+  ea.ldgx = ldgx;
+  ea.Kv = Kv;
+  ea.Kh = Kh;
+  ea.lam_mean = st.sc + SC_MEAN;
+  launch_adjoint_edges<T>(ea, s);
+  if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->pcg_total = iters;
+    stats->status = solve_st;
+    stats->iter[0].pcg_iters = iters;
+    stats->iter[0].relres = relres;
+    stats->iter[0].status = solve_st;
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  return solve_st;
+}
+
 template <class T>
 irlsu_status adjoint_impl(irlsu_plan* pl, const T* gU, int64_t ldg, const irlsu_params& prm,
                           T* gCv, int64_t ldgcv, T* gCh, int64_t ldgch, T* gX, int64_t ldgx,
-                          void* ws, irlsu_stats* stats, hipStream_t s) {
+                          void* ws, irlsu_stats* stats, hipStream_t s, bool implicit) {
   const Ws<T> W = carve<T>(pl, ws);
   const int64_t N = pl->N, M = pl->M, Np = pl->Np, ld = pl->Mp;
   const size_t npx = (size_t)Np * (size_t)ld;
   DevState st = W.st;
+  if (implicit)
+    return adjoint_implicit_impl<T>(pl, W, gU, ldg, prm, gCv, ldgcv, gCh, ldgch, gX, ldgx, stats,
+                                    s);
   WeightsArgs<T> wa;
   wa.U = W.U;
   wa.Gv = W.v[V_GV];
@@ -1228,10 +1291,11 @@ irlsu_status irlsu_unwrap(irlsu_plan* plan, const void* X, int64_t ldx, const vo
                             prm, static_cast<float*>(U), ldu, workspace, stats, s);
 }
 
-irlsu_status irlsu_adjoint(irlsu_plan* plan, const void* gU, int64_t ldg,
-                           const irlsu_params* params, void* gCv, int64_t ldgcv, void* gCh,
-                           int64_t ldgch, void* gX, int64_t ldgx, void* workspace,
-                           size_t workspace_bytes, irlsu_stats* stats, void* stream) {
+static irlsu_status adjoint_entry(irlsu_plan* plan, const void* gU, int64_t ldg,
+                                  const irlsu_params* params, void* gCv, int64_t ldgcv, void* gCh,
+                                  int64_t ldgch, void* gX, int64_t ldgx, void* workspace,
+                                  size_t workspace_bytes, irlsu_stats* stats, void* stream,
+                                  bool implicit) {
   if (!plan || !gU || !gCv || !gCh) return IRLSU_ERR_INVALID_ARG;
   if (ldg < plan->M || ldgcv < plan->M || ldgch < plan->M - 1) return IRLSU_ERR_INVALID_ARG;
   if (gX && ldgx < plan->M) return IRLSU_ERR_INVALID_ARG;
@@ -1246,10 +1310,27 @@ irlsu_status irlsu_adjoint(irlsu_plan* plan, const void* gU, int64_t ldg,
   if (plan->elem == 8)
     return adjoint_impl<double>(plan, static_cast<const double*>(gU), ldg, prm,
                                 static_cast<double*>(gCv), ldgcv, static_cast<double*>(gCh), ldgch,
-                                static_cast<double*>(gX), ldgx, workspace, stats, s);
+                                static_cast<double*>(gX), ldgx, workspace, stats, s, implicit);
   return adjoint_impl<float>(plan, static_cast<const float*>(gU), ldg, prm,
                              static_cast<float*>(gCv), ldgcv, static_cast<float*>(gCh), ldgch,
-                             static_cast<float*>(gX), ldgx, workspace, stats, s);
+                             static_cast<float*>(gX), ldgx, workspace, stats, s, implicit);
+}
+
+irlsu_status irlsu_adjoint(irlsu_plan* plan, const void* gU, int64_t ldg,
+                           const irlsu_params* params, void* gCv, int64_t ldgcv, void* gCh,
+                           int64_t ldgch, void* gX, int64_t ldgx, void* workspace,
+                           size_t workspace_bytes, irlsu_stats* stats, void* stream) {
+  return adjoint_entry(plan, gU, ldg, params, gCv, ldgcv, gCh, ldgch, gX, ldgx, workspace,
+                       workspace_bytes, stats, stream, false);
+}
+
+irlsu_status irlsu_adjoint_implicit(irlsu_plan* plan, const void* gU, int64_t ldg,
+                                    const irlsu_params* params, void* gCv, int64_t ldgcv,
+                                    void* gCh, int64_t ldgch, void* gX, int64_t ldgx,
+                                    void* workspace, size_t workspace_bytes, irlsu_stats* stats,
+                                    void* stream) {
+  return adjoint_entry(plan, gU, ldg, params, gCv, ldgcv, gCh, ldgch, gX, ldgx, workspace,
+                       workspace_bytes, stats, stream, true);
 }
 
 irlsu_status irlsu_setup(const irlsu_plan* plan, const void* X, int64_t ldx, const void* w,

@@ -169,11 +169,30 @@ struct AdjEdgeArgs {
   T* gCv; int64_t ldgcv;    // (N-1) x M, caller layout
   T* gCh; int64_t ldgch;    // N x (M-1)
   T* gX; int64_t ldgx;      // N x M, nullable
+  // full implicit derivative of the Huber minimiser: the Hessian weights
+  // (kappa, internal layout; pixels with no kappa > 0 edge are left out) and
+  // the mean of lambda over the other pixels (device scalar)
+  const T* Kv = nullptr; const T* Kh = nullptr;
+  const double* lam_mean = nullptr;
 };
 template <class T>
 void launch_adjoint_rhs(const T* g, int64_t ldg, int64_t N, int64_t M, int64_t Np, int64_t ld,
                         T* b, DevState st, double tol2, hipStream_t s);
 template <class T> void launch_adjoint_edges(const AdjEdgeArgs<T>& a, hipStream_t s);
+// kappa = C / eps where |DU - G| < eps, else 0, into Kv, Kh (internal layout)
+template <class T>
+void launch_adjoint_hessian(const double* U, const T* Gv, const T* Gh, const T* Cv, const T* Ch,
+                            double eps, int64_t N, int64_t M, int64_t Np, int64_t ld, T* Kv, T* Kh,
+                            hipStream_t s);
+// b = gU - mean(gU) over the pixels with a kappa > 0 edge, 0 on the others
+template <class T>
+void launch_adjoint_rhs_implicit(const T* g, int64_t ldg, int64_t N, int64_t M, int64_t Np,
+                                 int64_t ld, const T* Kv, const T* Kh, T* b, DevState st,
+                                 double tol2, hipStream_t s);
+// mean of lambda over the pixels with a kappa > 0 edge into sc[SC_MEAN]
+template <class T>
+void launch_adjoint_lam_mean(const double* lam, int64_t N, int64_t M, int64_t ld, const T* Kv,
+                             const T* Kh, DevState st, hipStream_t s);
 
 // ---- DCT preconditioner (dense cosine-basis products on MFMA) ----------
 enum OperandKind : int { OK_F64 = 0, OK_F32 = 1, OK_BF16 = 2, OK_F16 = 3 };

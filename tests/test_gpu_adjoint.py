@@ -119,3 +119,119 @@ def test_autograd_function_mse_loss():
     assert rel(logits_v.grad.cpu().numpy(), ref["gCv"] * sv) <= 1e-7
     assert rel(Xt.grad.cpu().numpy(), ref["gX"]) <= 1e-7
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Full implicit derivative of the Huber minimiser (irlsu_adjoint_implicit)
+# ---------------------------------------------------------------------------
+def at_u(prec, X, Cv, Ch, U0, eps):
+    """A plan whose workspace holds U = U0 (warm start, no IRLS iteration),
+    so the adjoint is taken at a given point."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    N, M = X.shape
+    plan = pkg.Plan(N, M, prec)
+    p = pkg.default_params(prec)
+    p.irls_iters, p.eps, p.pcg_max = 0, eps, 5000
+    p.pcg_rtol = 1e-12 if prec == "f64" else 1e-6
+    U = plan.unwrap(torch.from_numpy(X).to("cuda", dt), Cv=torch.from_numpy(Cv).to("cuda", dt),
+                    Ch=torch.from_numpy(Ch).to("cuda", dt),
+                    U0=torch.from_numpy(U0).to("cuda", dt), params=p)
+    torch.cuda.synchronize()
+    return plan, p, U
+
+
+@pytest.mark.parametrize("seed", [3, 5])
+def test_implicit_adjoint_matches_oracle_at_the_huber_minimiser(seed):
+    """At the exact Huber minimiser (oracle), FP64: gC and gX against the
+    oracle's implicit adjoint (sparse direct solve) to 1e-9; the solve runs
+    to 1e-12 and the Hessian weights are C / eps on the same edges."""
+    from test_oracle_pins import _huber_case
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(seed)
+    N, M = X.shape
+    plan, p, Ug = at_u("f64", X, Cv, Ch, U, eps)
+    assert np.abs(Ug.cpu().numpy() - U).max() < 1e-12
+    gU = np.random.default_rng(8 + seed).standard_normal((N, M))
+    gCv, gCh, gX, st = plan.adjoint(torch.from_numpy(gU).cuda(), params=p, stats=True,
+                                    implicit=True)
+    torch.cuda.synchronize()
+    ref = R.adjoint_implicit(U, Gv, Gh, Cv, Ch, eps, gU)
+    e = [rel(gCv.cpu().numpy(), ref["gCv"]), rel(gCh.cpu().numpy(), ref["gCh"]),
+         rel(gX.cpu().numpy(), ref["gX"])]
+    print(f"implicit adjoint seed {seed}: rel err {e[0]:.2e} {e[1]:.2e} {e[2]:.2e}, "
+          f"pcg {st['pcg_total']}")
+    assert st["code"] == 0 and max(e) <= 1e-9
+    # not the frozen-weight derivative
+    frozen = R.adjoint(U, Gv, Gh, Cv, Ch, eps, gU, tol=1e-13, maxit=20000)
+    assert rel(frozen["gCv"], ref["gCv"]) > 1e-2
+    plan.close()
+
+
+def test_implicit_adjoint_leaves_out_isolated_pixels():
+    """A point where one pixel has no quadratic-zone edge: that pixel gets
+    lambda = 0 and no share of gU, on the GPU as in the oracle."""
+    from test_oracle_pins import _huber_case
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(3)
+    N, M = X.shape
+    U2 = U.copy()
+    U2[10, 9] += 0.5
+    U2 -= U2.mean()
+    plan, p, _ = at_u("f64", X, Cv, Ch, U2, eps)
+    gU = 1.0 + np.arange(N * M, dtype=np.float64).reshape(N, M) / (N * M)
+    gCv, gCh, gX = plan.adjoint(torch.from_numpy(gU).cuda(), params=p, implicit=True)
+    ref = R.adjoint_implicit(U2, Gv, Gh, Cv, Ch, eps, gU)
+    assert ref["isolated"].sum() == 1
+    for a, b in ((gCv, ref["gCv"]), (gCh, ref["gCh"]), (gX, ref["gX"])):
+        assert rel(a.cpu().numpy(), b) <= 1e-9
+    plan.close()
+
+
+def test_implicit_adjoint_after_gpu_forward_f32():
+    """End to end in FP32: the GPU's IRLS to convergence (eps = 1e-2), then
+    the implicit adjoint at its U, against the oracle's at the same (FP32
+    rounded) U and inputs; 2e-3 in the norm (FP32 vectors, solve to 1e-6)."""
+    from test_oracle_pins import _huber_case
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(5)
+    N, M = X.shape
+    X32, Cv32, Ch32 = X.astype(np.float32), Cv.astype(np.float32), Ch.astype(np.float32)
+    plan = pkg.Plan(N, M, "f32")
+    p = pkg.default_params("f32")
+    p.irls_iters, p.eps, p.pcg_max = 200, eps, 3000
+    Ug = plan.unwrap(torch.from_numpy(X32).cuda(), Cv=torch.from_numpy(Cv32).cuda(),
+                     Ch=torch.from_numpy(Ch32).cuda(), params=p)
+    gU = np.random.default_rng(12).standard_normal((N, M)).astype(np.float32)
+    gCv, gCh, gX = plan.adjoint(torch.from_numpy(gU).cuda(), params=p, implicit=True)
+    torch.cuda.synchronize()
+    Uo = Ug.cpu().numpy().astype(np.float64)
+    Gv32, Gh32 = (g.astype(np.float32).astype(np.float64)
+                  for g in R.wrapped_gradients(X32.astype(np.float64)))
+    ref = R.adjoint_implicit(Uo, Gv32, Gh32, Cv32.astype(np.float64), Ch32.astype(np.float64),
+                             eps, gU.astype(np.float64))
+    e = [rel(gCv.cpu().numpy().astype(np.float64), ref["gCv"]),
+         rel(gCh.cpu().numpy().astype(np.float64), ref["gCh"]),
+         rel(gX.cpu().numpy().astype(np.float64), ref["gX"])]
+    print(f"implicit adjoint f32 after forward: rel err {e[0]:.2e} {e[1]:.2e} {e[2]:.2e}")
+    assert max(e) <= 2e-3
+    plan.close()
+
+
+def test_autograd_function_implicit_backward():
+    """UnwrapFn(..., implicit=True): torch.autograd gradients equal the
+    implicit adjoint of the same loss at the GPU's U (oracle)."""
+    from test_oracle_pins import _huber_case
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(3)
+    N, M = X.shape
+    plan = pkg.Plan(N, M, "f64")
+    p = pkg.default_params("f64")
+    p.irls_iters, p.eps, p.pcg_max, p.pcg_rtol = 200, eps, 3000, 1e-12
+    Xt = torch.from_numpy(X).cuda().requires_grad_(True)
+    Cvt = torch.from_numpy(Cv).cuda().requires_grad_(True)
+    Cht = torch.from_numpy(Ch).cuda().requires_grad_(True)
+    Ut = pkg.UnwrapFn.apply(Xt, Cvt, Cht, plan, p, None, True)
+    w = torch.from_numpy(np.random.default_rng(2).standard_normal((N, M))).cuda()
+    (Ut * w).sum().backward()
+    Ug = Ut.detach().cpu().numpy()
+    ref = R.adjoint_implicit(Ug, Gv, Gh, Cv, Ch, eps, w.cpu().numpy())
+    assert rel(Cvt.grad.cpu().numpy(), ref["gCv"]) <= 1e-8
+    assert rel(Cht.grad.cpu().numpy(), ref["gCh"]) <= 1e-8
+    assert rel(Xt.grad.cpu().numpy(), ref["gX"]) <= 1e-8
+    plan.close()

@@ -637,6 +637,107 @@ def dense_frozen_solve(Cv, Ch, Gv, Gh, wv, wh):
     return x.reshape((N, M), order="F")
 
 
+# ---------------------------------------------------------------------------
+# Full implicit derivative of the Huber minimiser
+# ---------------------------------------------------------------------------
+def _huber_case(seed, N=20, M=18, eps=1e-2):
+    """A residue field whose quadratic-zone graph connects every pixel (seeds
+    3 and 5 at this size), its weights and its exact Huber minimiser."""
+    rng = np.random.default_rng(seed)
+    X = synth.observe(synth.gaussian_sum_field(rng, N, M, amp=3.0, noise=1.2))
+    Gv, Gh = R.wrapped_gradients(X)
+    rng2 = np.random.default_rng(100 + seed)
+    Cv, Ch = rng2.uniform(0.5, 1.5, (N - 1, M)), rng2.uniform(0.5, 1.5, (N, M - 1))
+    U0, _ = R.irls(G=(Gv, Gh), Cv=Cv, Ch=Ch, eps=eps, iters=200, tol=1e-13, maxit=2000)
+    U, qv, qh = R.huber_minimiser(Gv, Gh, Cv, Ch, eps, U0)
+    return X, Gv, Gh, Cv, Ch, eps, U, qv, qh
+
+
+def test_huber_minimiser_is_stationary_and_irls_converges_to_it():
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(3)
+    assert R.huber_stationarity(U, Gv, Gh, Cv, Ch, eps) < 1e-10
+    assert 0.5 < qv.mean() < 1.0 and 0.5 < qh.mean() < 1.0    # both zones occur
+    U0, _ = R.irls(G=(Gv, Gh), Cv=Cv, Ch=Ch, eps=eps, iters=200, tol=1e-13, maxit=2000)
+    assert np.abs(U0 - U).max() < 1e-8
+
+
+@pytest.mark.parametrize("seed", [3, 5])
+def test_implicit_adjoint_matches_finite_differences_of_the_minimiser(seed):
+    """dL/dC and dL/dX of L = gU . U*(C, X) by central differences of the
+    exact minimiser (re-solved for each perturbed problem, same quadratic
+    zone) against the implicit adjoint."""
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(seed)
+    N, M = X.shape
+    rng = np.random.default_rng(7 + seed)
+    gU = rng.standard_normal((N, M))
+    adj = R.adjoint_implicit(U, Gv, Gh, Cv, Ch, eps, gU)
+    assert not adj["isolated"].any()
+    h = 1e-6
+    scale = max(np.abs(adj["gCv"]).max(), np.abs(adj["gCh"]).max())
+    for _ in range(10):
+        vert = rng.random() < 0.5
+        shp = (N - 1, M) if vert else (N, M - 1)
+        e = (rng.integers(shp[0]), rng.integers(shp[1]))
+        L = []
+        for sgn in (1, -1):
+            Cv2, Ch2 = Cv.copy(), Ch.copy()
+            (Cv2 if vert else Ch2)[e] += sgn * h
+            U2, qv2, qh2 = R.huber_minimiser(Gv, Gh, Cv2, Ch2, eps, U)
+            assert np.array_equal(qv2, qv) and np.array_equal(qh2, qh)
+            L.append(float(np.sum(gU * U2)))
+        fd = (L[0] - L[1]) / (2 * h)
+        got = (adj["gCv"] if vert else adj["gCh"])[e]
+        assert abs(fd - got) <= 1e-6 * scale, (vert, e, fd, got)
+    scale = np.abs(adj["gX"]).max()
+    checked = 0
+    while checked < 8:
+        i, j = rng.integers(N), rng.integers(M)
+        d = np.concatenate([np.diff(X, axis=0)[max(i - 1, 0):i + 1, j],
+                            np.diff(X, axis=1)[i, max(j - 1, 0):j + 1]])
+        if np.any(np.abs(np.abs(d) - np.pi) < 1e-3):
+            continue
+        L = []
+        for sgn in (1, -1):
+            X2 = X.copy()
+            X2[i, j] += sgn * h
+            Gv2, Gh2 = R.wrapped_gradients(X2)
+            U2, _, _ = R.huber_minimiser(Gv2, Gh2, Cv, Ch, eps, U)
+            L.append(float(np.sum(gU * U2)))
+        fd = (L[0] - L[1]) / (2 * h)
+        assert abs(fd - adj["gX"][i, j]) <= 1e-6 * scale, (i, j, fd, adj["gX"][i, j])
+        checked += 1
+
+
+def test_implicit_adjoint_itoh_case_is_the_mean_removal():
+    """No residues: every edge is quadratic and U* integrates G, so
+    dL/dX = gU - mean(gU) whatever C, and dL/dC = 0 (h'(0) = 0)."""
+    f = synth.smooth_field(2, 24, 20)
+    Gv, Gh = R.wrapped_gradients(f.X)
+    rng = np.random.default_rng(4)
+    Cv, Ch = rng.uniform(0.5, 1.5, Gv.shape), rng.uniform(0.5, 1.5, Gh.shape)
+    U0, _ = R.irls(G=(Gv, Gh), Cv=Cv, Ch=Ch, eps=1e-3, iters=3, tol=1e-13, maxit=2000)
+    U, qv, qh = R.huber_minimiser(Gv, Gh, Cv, Ch, 1e-3, U0)
+    assert qv.all() and qh.all()
+    gU = rng.standard_normal(U.shape)
+    adj = R.adjoint_implicit(U, Gv, Gh, Cv, Ch, 1e-3, gU)
+    assert np.abs(adj["gX"] - (gU - gU.mean())).max() < 1e-9
+    assert max(np.abs(adj["gCv"]).max(), np.abs(adj["gCh"]).max()) < 1e-9
+
+
+def test_implicit_adjoint_leaves_out_isolated_pixels():
+    """A pixel whose four edges all lie outside the quadratic zone (its
+    minimiser value is not unique) gets lambda = 0 and no share of gU; the
+    gradients are then those of the problem with gU zero there."""
+    X, Gv, Gh, Cv, Ch, eps, U, qv, qh = _huber_case(3)
+    N, M = X.shape
+    U2 = U.copy()
+    U2[10, 9] += 0.5                      # its four residuals leave the zone
+    adj = R.adjoint_implicit(U2, Gv, Gh, Cv, Ch, eps, np.ones((N, M)) + np.arange(N * M).reshape(N, M))
+    assert adj["isolated"][10, 9] and adj["isolated"].sum() == 1
+    assert adj["lam"][10, 9] == 0.0
+    assert abs(adj["lam"][~adj["isolated"]].sum()) < 1e-9
+
+
 def test_adjoint_matches_finite_differences():
     # residue-bearing moderate-amplitude phase with the sigmoid edge weights
     # of the differentiation case, so that r = DU - G is not identically zero
