@@ -297,9 +297,10 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     xa.q = W.v[V_Q];
     xa.n = (int64_t)npx;
     xa.nparts_pq = npq;
+    xa.nparts_out = nvec;
     xa.iter = l;
     xa.st = st;
-    launch_axpy<T>(xa, s, nvec);
+    launch_axpy<T>(xa, s, axpy_blocks(nvec));
     log_mark(L, IRLSU_LK_AXPY, s);
     if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max) {
       ra.check_done = 1;

@@ -36,6 +36,8 @@ struct AxpyArgs {
                       // type); u is then left alone until the solve ends
   int64_t n;          // Np * ld, a multiple of 4
   int nparts_pq;      // number of p.q partials written by the stencil
+  int nparts_out = 0; // partials the consumers of ||r||^2 and sum r read (the
+                      // stencil's count); slots beyond the grid are zeroed
   int iter;
   DevState st;
 };
@@ -105,6 +107,7 @@ template <class T> int launch_weights(const WeightsArgs<T>& a, hipStream_t s);
 void launch_finalize_weights(DevState st, int nparts, double* out, double tol2, hipStream_t s,
                              int want_model = 0);
 template <class T> int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks);
+int axpy_blocks(int stencil_blocks);
 // out = X + 2 pi rint((U + c - X) / 2 pi), c = arg sum exp(i (X - U))
 template <class T>
 void launch_congruent(const T* X, int64_t ldx, const T* U, int64_t ldu, T* out, int64_t ldo,

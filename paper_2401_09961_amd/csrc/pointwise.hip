@@ -238,6 +238,14 @@ __device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) 
   }
   const int slots[2] = {PR_RR, PR_RSUM};
   write_partials<2>(a.st, slots, acc, lb);
+  // a grid smaller than the residual stencil's leaves the rest of its
+  // partial range at zero, so every consumer reads one count
+  if (threadIdx.x == 0) {
+    for (int k = lb + nb; k < a.nparts_out; k += nb) {
+      a.st.part[(size_t)PR_RR * kMaxPartials + a.st.off + k] = 0.0;
+      a.st.part[(size_t)PR_RSUM * kMaxPartials + a.st.off + k] = 0.0;
+    }
+  }
 }
 
 template <class T>
@@ -462,6 +470,13 @@ template <class T>
 int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks) {
   hipLaunchKernelGGL((axpy_kernel<T>), dim3(nblocks), dim3(kThreads), 0, s, a);
   return nblocks;
+}
+
+// Blocks of the CG update: two per compute unit of the 256, each streaming
+// its share with two 16-byte chunks per array in flight per thread (more
+// blocks measured slower at 8192^2), never more than the stencil's.
+int axpy_blocks(int stencil_blocks) {
+  return stencil_blocks < 512 ? stencil_blocks : 512;
 }
 
 void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s) {

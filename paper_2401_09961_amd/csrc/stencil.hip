@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void stencil_batched_kernel(const BatchTi
 dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out) {
   const int64_t bx = (ld + 4 * kThreads - 1) / (4 * kThreads);
   int64_t rows = 64;
-  while (rows > 4 && bx * ((Np + rows - 1) / rows) < 2048) rows /= 2;
+  while (rows > 4 && bx * ((Np + rows - 1) / rows) < 1024) rows /= 2;
   while (bx * ((Np + rows - 1) / rows) > kMaxPartials) rows *= 2;
   *rows_out = (int)rows;
   return dim3((unsigned)bx, (unsigned)((Np + rows - 1) / rows));
