@@ -472,11 +472,12 @@ int launch_axpy(const AxpyArgs<T>& a, hipStream_t s, int nblocks) {
   return nblocks;
 }
 
-// Blocks of the CG update: two per compute unit of the 256, each streaming
-// its share with two 16-byte chunks per array in flight per thread (more
-// blocks measured slower at 8192^2), never more than the stencil's.
+// Blocks of the CG update: one per compute unit of the 256, each streaming
+// its share with two 16-byte chunks per array in flight per thread (512,
+// 1024 and 2048 blocks measured slower at 8192^2), never more than the
+// stencil's.
 int axpy_blocks(int stencil_blocks) {
-  return stencil_blocks < 512 ? stencil_blocks : 512;
+  return stencil_blocks < 256 ? stencil_blocks : 256;
 }
 
 void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s) {
