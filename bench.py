@@ -445,8 +445,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     a.warmup = max(1, a.warmup)
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         return 2
 
     import torch
