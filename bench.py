@@ -152,14 +152,19 @@ def kernel_table(launches, prec, form, N, M, flexible):
     e = 8 if prec == "f64" else 4
     s = 2 if (form == "fast" and prec in ("bf16", "f16")) else e
     px = N * M
+    # fast form with plain beta: the last preconditioner pass writes the new
+    # direction p (rho from the column pass's spectral sum), the stencil
+    # applies the operator only
+    spectral = form == "fast" and not flexible
     bpp = {  # kind -> (kernel, bytes per pixel)
-        "stencil": ("stencil_kernel", 6 * e),              # z, p_old, Ov, Oh in; p, q out
+        "stencil": ("stencil_kernel", 4 * e if spectral else 6 * e),  # (z,) p, Ov, Oh in; (p,) q out
         "axpy": ("axpy_kernel", 6 * e),                    # p, q, r, d in; r, d out
         "residual": ("stencil_kernel(residual)", 8 + 5 * e),  # u, d, b, Ov, Oh in; r out
         "rows_dct2": ("fct_rows_fwd_kernel", e + s),        # r in; T1 out
         "transpose": ("transpose_kernel", 2 * s),
         "cols": ("fct_cols_kernel", 2 * s),
-        "rows_dct3": ("fct_rows_inv_kernel", s + (3 if flexible else 2) * e),  # T, r, (q) in; z out
+        # T, r, (q) in; z out -- spectral: T, p_old in; p out
+        "rows_dct3": ("fct_rows_inv_kernel", s + (3 if flexible else 2) * e),
     }
     n_prod = sum(1 for k, _ in launches if k == "product")
     out = {}

@@ -522,12 +522,12 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
 
 // ---- pass 3: DCT-II, spectral division, DCT-III along rows of the
 // transposed intermediate (the columns of the image) ----------------------
-template <class CT, class ST, int H>
+template <class CT, class ST, int H, bool RHO>
 __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io, int64_t ld,
                                                            const void* twp,
                                                            const double* __restrict__ eig_l,
-                                                           const int32_t* done) {
-  if (*done) return;
+                                                           DevState st) {
+  if (st.fl[FL_DONE]) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
@@ -536,6 +536,7 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
+  double rho = 0.0;   // RHO: this block's share of sum rhat^2 / (lambda + mu)
   {
     RowChunks<ST, H> ch;
     load_rows<ST, H>(io, ld, row0, ch, tid);
@@ -560,11 +561,22 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
       Cx<CT> ck, cp;
       post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
       // X~ at k, n-k, h-k, h+k; c_k (inverse) = X~_k - i X~_{n-k}
-      const CT xk = ck.x * d(k);
-      const CT xnk = k > 0 ? -ck.y * d(N - k) : (CT)0;
-      const CT xp = cp.x * d(H - k);
-      const CT xnp = -cp.y * d(H + k);   // k = 0: index h, equal to xp
+      const CT dk = d(k), dnk = d(N - k), dp = d(H - k), dnp = d(H + k);
+      const CT xk = ck.x * dk;
+      const CT xnk = k > 0 ? -ck.y * dnk : (CT)0;
+      const CT xp = cp.x * dp;
+      const CT xnp = -cp.y * dnp;   // k = 0: index h, equal to xp
       pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf, row * H);
+      if constexpr (RHO) {
+        // squared orthonormal coefficients (s_k Re c_k etc.) over the
+        // eigenvalue sum; each index of the column once (k = 0 and k = h/2
+        // hold two of them, not four)
+        const double s0 = 1.0 / (double)N, s1 = 2.0 / (double)N;   // s_k^2
+        rho += (k == 0 ? s0 : s1) * (double)ck.x * (double)ck.x * (double)dk;
+        if (k > 0) rho += s1 * (double)ck.y * (double)ck.y * (double)dnk;
+        if (k < H / 2) rho += s1 * (double)cp.x * (double)cp.x * (double)dp;
+        if (k > 0 && k < H / 2) rho += s1 * (double)cp.y * (double)cp.y * (double)dnp;
+      }
     }
   }
   __syncthreads();
@@ -589,16 +601,41 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     }
     *reinterpret_cast<V*>(io + (row0 + row) * ld + c) = o;
   }
+  if constexpr (RHO) {
+    double acc[1] = {rho};
+    const int slots[1] = {PR_ZR};
+    write_partials<1>(st, slots, acc, (int)blockIdx.x);
+  }
+}
+
+// rho = sum of the column pass's partials (divided by the square of the FP16
+// input scale), stored for iteration iter with beta = rho / rho_{iter-1}
+// (0 at iter 0).
+__global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int iter, int f16) {
+  if (st.fl[FL_DONE]) return;
+  double rho = reduce_slot<1024>(st, PR_ZR, n);
+  if (threadIdx.x == 0) {
+    if (f16) {
+      const double sc = st.sc[SC_SCALE];
+      rho /= sc * sc;
+    }
+    st.sc[SC_RHO + (iter & 1)] = rho;
+    st.sc[SC_BETA] = iter > 0 ? rho / st.sc[SC_RHO + ((iter - 1) & 1)] : 0.0;
+  }
 }
 
 // ---- pass 5: DCT-III along rows, z.r, z.q, sum z -------------------------
 // The stored coefficients go to LDS by put_rows_inv, so that each pair's four
 // inputs sit in the two slots the pair overwrites: the pre-processing runs in
 // place with no barrier between its reads and writes.
-template <class CT, class SI, class TO, int H, bool FLEX>
+// OUT: 0 z and the dots z.r, sum z; 1 also z.q (flexible beta); 2 the new
+// direction p = z + beta p_in into z (p_in, passed as q, unread at iter 0),
+// no dots.
+template <class CT, class SI, class TO, int H, int OUT>
 __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
     const SI* __restrict__ in, int64_t ld, TO* __restrict__ z, const TO* __restrict__ r,
-    const TO* __restrict__ q, const void* twp, DevState st, int use_scale) {
+    const TO* __restrict__ q, const void* twp, DevState st, int use_scale, int iter) {
+  constexpr bool FLEX = OUT == 1;
   if (st.fl[FL_DONE]) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
@@ -639,6 +676,36 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   constexpr int NCH = ROWS * N / W / kThreads;
   constexpr int BATCH = NCH < 8 ? NCH : 8;
   static_assert(NCH % BATCH == 0, "output batches");
+  if constexpr (OUT == 2) {
+    const TO beta = (TO)st.sc[SC_BETA];
+    const bool first = iter == 0;
+#pragma unroll
+    for (int i0 = 0; i0 < NCH; i0 += BATCH) {
+      V pv[BATCH];
+#pragma unroll
+      for (int b = 0; b < BATCH; ++b) {
+        const int e0 = (tid + (i0 + b) * kThreads) * W;
+        if (!first) pv[b] = *reinterpret_cast<const V*>(q + (row0 + e0 / N) * ld + e0 % N);
+      }
+#pragma unroll
+      for (int b = 0; b < BATCH; ++b) {
+        const int e0 = (tid + (i0 + b) * kThreads) * W;
+        const int row = e0 / N, c = e0 % N;
+        TO zo[W];
+        if constexpr (W >= 4) {
+          inv_chunk<CT, H, W, TO>(buf, row, c, inv_h, zo);
+        } else {
+#pragma unroll
+          for (int t = 0; t < W; ++t) zo[t] = (TO)inv_value<CT, N>(v, row, c + t, inv_h);
+        }
+        V o;
+#pragma unroll
+        for (int t = 0; t < W; ++t) o[t] = first ? zo[t] : zo[t] + beta * pv[b][t];
+        *reinterpret_cast<V*>(z + (row0 + row) * ld + c) = o;
+      }
+    }
+    return;
+  }
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i0 = 0; i0 < NCH; i0 += BATCH) {
@@ -846,29 +913,46 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   log_mark(L, IRLSU_LK_ROWS_DCT2, s);
   launch_transpose<ST>(T1, N, M, T2, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
+  int ncols = 0;
   with_h(N / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
-    hipLaunchKernelGGL((fct_cols_kernel<CT, ST, H>), dim3((unsigned)(M / rows_per_block<H>())),
-                       dim3(kThreads), 0, s, T2, N, a.twN, static_cast<const double*>(a.eigM),
-                       done);
+    ncols = (int)(M / rows_per_block<H>());
+    if (a.spectral)
+      hipLaunchKernelGGL((fct_cols_kernel<CT, ST, H, true>), dim3((unsigned)ncols),
+                         dim3(kThreads), 0, s, T2, N, a.twN,
+                         static_cast<const double*>(a.eigM), a.st);
+    else
+      hipLaunchKernelGGL((fct_cols_kernel<CT, ST, H, false>), dim3((unsigned)ncols),
+                         dim3(kThreads), 0, s, T2, N, a.twN,
+                         static_cast<const double*>(a.eigM), a.st);
   });
   log_mark(L, IRLSU_LK_COLS, s);
+  if (a.spectral) {
+    hipLaunchKernelGGL(fct_rho_kernel, dim3(1), dim3(1024), 0, s, a.st, ncols, a.iter, f16);
+    log_mark(L, IRLSU_LK_PARTIALS, s);
+  }
   launch_transpose<ST>(T2, M, N, T1, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
   int nb = 0;
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
     nb = (int)(N / rows_per_block<H>());
-    if (q)
-      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, true>), dim3((unsigned)nb),
-                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16);
+    if (a.spectral)
+      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, 2>), dim3((unsigned)nb),
+                         dim3(kThreads), 0, s, T1, M, static_cast<T*>(a.p_out), r,
+                         static_cast<const T*>(a.p_in), a.twM, a.st, f16, a.iter);
+    else if (q)
+      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, 1>), dim3((unsigned)nb),
+                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16, 0);
     else
-      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, false>), dim3((unsigned)nb),
-                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16);
+      hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, 0>), dim3((unsigned)nb),
+                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16, 0);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT3, s);
-  hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, a.st, nb);
-  log_mark(L, IRLSU_LK_PARTIALS, s);
+  if (!a.spectral) {
+    hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, a.st, nb);
+    log_mark(L, IRLSU_LK_PARTIALS, s);
+  }
   return 1;
 }
 

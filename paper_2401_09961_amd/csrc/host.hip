@@ -270,6 +270,17 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
   launch_stencil<T>(ST_RESID, ra, s);
   PrecondArgs pa = precond_args<T>(pl, W, W.v[V_R], W.v[V_Z], flexible ? W.v[V_Q] : nullptr, 1,
                                    nvec);
+  // Fast form with plain beta: rho = r . z comes from the spectral
+  // coefficients (Parseval) in the column pass, and the last pass writes the
+  // direction p_l = z_l + beta_l p_{l-1} itself; the stencil then only
+  // applies the operator to p (it reads p and Omega instead of z, p_old and
+  // Omega).
+  const bool spectral = pl->fast && !flexible;
+  if (spectral) {
+    pa.spectral = 1;
+    pa.iter = 0;
+    pa.p_out = P[0];
+  }
   const int nprec = launch_precond(pa, s);
   for (int l = 0; l < prm.pcg_max; ++l) {
     LaunchLog* L = (pl->prof && irls_k == pl->prof_k && l == pl->prof_l) ? pl->prof : nullptr;
@@ -279,7 +290,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     }
     StencilArgs<T> fa = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
     fa.z = W.v[V_Z];
-    fa.p_in = P[(l + 1) & 1];
+    fa.p_in = spectral ? P[l & 1] : P[(l + 1) & 1];
     fa.p_out = P[l & 1];
     fa.q = W.v[V_Q];
     fa.iter = l;
@@ -287,7 +298,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     fa.nparts_prec = nprec;
     fa.nparts_res = nvec;
     fa.check_done = 1;
-    const int npq = launch_stencil<T>(ST_FUSED, fa, s);
+    const int npq = launch_stencil<T>(spectral ? ST_APPLY : ST_FUSED, fa, s);
     log_mark(L, IRLSU_LK_STENCIL, s);
     AxpyArgs<T> xa;
     xa.u = x;
@@ -310,6 +321,11 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     if (l + 1 < prm.pcg_max) {
       PrecondArgs pl_args = pa;
       pl_args.log = L;
+      if (spectral) {
+        pl_args.iter = l + 1;
+        pl_args.p_in = P[l & 1];
+        pl_args.p_out = P[(l + 1) & 1];
+      }
       launch_precond(pl_args, s);
     }
     if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;

@@ -249,6 +249,14 @@ struct PrecondArgs {
   int fast = 0;
   const void* twN = nullptr;
   const void* twM = nullptr;
+  // fast form, direction output: rho = r . z from the spectral coefficients
+  // (Parseval: sum rhat^2 / (lambda + mu)) in the column pass, then the last
+  // pass writes p_out = z + beta p_in (beta = rho_iter / rho_{iter-1}; p_out
+  // = z at iter 0) instead of z and the dots
+  int spectral = 0;
+  int iter = 0;
+  const void* p_in = nullptr;
+  void* p_out = nullptr;
   LaunchLog* log = nullptr;   // nullable: per-launch events
 };
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s);

@@ -37,5 +37,14 @@ def test_folded_form_reports_dense_equivalent_and_executed():
 
 
 def test_f64_bytes_double():
-    kern = bench.kernel_table([("stencil", 1.0), ("axpy", 1.0)], "f64", "fast", 256, 256, False)
+    kern = bench.kernel_table([("stencil", 1.0), ("axpy", 1.0)], "f64", "folded", 256, 256, False)
     assert kern["stencil_kernel"]["bytes_per_launch"] == 48 * 256 * 256
+    assert kern["axpy_kernel"]["bytes_per_launch"] == 48 * 256 * 256
+
+
+def test_fast_plain_beta_stencil_applies_the_operator_only():
+    """Fast form, plain beta: the stencil reads p, Ov, Oh and writes q."""
+    kern = bench.kernel_table([("stencil", 1.0), ("rows_dct3", 1.0)], "f16", "fast", 256, 256,
+                              False)
+    assert kern["stencil_kernel"]["bytes_per_launch"] == 16 * 256 * 256
+    assert kern["fct_rows_inv_kernel"]["bytes_per_launch"] == 10 * 256 * 256

@@ -206,8 +206,10 @@ def test_profile_records_one_pcg_iteration(form):
     torch.cuda.synchronize()
     kinds = [k for k, _ in rec]
     assert kinds[:2] == ["stencil", "axpy"]
-    expect = {"fast": ["prologue", "rows_dct2", "transpose", "cols", "transpose", "rows_dct3",
-                       "partials"],
+    # fast form, plain beta: rho from the column pass's spectral sum, then
+    # the last pass writes the new direction
+    expect = {"fast": ["prologue", "rows_dct2", "transpose", "cols", "partials", "transpose",
+                       "rows_dct3"],
               "folded": ["prologue", "butterfly"] + ["product"] * 2 + ["butterfly"]
               + ["product"] * 4 + ["butterfly"] + ["product"] * 2 + ["dots"],
               "dense": ["product"] * 4}[form]
