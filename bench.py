@@ -161,6 +161,8 @@ def kernel_table(launches, prec, form, N, M, flexible):
         "axpy": ("axpy_kernel", 6 * e),                    # p, q, r, d in; r, d out
         "residual": ("stencil_kernel(residual)", 8 + 5 * e),  # u, d, b, Ov, Oh in; r out
         "rows_dct2": ("fct_rows_fwd_kernel", e + s),        # r in; T1 out
+        # CG update fused with the row DCT-II: p, q, r, d in; r, d, T1 out
+        "update_dct2": ("fct_rows_fwd_cg_kernel", 6 * e + s),
         "transpose": ("transpose_kernel", 2 * s),
         "cols": ("fct_cols_kernel", 2 * s),
         # T, r, (q) in; z out -- spectral: T, p_old in; p out

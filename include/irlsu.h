@@ -394,7 +394,10 @@ enum {
   IRLSU_LK_PARTIALS = 8,   /* fold of per-block partial sums */
   IRLSU_LK_STENCIL = 9,    /* p = z + beta p, q = D^T Omega D p, p.q (PCG loop form) */
   IRLSU_LK_AXPY = 10,      /* alpha, d += alpha p, r -= alpha q, ||r||^2 */
-  IRLSU_LK_RESIDUAL = 11   /* true-residual refresh r = b - A (u + d) */
+  IRLSU_LK_RESIDUAL = 11,  /* true-residual refresh r = b - A (u + d) */
+  IRLSU_LK_UPDATE_DCT2 = 12, /* fast form: r -= alpha q, d += alpha p fused with the
+                                DCT-II along rows of the new r */
+  IRLSU_LK_ALPHA = 13      /* alpha = rho / p.q and the FP16 input scale */
 };
 
 /* Timing of the preconditioner of Section 3.3 (the products named there as

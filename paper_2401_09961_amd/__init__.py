@@ -117,7 +117,7 @@ PLAN_FORMS = {"auto": 0, "dense": 1, "folded": 2, "fast": 3}
 IRLSU_MAX_LAUNCHES = 32
 LAUNCH_KINDS = {0: "product", 1: "rows_dct2", 2: "transpose", 3: "cols", 4: "rows_dct3",
                 5: "butterfly", 6: "dots", 7: "prologue", 8: "partials", 9: "stencil",
-                10: "axpy", 11: "residual"}
+                10: "axpy", 11: "residual", 12: "update_dct2", 13: "alpha"}
 
 
 _lib = None

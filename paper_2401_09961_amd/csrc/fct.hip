@@ -520,6 +520,117 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
   }
 }
 
+// ---- CG update fused with pass 1 ---------------------------------------
+// alpha = rho / p.q (p.q and ||q||^2 from the stencil's partials); the FP16
+// input scale of the next application from the bound ||r - alpha q|| <=
+// ||r|| + |alpha| ||q|| (||r||^2 as the last convergence test stored it), so
+// the new residual's scaled values stay at or below the usual 1e-3 rms.
+__global__ __launch_bounds__(kThreads) void cg_alpha_kernel(DevState st, int nparts_pq, int iter,
+                                                           int f16, double npix) {
+  if (st.fl[FL_DONE]) return;
+  const double pq = reduce_slot(st, PR_PQ, nparts_pq);
+  const double qq = reduce_slot(st, PR_AUX, nparts_pq);
+  if (threadIdx.x != 0) return;
+  const double rho = st.sc[SC_RHO + (iter & 1)];
+  if (!(pq > 0.0) || !(rho >= 0.0) || !isfinite(pq)) {
+    st.fl[FL_STATUS] |= 1;
+    st.fl[FL_DONE] = 1;
+    return;
+  }
+  const double alpha = rho / pq;
+  st.sc[SC_ALPHA + (iter & 1)] = alpha;
+  st.sc[SC_PQ] = pq;
+  st.fl[FL_ITERS] = iter + 1;
+  if (f16) {
+    const double bound = sqrt(st.sc[SC_RR]) + fabs(alpha) * sqrt(qq);
+    st.sc[SC_SCALE] = bound > 0.0 ? 1e-3 * sqrt(npix) / bound : 1.0;
+  }
+}
+
+// Per row group: r -= alpha q, d += alpha p (written back, streaming), the
+// new r (times the input scale) transformed like pass 1 into out; partials
+// ||r||^2 and sum r, zero padded to nparts_out.
+template <class CT, class T, class TO, int H>
+__global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
+    T* __restrict__ r, T* __restrict__ d, const T* __restrict__ p, const T* __restrict__ q,
+    int64_t ld, TO* __restrict__ out, const void* twp, DevState st, int iter, int f16,
+    int nparts_out) {
+  if (st.fl[FL_DONE]) return;
+  constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  constexpr int NP = H / 2 + 1;
+  constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
+  using RC = RowChunks<T, H>;
+  using V = typename Vec16<T>::type;
+  constexpr int W = RC::W;
+  __shared__ Cx<CT> buf[padded<ROWS * H>()];
+  const Tw<CT> tw = tw_of<CT, H>(twp);
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  CT* v = reinterpret_cast<CT*>(buf);
+  const T al = (T)st.sc[SC_ALPHA + (iter & 1)];
+  double acc[2] = {0.0, 0.0};
+  {
+    RC ch;
+    constexpr int UN = RC::NCH < 2 ? RC::NCH : 2;
+#pragma unroll
+    for (int i0 = 0; i0 < RC::NCH; i0 += UN) {
+      V pv[UN], qv[UN], rv[UN], dv[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int e0 = (tid + (i0 + u) * kThreads) * W;
+        const int64_t o = (row0 + e0 / N) * ld + e0 % N;
+        pv[u] = *reinterpret_cast<const V*>(p + o);
+        qv[u] = *reinterpret_cast<const V*>(q + o);
+        rv[u] = *reinterpret_cast<const V*>(r + o);
+        dv[u] = *reinterpret_cast<const V*>(d + o);
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int e0 = (tid + (i0 + u) * kThreads) * W;
+        const int64_t o = (row0 + e0 / N) * ld + e0 % N;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          rv[u][t] = rv[u][t] - al * qv[u][t];
+          dv[u][t] = dv[u][t] + al * pv[u][t];
+          acc[0] += (double)rv[u][t] * (double)rv[u][t];
+          acc[1] += (double)rv[u][t];
+        }
+        __builtin_nontemporal_store(rv[u], reinterpret_cast<V*>(r + o));
+        __builtin_nontemporal_store(dv[u], reinterpret_cast<V*>(d + o));
+        ch.d[i0 + u] = rv[u];
+      }
+    }
+    put_rows<CT, T, H>(ch, v, f16 ? (CT)st.sc[SC_SCALE] : (CT)1, tid);
+  }
+  __syncthreads();
+  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
+  const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
+#pragma unroll
+  for (int qq = 0; qq < PP; ++qq) {
+    const int pp = tid + qq * kThreads;
+    if (pp < ROWS * NP) {
+      const int row = pp / NP, k = pp % NP;
+      Cx<CT> ck, cp;
+      post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
+      TO* o = out + (row0 + row) * ld;
+      o[k] = (TO)(ck.x * (k == 0 ? s0 : s1));
+      if (k > 0) o[N - k] = (TO)(-ck.y * s1);
+      if (H - k != k) {
+        o[H - k] = (TO)(cp.x * s1);
+        if (k > 0) o[H + k] = (TO)(-cp.y * s1);
+      }
+    }
+  }
+  const int slots[2] = {PR_RR, PR_RSUM};
+  write_partials<2>(st, slots, acc, (int)blockIdx.x);
+  if (threadIdx.x == 0) {
+    for (int k = (int)blockIdx.x + (int)gridDim.x; k < nparts_out; k += (int)gridDim.x) {
+      st.part[(size_t)PR_RR * kMaxPartials + st.off + k] = 0.0;
+      st.part[(size_t)PR_RSUM * kMaxPartials + st.off + k] = 0.0;
+    }
+  }
+}
+
 // ---- pass 3: DCT-II, spectral division, DCT-III along rows of the
 // transposed intermediate (the columns of the image) ----------------------
 template <class CT, class ST, int H, bool RHO>
@@ -902,15 +1013,18 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   const int f16 = std::is_same<ST, _Float16>::value ? 1 : 0;
   LaunchLog* L = a.log;
   log_start(L, s);
-  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
+  // fused head: pass 1 ran with the CG update and set the input scale
+  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, a.fused_head ? -1 : f16, N * M, s);
   log_mark(L, IRLSU_LK_PROLOGUE, s);
-  with_h(M / 2, [&](auto hc) {
-    constexpr int H = decltype(hc)::value;
-    hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, T, ST, H>),
-                       dim3((unsigned)(N / rows_per_block<H>())), dim3(kThreads), 0, s, r, M, T1,
-                       a.twM, done, f16 ? a.st.sc + SC_SCALE : nullptr);
-  });
-  log_mark(L, IRLSU_LK_ROWS_DCT2, s);
+  if (!a.fused_head) {
+    with_h(M / 2, [&](auto hc) {
+      constexpr int H = decltype(hc)::value;
+      hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, T, ST, H>),
+                         dim3((unsigned)(N / rows_per_block<H>())), dim3(kThreads), 0, s, r, M,
+                         T1, a.twM, done, f16 ? a.st.sc + SC_SCALE : nullptr);
+    });
+    log_mark(L, IRLSU_LK_ROWS_DCT2, s);
+  }
   launch_transpose<ST>(T1, N, M, T2, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
   int ncols = 0;
@@ -955,6 +1069,58 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   }
   return 1;
 }
+
+int fct_row_blocks(int64_t N, int64_t M) {
+  int nb = 0;
+  with_h(M / 2, [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    nb = (int)(N / rows_per_block<H>());
+  });
+  return nb;
+}
+
+template <class CT, class T, class ST>
+static int cg_update_impl(const PrecondArgs& a, T* r, T* d, const T* p, const T* q, int nparts_pq,
+                          int iter, int nparts_out, hipStream_t s) {
+  const int64_t N = a.N, M = a.M;
+  const int f16 = std::is_same<ST, _Float16>::value ? 1 : 0;
+  LaunchLog* L = a.log;
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, s, a.st, nparts_pq, iter, f16,
+                     (double)(N * M));
+  log_mark(L, IRLSU_LK_ALPHA, s);
+  int nb = 0;
+  with_h(M / 2, [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    nb = (int)(N / rows_per_block<H>());
+    hipLaunchKernelGGL((fct_rows_fwd_cg_kernel<CT, T, ST, H>), dim3((unsigned)nb),
+                       dim3(kThreads), 0, s, r, d, p, q, M, static_cast<ST*>(a.T1), a.twM, a.st,
+                       iter, f16, nparts_out);
+  });
+  log_mark(L, IRLSU_LK_UPDATE_DCT2, s);
+  return nb;
+}
+
+template <class T>
+int launch_cg_update_fast(const PrecondArgs& a, T* r, T* d, const T* p, const T* q,
+                          int nparts_pq, int iter, int nparts_out, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    return cg_update_impl<double, double, double>(a, r, d, p, q, nparts_pq, iter, nparts_out, s);
+  } else {
+    switch (a.kind) {
+      case OK_F32: return cg_update_impl<float, float, float>(a, r, d, p, q, nparts_pq, iter,
+                                                              nparts_out, s);
+      case OK_BF16: return cg_update_impl<float, float, __bf16>(a, r, d, p, q, nparts_pq, iter,
+                                                                nparts_out, s);
+      case OK_F16: return cg_update_impl<float, float, _Float16>(a, r, d, p, q, nparts_pq, iter,
+                                                                 nparts_out, s);
+    }
+    return 0;
+  }
+}
+template int launch_cg_update_fast<float>(const PrecondArgs&, float*, float*, const float*,
+                                          const float*, int, int, int, hipStream_t);
+template int launch_cg_update_fast<double>(const PrecondArgs&, double*, double*, const double*,
+                                           const double*, int, int, int, hipStream_t);
 
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s) {
   switch (a.kind) {

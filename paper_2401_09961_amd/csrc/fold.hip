@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kThreads) void fold_prologue_kernel(DevState st, in
     }
   }
   // the same FP16 range argument as the dense form's first product
-  st.sc[SC_SCALE] = want_scale ? (rr > 0.0 ? 1e-3 * sqrt((double)npix / rr) : 1.0) : 1.0;
+  // (want_scale < 0: the scale was set already, with the input it applies to)
+  if (want_scale >= 0)
+    st.sc[SC_SCALE] = want_scale ? (rr > 0.0 ? 1e-3 * sqrt((double)npix / rr) : 1.0) : 1.0;
 }
 
 void launch_fold_prologue(DevState st, int nparts_rr, int check_conv, int want_scale, int64_t npix,

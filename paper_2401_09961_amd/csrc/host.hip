@@ -267,6 +267,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
   ra.b = rhs;
   ra.r = W.v[V_R];
   ra.check_done = 0;
+  if (pl->fast && !flexible) ra.nparts_out = std::max(nvec, fct_row_blocks(pl->N, pl->M));
   launch_stencil<T>(ST_RESID, ra, s);
   PrecondArgs pa = precond_args<T>(pl, W, W.v[V_R], W.v[V_Z], flexible ? W.v[V_Q] : nullptr, 1,
                                    nvec);
@@ -276,10 +277,16 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
   // applies the operator to p (it reads p and Omega instead of z, p_old and
   // Omega).
   const bool spectral = pl->fast && !flexible;
+  // On that path the CG update of iteration l also runs fused with the next
+  // application's first pass (launch_cg_update_fast), except where a
+  // true-residual refresh follows it; the producers of ||r||^2 partials
+  // (residual stencil, update, fused update) then write one common count.
+  const int nrr = spectral ? std::max(nvec, fct_row_blocks(pl->N, pl->M)) : nvec;
   if (spectral) {
     pa.spectral = 1;
     pa.iter = 0;
     pa.p_out = P[0];
+    pa.nparts_rr = nrr;
   }
   const int nprec = launch_precond(pa, s);
   for (int l = 0; l < prm.pcg_max; ++l) {
@@ -298,8 +305,29 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     fa.nparts_prec = nprec;
     fa.nparts_res = nvec;
     fa.check_done = 1;
+    fa.want_qq = spectral ? 1 : 0;
     const int npq = launch_stencil<T>(spectral ? ST_APPLY : ST_FUSED, fa, s);
     log_mark(L, IRLSU_LK_STENCIL, s);
+    const bool refresh =
+        prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max;
+    if (spectral && !refresh && l + 1 < prm.pcg_max) {
+      PrecondArgs fused = pa;
+      fused.log = L;
+      fused.iter = l + 1;
+      fused.p_in = P[l & 1];
+      fused.p_out = P[(l + 1) & 1];
+      fused.fused_head = 1;
+      launch_cg_update_fast<T>(fused, W.v[V_R], d, P[l & 1], W.v[V_Q], npq, l, nrr, s);
+      launch_precond(fused, s);
+      if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+      if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
+        HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (pl->h_flags[FL_DONE]) break;
+      }
+      continue;
+    }
     AxpyArgs<T> xa;
     xa.u = x;
     xa.d = d;
@@ -308,12 +336,12 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     xa.q = W.v[V_Q];
     xa.n = (int64_t)npx;
     xa.nparts_pq = npq;
-    xa.nparts_out = nvec;
+    xa.nparts_out = nrr;
     xa.iter = l;
     xa.st = st;
     launch_axpy<T>(xa, s, axpy_blocks(nvec));
     log_mark(L, IRLSU_LK_AXPY, s);
-    if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max) {
+    if (refresh) {
       ra.check_done = 1;
       launch_stencil<T>(ST_RESID, ra, s);
       log_mark(L, IRLSU_LK_RESIDUAL, s);
@@ -336,7 +364,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
       if (pl->h_flags[FL_DONE]) break;
     }
   }
-  launch_finalize_rr(st, nvec, s);
+  launch_finalize_rr(st, nrr, s);
   launch_commit<T>(x, d, (int64_t)npx, s);
   irlsu_status rs = read_back(pl, W, s);
   if (rs != IRLSU_OK) return rs;

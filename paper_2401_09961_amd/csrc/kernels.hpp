@@ -66,6 +66,8 @@ struct StencilArgs {
   int nparts_prec;     // FUSED: partials of the preconditioner epilogue
   int nparts_res;      // FUSED: partials of sum r (axpy or residual kernel)
   int check_done;      // skip when the PCG done flag is set
+  int want_qq = 0;     // APPLY: also the partial ||q||^2 (slot PR_AUX)
+  int nparts_out = 0;  // RESID: partial count the consumers read (zero padded)
   DevState st;
 };
 
@@ -257,9 +259,22 @@ struct PrecondArgs {
   int iter = 0;
   const void* p_in = nullptr;
   void* p_out = nullptr;
+  // the row DCT-II of r already ran, fused with the CG update that produced r
+  // (launch_cg_update_fast); the prologue then only tests convergence
+  int fused_head = 0;
   LaunchLog* log = nullptr;   // nullable: per-launch events
 };
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s);
+// Blocks of the fast form's row passes over an N x M image.
+int fct_row_blocks(int64_t N, int64_t M);
+// The CG update of iteration iter fused with the first pass of the next
+// preconditioner application: alpha (and the FP16 input scale from the bound
+// ||r|| + |alpha| ||q|| on the new residual) in one block, then per row
+// r -= alpha q, d += alpha p and the DCT-II of the new r into a.T1; partials
+// ||r||^2, sum r zero padded to nparts_out.  Returns the row-pass grid.
+template <class T>
+int launch_cg_update_fast(const PrecondArgs& a, T* r, T* d, const T* p, const T* q,
+                          int nparts_pq, int iter, int nparts_out, hipStream_t s);
 
 // ---- augmented (U, V^v, V^h) solve ------------------------------------------
 template <class T>

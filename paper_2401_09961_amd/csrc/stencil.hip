@@ -183,6 +183,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, in
         for (int e = 0; e < 4; ++e) {
           qt.v[e] = (T)q.v[e];
           acc0 += (double)pc.v[e] * (double)qt.v[e];
+          if (MODE == ST_APPLY && a.want_qq) acc1 += (double)qt.v[e] * (double)qt.v[e];
         }
         st4(a.q + o, qt);
         if constexpr (MODE == ST_FUSED) {
@@ -203,6 +204,18 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, in
   if constexpr (MODE == ST_RESID) {
     double v[2] = {acc0, acc1};
     const int slots[2] = {PR_RR, PR_RSUM};
+    write_partials<2>(a.st, slots, v, lb);
+    // a larger partial count read by the consumers: the rest is zero
+    if (threadIdx.x == 0 && a.nparts_out > 0) {
+      const int nb = (int)(gridDim.x * gridDim.y);
+      for (int k = lb + nb; k < a.nparts_out; k += nb) {
+        a.st.part[(size_t)PR_RR * kMaxPartials + a.st.off + k] = 0.0;
+        a.st.part[(size_t)PR_RSUM * kMaxPartials + a.st.off + k] = 0.0;
+      }
+    }
+  } else if (MODE == ST_APPLY && a.want_qq) {
+    double v[2] = {acc0, acc1};
+    const int slots[2] = {PR_PQ, PR_AUX};
     write_partials<2>(a.st, slots, v, lb);
   } else {
     double v[1] = {acc0};
