@@ -525,11 +525,11 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
 // input scale of the next application from the bound ||r - alpha q|| <=
 // ||r|| + |alpha| ||q|| (||r||^2 as the last convergence test stored it), so
 // the new residual's scaled values stay at or below the usual 1e-3 rms.
-__global__ __launch_bounds__(kThreads) void cg_alpha_kernel(DevState st, int nparts_pq, int iter,
-                                                           int f16, double npix) {
+__global__ __launch_bounds__(1024) void cg_alpha_kernel(DevState st, int nparts_pq, int iter,
+                                                       int f16, double npix) {
   if (st.fl[FL_DONE]) return;
-  const double pq = reduce_slot(st, PR_PQ, nparts_pq);
-  const double qq = reduce_slot(st, PR_AUX, nparts_pq);
+  const double pq = reduce_slot<1024>(st, PR_PQ, nparts_pq);
+  const double qq = reduce_slot<1024>(st, PR_AUX, nparts_pq);
   if (threadIdx.x != 0) return;
   const double rho = st.sc[SC_RHO + (iter & 1)];
   if (!(pq > 0.0) || !(rho >= 0.0) || !isfinite(pq)) {
@@ -1085,7 +1085,7 @@ static int cg_update_impl(const PrecondArgs& a, T* r, T* d, const T* p, const T*
   const int64_t N = a.N, M = a.M;
   const int f16 = std::is_same<ST, _Float16>::value ? 1 : 0;
   LaunchLog* L = a.log;
-  hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kThreads), 0, s, a.st, nparts_pq, iter, f16,
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(1024), 0, s, a.st, nparts_pq, iter, f16,
                      (double)(N * M));
   log_mark(L, IRLSU_LK_ALPHA, s);
   int nb = 0;

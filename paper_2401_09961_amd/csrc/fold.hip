@@ -105,11 +105,12 @@ __global__ __launch_bounds__(kThreads) void unfold_cols_dots_kernel(const T* zeo
 
 // Prologue of one application: convergence test on ||r||^2 (the first
 // product's job in the dense form) and the FP16 input scale.
-__global__ __launch_bounds__(kThreads) void fold_prologue_kernel(DevState st, int nparts_rr,
-                                                                int check_conv, int want_scale,
-                                                                int64_t npix) {
+template <int NT>
+__global__ __launch_bounds__(NT) void fold_prologue_kernel(DevState st, int nparts_rr,
+                                                          int check_conv, int want_scale,
+                                                          int64_t npix) {
   if (st.fl[FL_DONE]) return;
-  const double rr = reduce_slot(st, PR_RR, nparts_rr);
+  const double rr = reduce_slot<NT>(st, PR_RR, nparts_rr);
   if (threadIdx.x != 0) return;
   if (check_conv) {
     st.sc[SC_RR] = rr;
@@ -126,8 +127,13 @@ __global__ __launch_bounds__(kThreads) void fold_prologue_kernel(DevState st, in
 
 void launch_fold_prologue(DevState st, int nparts_rr, int check_conv, int want_scale, int64_t npix,
                           hipStream_t s) {
-  hipLaunchKernelGGL(fold_prologue_kernel, dim3(1), dim3(kThreads), 0, s, st, nparts_rr, check_conv,
-                     want_scale, npix);
+  // one block; 1024 threads once there are many partials to read
+  if (nparts_rr > 2048)
+    hipLaunchKernelGGL(fold_prologue_kernel<1024>, dim3(1), dim3(1024), 0, s, st, nparts_rr,
+                       check_conv, want_scale, npix);
+  else
+    hipLaunchKernelGGL(fold_prologue_kernel<kThreads>, dim3(1), dim3(kThreads), 0, s, st,
+                       nparts_rr, check_conv, want_scale, npix);
 }
 
 // Folded basis tables of size n (even): Pe[i][k'] = P[i][2k'], Po[i][k'] =
