@@ -721,11 +721,22 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
 
 // rho = sum of the column pass's partials (divided by the square of the FP16
 // input scale), stored for iteration iter with beta = rho / rho_{iter-1}
-// (0 at iter 0).
-__global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int iter, int f16) {
+// (0 at iter 0).  nparts_rr > 0: also the convergence test on the ||r||^2
+// partials of the fused update (the prologue's job on the other path; a
+// converged solve then wasted only the passes before this one).
+__global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int iter, int f16,
+                                                      int nparts_rr) {
   if (st.fl[FL_DONE]) return;
   double rho = reduce_slot<1024>(st, PR_ZR, n);
+  const double rr = nparts_rr > 0 ? reduce_slot<1024>(st, PR_RR, nparts_rr) : 0.0;
   if (threadIdx.x == 0) {
+    if (nparts_rr > 0) {
+      st.sc[SC_RR] = rr;
+      if (rr <= st.sc[SC_TOL2] * st.sc[SC_BB]) {
+        st.fl[FL_DONE] = 1;
+        return;
+      }
+    }
     if (f16) {
       const double sc = st.sc[SC_SCALE];
       rho /= sc * sc;
@@ -1013,10 +1024,11 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   const int f16 = std::is_same<ST, _Float16>::value ? 1 : 0;
   LaunchLog* L = a.log;
   log_start(L, s);
-  // fused head: pass 1 ran with the CG update and set the input scale
-  launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, a.fused_head ? -1 : f16, N * M, s);
-  log_mark(L, IRLSU_LK_PROLOGUE, s);
+  // fused head: pass 1 ran with the CG update and set the input scale; the
+  // convergence test moves into the rho kernel
   if (!a.fused_head) {
+    launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
+    log_mark(L, IRLSU_LK_PROLOGUE, s);
     with_h(M / 2, [&](auto hc) {
       constexpr int H = decltype(hc)::value;
       hipLaunchKernelGGL((fct_rows_fwd_kernel<CT, T, ST, H>),
@@ -1042,7 +1054,8 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   });
   log_mark(L, IRLSU_LK_COLS, s);
   if (a.spectral) {
-    hipLaunchKernelGGL(fct_rho_kernel, dim3(1), dim3(1024), 0, s, a.st, ncols, a.iter, f16);
+    hipLaunchKernelGGL(fct_rho_kernel, dim3(1), dim3(1024), 0, s, a.st, ncols, a.iter, f16,
+                       a.fused_head && a.check_conv ? a.nparts_rr : 0);
     log_mark(L, IRLSU_LK_PARTIALS, s);
   }
   launch_transpose<ST>(T2, M, N, T1, done, s);
