@@ -22,6 +22,11 @@
 //   cols_fused    T1[l][.]  = DCT-III( DCT-II(T2[l][.]) ./ (lambda_k + mu_l) )
 //   transpose     T2 = T1^T
 //   rows_inv      z[i][.]   = DCT-III along each row of T2; z.r, z.q, sum z
+// With plain beta (spectral path): cols also sums rhat^2 / (lambda + mu) =
+// r.z (Parseval), a one-block kernel forms rho and beta, and rows_inv writes
+// the direction p = z + beta p_old instead of z and its dots; the CG update
+// r -= alpha q, d += alpha p runs fused with rows_fwd of the next application
+// (fct_rows_fwd_cg_kernel, alpha from cg_alpha_kernel).
 #include <type_traits>
 
 #include "kernels.hpp"
