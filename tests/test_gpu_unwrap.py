@@ -25,7 +25,7 @@ from oracle import reduced as R
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-L1_RTOL = {"f64": 1e-9, "f32": 1e-5, "bf16": 1e-3}
+L1_RTOL = {"f64": 1e-9, "f32": 1e-5, "bf16": 1e-3, "f16": 1e-3}
 
 
 def npdt(prec):
@@ -84,7 +84,7 @@ def test_f64_history_matches_oracle(gen, shape):
     assert all(H[k + 1] <= H[k] * (1 + 1e-12) for k in range(K))
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("gen,shape", [("c2", (192, 176)), ("c3", (256, 256))])
 def test_reduced_precision_objective(prec, gen, shape):
     f = getattr(synth, "field_" + gen)(4, *shape)
@@ -111,7 +111,7 @@ def test_folded_plan_objective(prec):
         assert np.abs(Ug - Uo).max() < 1e-5 * np.abs(Uo).max()  # objectives are the parity; see above
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
 def test_fast_plan_objective(prec):
     """The whole path with the fast (cosine-transform) preconditioner on a
     rectangular power-of-two c3 residue field."""
