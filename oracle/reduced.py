@@ -26,12 +26,19 @@ What is computed (paper arXiv 2401.09961):
   mode (0, 0) set to zero (the pseudo-inverse choice of Appendix B).  The
   tau factor is dropped: CG iterates do not change when the preconditioner
   is scaled by a positive constant.
+* The Section 4.3 surrogate and the rounded (2 pi-congruent) output.
+* Adjoints: of the frozen-weight least-squares map (``adjoint``), and the
+  full implicit derivative of the Huber minimiser (``huber_minimiser``, an
+  exact active-set solve of the stationarity condition, and
+  ``adjoint_implicit``).
 
 Pins (tests/test_oracle_pins.py): closed-form eigenpairs, dense matrix
 definitions of S, T and D^T Omega D, pseudo-inverse identities, one-step
 convergence for unit weights, dense least squares, the Itoh integration
 case, monotone decrease of H_eps, linear-programming brute force on small
-grids, the 2 x 2 single-loop closed form, and the paper-form cross-oracle.
+grids, the 2 x 2 single-loop closed form, the paper-form cross-oracle,
+finite differences of both adjoints (of the frozen map; of the exact
+minimiser in C and X), the Itoh closed form of the implicit adjoint.
 Parity unpinned: pointwise U when the L1 / Huber minimiser is not unique.
 """
 from __future__ import annotations
