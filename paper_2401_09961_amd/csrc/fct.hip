@@ -212,10 +212,11 @@ __device__ __forceinline__ int pr(int e) { return 2 * pc(e >> 1) + (e & 1); }
 // value is rounded once from FP64, and a load replaces the products that
 // would form it.
 //
-// LOAD_ALL: every power from the table (fewest instructions; for passes bound
-// by arithmetic).  Otherwise w, w^2, w^4, w^8 from the table and the others
-// as products of two of them (at most three roundings; fewer loads, whose
-// waits would also wait for the pass's own HBM traffic).
+// LOAD_ALL: every power from the table (fewest instructions).  Otherwise w,
+// w^2, w^4, w^8 from the table and the others as products of two of them
+// (at most three roundings; fewer loads, whose waits also wait for the
+// pass's own earlier loads) -- measured faster in all three passes at
+// 8192^2, so the passes use it.
 template <class CT, int R, int NS, bool LOAD_ALL>
 __device__ __forceinline__ void stage_twiddles(const Cx<CT>* __restrict__ tw, int k,
                                                Cx<CT> (&w)[R]) {
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     put_rows<CT, ST, H>(ch, v, (CT)1, tid);
   }
   __syncthreads();
-  fft_rows<CT, H, ROWS, true>(buf, tw.fft, tid);
+  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
   // forward post-processing, division and inverse pre-processing of pair
   // (k, h-k), in place: the pair's two slots are read and written by the
   // same thread only.  With d = 1 / (lambda_k + mu_l), the scaled
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     }
   }
   __syncthreads();
-  fft_rows<CT, H, ROWS, true>(buf, tw.fft, tid);
+  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
   const CT inv_h = (CT)(1.0 / H);
   using V = typename Vec16<ST>::type;
   constexpr int W = Vec16<ST>::W;
