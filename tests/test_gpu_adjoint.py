@@ -39,7 +39,9 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-8), ("f32", 2e-3)])
-@pytest.mark.parametrize("shape", [(40, 33), (130, 140)])
+# (128, 256): power-of-two sides, the fast preconditioner with the spectral
+# rho and the fused CG update in the adjoint solve
+@pytest.mark.parametrize("shape", [(40, 33), (130, 140), (128, 256)])
 def test_adjoint_matches_oracle(prec, tol, shape):
     N, M = shape
     phi, X = residue_field(1, N, M)
