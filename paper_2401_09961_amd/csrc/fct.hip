@@ -342,15 +342,16 @@ __device__ __forceinline__ int perm(int e) {
   return (e & 1) ? N - 1 - (e >> 1) : (e >> 1);
 }
 
-// Forward post-processing of pair k (0 <= k <= h/2): c_k and c_{h-k} from
-// W_k and W_{h-k}.
+// Forward post-processing of pair k (0 <= k <= h/2): 2 c_k and 2 c_{h-k}
+// from W_k and W_{h-k}.  The even/odd split's factor 1/2 is left to the
+// caller's own scale (a power of two, so every rounding is unchanged).
 template <class CT, int H>
 __device__ __forceinline__ void post_pair(const Cx<CT>* buf, int base, int k, const Tw<CT>& tw,
                                           Cx<CT>& ck, Cx<CT>& cp) {
   const Cx<CT> wa = buf[pc(base + (k & (H - 1)))], wb = buf[pc(base + ((H - k) & (H - 1)))];
   auto c_of = [&](int kk, Cx<CT> x, Cx<CT> y) {
-    const Cx<CT> E = cscale(cadd(x, conjg(y)), (CT)0.5);
-    const Cx<CT> O = cscale(mul_mi(csub(x, conjg(y))), (CT)0.5);
+    const Cx<CT> E = cadd(x, conjg(y));
+    const Cx<CT> O = mul_mi(csub(x, conjg(y)));
     return cmul(tw.tq[kk], cadd(E, cmul(tw.tn[kk], O)));
   };
   ck = c_of(k, wa, wb);
@@ -358,18 +359,19 @@ __device__ __forceinline__ void post_pair(const Cx<CT>* buf, int base, int k, co
 }
 
 // Inverse pre-processing of pair k: from c_k = Xt_k - i Xt_{n-k} and
-// c_{h-k}, the FFT inputs W_k, W_{h-k} (conjugated for the forward FFT).
+// c_{h-k}, the FFT inputs 2 W_k, 2 W_{h-k} (conjugated for the forward FFT;
+// the factor 1/2 is left to the caller's output scale, as in post_pair).
 template <class CT, int H>
 __device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<CT>& tw, Cx<CT>* buf,
                                          int base) {
   const Cx<CT> vk = cmulc(ck, tw.tq[k]);      // e^{+i pi k/(2n)} c_k
   const Cx<CT> vp = cmulc(cp, tw.tq[H - k]);
-  const Cx<CT> Ek = cscale(cadd(vk, conjg(vp)), (CT)0.5);
-  const Cx<CT> Ok = cmulc(cscale(csub(vk, conjg(vp)), (CT)0.5), tw.tn[k]);
+  const Cx<CT> Ek = cadd(vk, conjg(vp));
+  const Cx<CT> Ok = cmulc(csub(vk, conjg(vp)), tw.tn[k]);
   buf[pc(base + (k & (H - 1)))] = conjg(cadd(Ek, mul_i(Ok)));
   if (k != H - k && k > 0) {
-    const Cx<CT> Ep = cscale(cadd(vp, conjg(vk)), (CT)0.5);
-    const Cx<CT> Op = cmulc(cscale(csub(vp, conjg(vk)), (CT)0.5), tw.tn[H - k]);
+    const Cx<CT> Ep = cadd(vp, conjg(vk));
+    const Cx<CT> Op = cmulc(csub(vp, conjg(vk)), tw.tn[H - k]);
     buf[pc(base + H - k)] = conjg(cadd(Ep, mul_i(Op)));
   }
 }
@@ -507,7 +509,8 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
   }
   __syncthreads();
   fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
-  const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
+  // s_k / 2: post_pair returns twice the coefficient
+  const CT s0 = (CT)(0.5 * sqrt(1.0 / N)), s1 = (CT)(0.5 * sqrt(2.0 / N));
 #pragma unroll
   for (int qq = 0; qq < PP; ++qq) {
     const int p = tid + qq * kThreads;
@@ -610,7 +613,8 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
   }
   __syncthreads();
   fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
-  const CT s0 = (CT)sqrt(1.0 / N), s1 = (CT)sqrt(2.0 / N);
+  // s_k / 2: post_pair returns twice the coefficient
+  const CT s0 = (CT)(0.5 * sqrt(1.0 / N)), s1 = (CT)(0.5 * sqrt(2.0 / N));
 #pragma unroll
   for (int qq = 0; qq < PP; ++qq) {
     const int pp = tid + qq * kThreads;
@@ -653,7 +657,9 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
-  double rho = 0.0;   // RHO: this block's share of sum rhat^2 / (lambda + mu)
+  // RHO: this thread's share of sum rhat^2 / (lambda + mu), in units of
+  // (2 c)^2 s_k^2 / 2 -- see the scale at the end
+  CT rho = (CT)0;
   {
     RowChunks<ST, H> ch;
     load_rows<ST, H>(io, ld, row0, ch, tid);
@@ -664,7 +670,9 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
   // forward post-processing, division and inverse pre-processing of pair
   // (k, h-k), in place: the pair's two slots are read and written by the
   // same thread only.  With d = 1 / (lambda_k + mu_l), the scaled
-  // coefficient divided by s_k is Re(c_k) d_k, and -Im(c_k) d_{n-k} at n-k.
+  // coefficient divided by s_k is Re(c_k) d_k, and -Im(c_k) d_{n-k} at n-k
+  // (here all of them twice over, from post_pair, and twice again from
+  // pre_pair: the output scale takes 1/4).
 #pragma unroll
   for (int qq = 0; qq < PP; ++qq) {
     const int p = tid + qq * kThreads;
@@ -687,18 +695,18 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
       if constexpr (RHO) {
         // squared orthonormal coefficients (s_k Re c_k etc.) over the
         // eigenvalue sum; each index of the column once (k = 0 and k = h/2
-        // hold two of them, not four)
-        const double s0 = 1.0 / (double)N, s1 = 2.0 / (double)N;   // s_k^2
-        rho += (k == 0 ? s0 : s1) * (double)ck.x * (double)ck.x * (double)dk;
-        if (k > 0) rho += s1 * (double)ck.y * (double)ck.y * (double)dnk;
-        if (k < H / 2) rho += s1 * (double)cp.x * (double)cp.x * (double)dp;
-        if (k > 0 && k < H / 2) rho += s1 * (double)cp.y * (double)cp.y * (double)dnp;
+        // hold two of them, not four).  s_0^2 = 1/n is half of the other
+        // s_k^2 = 2/n, which the scale at the end carries.
+        rho += (k == 0 ? (CT)0.5 : (CT)1) * ck.x * ck.x * dk;
+        if (k > 0) rho += ck.y * ck.y * dnk;
+        if (k < H / 2) rho += cp.x * cp.x * dp;
+        if (k > 0 && k < H / 2) rho += cp.y * cp.y * dnp;
       }
     }
   }
   __syncthreads();
   fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
-  const CT inv_h = (CT)(1.0 / H);
+  const CT inv_h = (CT)(0.25 / H);
   using V = typename Vec16<ST>::type;
   constexpr int W = Vec16<ST>::W;
   constexpr int NCH = ROWS * N / W / kThreads;
@@ -719,7 +727,8 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     *reinterpret_cast<V*>(io + (row0 + row) * ld + c) = o;
   }
   if constexpr (RHO) {
-    double acc[1] = {rho};
+    // (2 c)^2 -> c^2 and the factor s_k^2 = 2/n
+    double acc[1] = {(double)rho * (0.5 / (double)N)};
     const int slots[1] = {PR_ZR};
     write_partials<1>(st, slots, acc, (int)blockIdx.x);
   }
@@ -772,9 +781,10 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   const Tw<CT> tw = tw_of<CT, H>(twp);
   const int tid = threadIdx.x;
   CT* v = reinterpret_cast<CT*>(buf);
-  // output scale: 1/h of the inverse FFT, undoing the input scale of the
-  // first pass when the intermediates are FP16
-  const CT inv_h = (CT)(1.0 / H) / (use_scale ? (CT)st.sc[SC_SCALE] : (CT)1);
+  // output scale: 1/h of the inverse FFT and the 1/2 that pre_pair leaves
+  // out, undoing the input scale of the first pass when the intermediates
+  // are FP16
+  const CT inv_h = (CT)(0.5 / H) / (use_scale ? (CT)st.sc[SC_SCALE] : (CT)1);
   const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   {
