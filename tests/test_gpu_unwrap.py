@@ -327,3 +327,22 @@ def test_fast_path_with_frequent_residual_refresh(prec, every):
     done = [h for h in st["history"] if h["iters"] < p.pcg_max]
     assert done
     assert all(h["relres"] <= 1e-6 for h in done), [h["relres"] for h in done]
+
+
+@pytest.mark.parametrize("prec,bar", [("f32", 1e-5), ("f16", 5e-3)])
+def test_fast_form_short_solve_matches_oracle_iterate(prec, bar):
+    """One weight step and ten PCG iterations (Algorithm 2, no early stop) on
+    the fast form, whose rho = r.z comes from the column pass's spectral sum
+    and whose updates run fused: the iterate matches the oracle's after the
+    same ten iterations.  A wrong scale of rho would scale every step length
+    alpha and show here.  Bars: FP32 vectors and transforms, rounding
+    carried through ten iterations; FP16 stored intermediates (2^-11
+    relative) in every preconditioner application."""
+    f = synth.field_c3(3, 256, 128)
+    Ug, st, Uo, hist = run_both(f, prec, iters=1, maxit=10, tol=1e-14, form="fast")
+    assert st["history"][0]["iters"] == 10
+    Ug = Ug - Ug.mean()
+    Uo = Uo - Uo.mean()
+    rel = np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo)
+    print(f"short solve {prec}: rel L2 {rel:.3e}")
+    assert rel <= bar
