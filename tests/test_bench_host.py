@@ -17,6 +17,7 @@ def test_fast_form_table_and_dominant_kernel():
     assert kern["fct_rows_fwd_kernel"]["bytes_per_launch"] == 6 * px   # r FP32 in, T1 FP16 out
     assert kern["fct_rows_inv_kernel"]["bytes_per_launch"] == 14 * px  # T, r, q in; z out
     assert kern["stencil_kernel"]["bytes_per_launch"] == 24 * px
+    assert kern["fct_cols_kernel"]["bound"] == "alu"
     roof = bench.roofline(kern, "f16")
     assert roof["kernel"] == "axpy_kernel" and roof["bound"] == "hbm"
     assert abs(roof["achieved"] - 24 * px / 0.36e-3 / 1e9) < 0.1
@@ -48,3 +49,12 @@ def test_fast_plain_beta_stencil_applies_the_operator_only():
                               False)
     assert kern["stencil_kernel"]["bytes_per_launch"] == 16 * 256 * 256
     assert kern["fct_rows_inv_kernel"]["bytes_per_launch"] == 10 * 256 * 256
+
+
+def test_roofline_skips_the_issue_bound_column_pass():
+    """The column pass is reported as bound by instruction issue and never
+    priced against the HBM peak, even where it takes the most time."""
+    kern = bench.kernel_table([("stencil", 0.1), ("cols", 0.5), ("rows_dct3", 0.2)], "f16",
+                              "fast", 512, 512, False)
+    roof = bench.roofline(kern, "f16")
+    assert roof["kernel"] == "fct_rows_inv_kernel" and roof["bound"] == "hbm"
