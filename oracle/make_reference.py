@@ -8,6 +8,15 @@ so a partial run is still usable.  Only ``oracle`` and ``synth`` are used.
 Usage:
     python -m oracle.make_reference c3 --seed 0 --dtype float32
     python -m oracle.make_reference c2 --seed 0 --dtype float32 --size 2048
+    # converged schedule (solves that reach their tolerance): the plain-path
+    # parity reference of the 2048^2 field
+    python -m oracle.make_reference c2 --seed 0 --dtype float32 --iters 5 \
+        --tol 1e-6 --maxit 20000 --tag conv
+    # one weight step and exactly 30 PCG iterations from U = 0 (tol 0: no
+    # early stop), with U at 10^4 seeded pixels: a record free of the
+    # capped schedule's sensitivity
+    python -m oracle.make_reference c3 --seed 0 --dtype float32 --iters 1 \
+        --tol 0 --maxit 30 --samples 10000 --tag onestep30
 
 ``--dtype float32`` rounds the inputs (X and the weights) to float32 before
 the FP64 solve, which is what the FP32 and mixed GPU paths receive.
@@ -32,8 +41,19 @@ from oracle import reduced as R  # noqa: E402
 OUT_DIR = os.path.join(HERE, "reference")
 
 
-def reference_path(gen, seed, size, dtype):
-    return os.path.join(OUT_DIR, f"{gen}_seed{seed}_{size}_{dtype}.json")
+SAMPLE_SEED = 12345
+
+
+def reference_path(gen, seed, size, dtype, tag=""):
+    suffix = f"_{tag}" if tag else ""
+    return os.path.join(OUT_DIR, f"{gen}_seed{seed}_{size}_{dtype}{suffix}.json")
+
+
+def sample_positions(N, M, k):
+    """k seeded pixel positions (row, column), drawn without replacement."""
+    rng = np.random.default_rng(SAMPLE_SEED)
+    flat = rng.choice(N * M, size=k, replace=False)
+    return flat // M, flat % M
 
 
 def main(argv=None):
@@ -47,6 +67,9 @@ def main(argv=None):
     ap.add_argument("--maxit", type=int, default=100)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--workers", type=int, default=os.cpu_count())
+    ap.add_argument("--tag", default="")
+    ap.add_argument("--samples", type=int, default=0,
+                    help="store the returned U at this many seeded pixels")
     a = ap.parse_args(argv)
     default = {"c1": 256, "c2": 2048, "c3": 8192}[a.gen]
     n = a.size or default
@@ -56,7 +79,7 @@ def main(argv=None):
         X = X.astype(np.float32).astype(np.float64)
         w = None if w is None else w.astype(np.float32).astype(np.float64)
     os.makedirs(OUT_DIR, exist_ok=True)
-    path = reference_path(a.gen, a.seed, n, a.dtype)
+    path = reference_path(a.gen, a.seed, n, a.dtype, a.tag)
     rec = dict(gen=a.gen, seed=a.seed, N=n, M=n, input_dtype=a.dtype,
                iters=a.iters, tol=a.tol, maxit=a.maxit, eps=a.eps,
                workers=a.workers, host=platform.node(),
@@ -82,6 +105,12 @@ def main(argv=None):
     rec["L1_final"] = final["L1"]
     rec["H_final"] = final["H"]
     rec["pcg_total"] = int(sum(h.get("iters", 0) for h in hist))
+    if a.samples > 0:
+        i, j = sample_positions(n, n, a.samples)
+        rec["samples"] = dict(seed=SAMPLE_SEED, i=i.tolist(), j=j.tolist(),
+                              U=[float(v) for v in U[i, j]])
+        rec["U_norm2"] = float(np.sqrt(np.sum(U * U)))
+        rec["U_maxabs"] = float(np.max(np.abs(U)))
     rec["complete"] = True
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)

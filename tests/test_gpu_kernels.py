@@ -7,8 +7,11 @@ Tolerances (derived from the arithmetic, per precision of the plan):
   rounded operations, the FP32 plan then rounds to nearest.
 * weights / operator: element-wise bound 8 u sum_e Omega_e (|p_i| + |p_j|)
   (u the unit roundoff of the vector type; each output sums four terms).
-* preconditioner: norm-wise relative error; FP64 1e-11, FP32 2e-5, BF16
-  3e-2 (operands rounded to 8 mantissa bits in four chained products).
+* preconditioner: element-wise, |z_gpu - z| <= 8 sigma_ij with sigma_ij
+  from the probabilistic rounding model of each form (tests/precond_bound.py:
+  the roundings of each stage propagated through the rest of the map), and
+  norm-wise relative error beside it: FP64 1e-11, FP32 2e-5, BF16 3e-2
+  (operands rounded to 8 mantissa bits in four chained products).
 """
 import numpy as np
 import pytest
@@ -16,6 +19,7 @@ import torch
 
 import synth
 import paper_2401_09961_amd as pkg
+import precond_bound as PB
 from oracle import reduced as R
 
 pytestmark = pytest.mark.gpu
@@ -34,6 +38,18 @@ def npdt(prec):
 def internal(plan, A, dtype=None):
     t = torch.from_numpy(np.ascontiguousarray(A)).cuda()
     return plan.to_internal(t, dtype=dtype)
+
+
+def assert_elementwise(zg, r, form, prec):
+    """Every element of z within 8 sigma of the oracle's FP64 z (Section 3.3
+    eigendecomposition solve, Appendix B zero mode), sigma from the rounding
+    model of the plan's form and precision."""
+    S = PB.stages(np.asarray(r, np.float64))
+    sig = PB.plan_sigma(S, form, prec)
+    ok, worst, idx = PB.check(zg, S, sig)
+    print(f"  element-wise {form} {prec} {S['z'].shape}: worst |dz|/sigma {worst:.3f} at {idx}, "
+          f"8 sigma / max|z| = {PB.KAPPA * sig.max() / np.abs(S['z']).max():.2e}")
+    assert ok, (worst, idx)
 
 
 def edge_v(plan, Ev, dtype=None):
@@ -161,6 +177,7 @@ def test_precond_matches_dct_oracle(prec, shape):
     rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
     print(f"precond {prec} {shape}: rel err {rel:.3e}")
     assert rel <= PRECOND_RTOL[prec]
+    assert_elementwise(zg[:N, :M], r, "dense", prec)
     assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
     ref = float(np.sum(r.astype(np.float64) * z_o))
     assert abs(rz.item() - ref) <= 2 * PRECOND_RTOL[prec] * abs(ref)
@@ -181,6 +198,7 @@ def test_precond_big_tiles(p16, shape):
     rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
     print(f"precond {p16} {shape}: rel err {rel:.3e}")
     assert rel <= PRECOND_RTOL["bf16"]
+    assert_elementwise(zg[:N, :M], r, "dense", p16)
     assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
     plan.close()
 
@@ -206,6 +224,7 @@ def test_precond_folded_matches_dct_oracle(fprec, shape):
     rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
     print(f"precond folded {fprec} {shape}: rel err {rel:.3e}")
     assert rel <= PRECOND_RTOL["bf16" if fprec == "f16" else fprec]
+    assert_elementwise(zg[:N, :M], r, "folded", fprec)
     assert np.abs(zg[N:, :]).max(initial=0) == 0 and np.abs(zg[:, M:]).max(initial=0) == 0
     ref = float(np.sum(r.astype(np.float64) * z_o))
     assert abs(rz.item() - ref) <= 2 * PRECOND_RTOL["bf16" if fprec == "f16" else fprec] * abs(ref)
@@ -253,6 +272,7 @@ def test_precond_fast_matches_dct_oracle(fprec, shape):
     rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
     print(f"precond fast {fprec} {shape}: rel err {rel:.3e}")
     assert rel <= FAST_RTOL[fprec]
+    assert_elementwise(zg[:N, :M], r, "fast", fprec)
     ref = float(np.sum(r.astype(np.float64) * z_o))
     assert abs(rz.item() - ref) <= 2 * FAST_RTOL[fprec] * abs(ref)
     plan.close()

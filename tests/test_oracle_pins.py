@@ -415,6 +415,52 @@ def test_theorem2_smoothing_bound():
     assert h0 <= PF.h_delta(U, Vv, Vh, Wv * 1.1, Wh * 0.9, Gv, Gh, Cv, Ch, tau, 0.1)
 
 
+def test_theorem2_gap_is_attained_at_zero_slack():
+    """Both sides of Theorem 2 are tight: at V = 0 every smoothed term is
+    sqrt(0 + delta^2) = delta, so F_delta - F equals delta times the number
+    of edges (counted here as the rows of the dense D of Section 2), and for
+    slacks far larger than delta / C the gap vanishes.  An over- or
+    under-count of the edges in the oracle's bound fails the first check."""
+    rng = np.random.default_rng(11)
+    tau = 1e-2
+    for (N, M) in ((7, 5), (4, 9), (2, 2)):
+        n_edges = D_dense(N, M).shape[0]
+        assert n_edges == (N - 1) * M + N * (M - 1)
+        U = rng.standard_normal((N, M))
+        Gv, Gh = rng.uniform(-PI, PI, (N - 1, M)), rng.uniform(-PI, PI, (N, M - 1))
+        Cv, Ch = rng.uniform(0.1, 2, (N - 1, M)), rng.uniform(0.1, 2, (N, M - 1))
+        Z0v, Z0h = np.zeros((N - 1, M)), np.zeros((N, M - 1))
+        for delta in (1e-6, 1e-2, 0.5):
+            F = PF.f_delta(U, Z0v, Z0h, Gv, Gh, Cv, Ch, tau, 0.0)
+            Fd = PF.f_delta(U, Z0v, Z0h, Gv, Gh, Cv, Ch, tau, delta)
+            assert abs((Fd - F) - delta * n_edges) <= 1e-12 * max(Fd, 1.0)
+            assert PF.smoothing_gap_bound(N, M, delta) == pytest.approx(delta * n_edges, rel=1e-15)
+        big = 1e6
+        Vv, Vh = np.full((N - 1, M), big), np.full((N, M - 1), -big)
+        delta = 1e-3
+        gap = (PF.f_delta(U, Vv, Vh, Gv, Gh, Cv, Ch, tau, delta)
+               - PF.f_delta(U, Vv, Vh, Gv, Gh, Cv, Ch, tau, 0.0))
+        # sqrt(C^2 V^2 + d^2) - C|V| = d^2 / (2 C |V|) + O(d^4): far below d
+        assert 0.0 <= gap <= delta * n_edges * 1e-6
+
+
+def test_theorem3_L_equals_the_printed_value():
+    """L = 12 / tau + C_max^2 / delta at the paper's tau and delta
+    (Section 4.4) and unit weights, against the stored constant 1 001 200;
+    C_max enters squared and only through the largest weight."""
+    with open(os.path.join(GOLDEN, "paper_parameters.json")) as fh:
+        g = json.load(fh)
+    tau, delta = g["tau"], g["delta"]
+    ones_v, ones_h = np.ones((5, 6)), np.ones((6, 5))
+    assert PF.lipschitz_L(ones_v, ones_h, tau, delta) == pytest.approx(
+        g["theorem3_L_unit_weights"], rel=1e-15)
+    Cv = np.full((5, 6), 0.5)
+    Cv[2, 3] = 2.0
+    assert PF.lipschitz_L(Cv, ones_h, tau, delta) == pytest.approx(1200.0 + 4e6, rel=1e-15)
+    assert PF.lipschitz_L(0.5 * ones_v, 0.5 * ones_h, tau, delta) == pytest.approx(
+        1200.0 + 0.25e6, rel=1e-15)
+
+
 def test_paper_form_alg1_monotone_f_delta():
     f = synth.field_c2(2, 16, 14)
     U, Vv, Vh, hist = PF.irls(f.X, w=f.w, tau=1e-2, delta=1e-6, iters=10, tol=1e-12, maxit=400)
