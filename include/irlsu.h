@@ -59,11 +59,20 @@ typedef enum irlsu_status {
   IRLSU_ERR_WORKSPACE = -9     /* workspace missing or smaller than required */
 } irlsu_status;
 
+/* Precision of a plan.  The vectors, scalars and FP64 reductions are fixed
+ * by the precision alone; where the preconditioner's arithmetic runs depends
+ * on the plan's form (IRLSU_PLAN_*, below):
+ *   fast form (the default for power-of-two sides): FP32 VALU transforms
+ *     (FP64 for F64 plans), the two stored intermediates in the operand
+ *     type (FP16 / BF16 for the mixed plans, FP32 / FP64 otherwise);
+ *   dense and folded forms (every other side, or forced through
+ *     irlsu_plan_create_ex): MFMA products with the cosine bases in the
+ *     operand type, FP32 accumulation (FP64 for F64 plans). */
 typedef enum irlsu_precision {
-  IRLSU_F64 = 0,        /* FP64 vectors, FP64 MFMA preconditioner */
-  IRLSU_F32 = 1,        /* FP32 vectors, FP32 MFMA preconditioner */
-  IRLSU_MIXED_BF16 = 2, /* FP32 vectors, BF16 MFMA preconditioner (FP32 accumulate) */
-  IRLSU_MIXED_F16 = 3   /* FP32 vectors, FP16 MFMA preconditioner (FP32 accumulate) */
+  IRLSU_F64 = 0,        /* FP64 vectors; FP64 preconditioner */
+  IRLSU_F32 = 1,        /* FP32 vectors; FP32 preconditioner */
+  IRLSU_MIXED_BF16 = 2, /* FP32 vectors; BF16 operands / intermediates, FP32 arithmetic */
+  IRLSU_MIXED_F16 = 3   /* FP32 vectors; FP16 operands / intermediates (scaled), FP32 arithmetic */
 } irlsu_precision;
 
 typedef struct irlsu_plan irlsu_plan;
@@ -161,24 +170,39 @@ enum {
                             powers of two in [128, 16384] (else ERR_SHAPE) */
 };
 
+/* Testing hook for the ERR_OOM path (for callers that test their own error
+ * handling): with nth >= 0, the nth (from 0) device or pinned host
+ * allocation made by the following plan and batch creations fails as if
+ * the device were out of memory, after which the hook disarms itself; a
+ * negative nth disarms it.  Process-wide and not thread-safe. */
+void irlsu_test_fail_alloc(int32_t nth);
+
 /* Human-readable name of a status code (static storage). */
 const char* irlsu_status_string(irlsu_status st);
 
 /* Fill *p with the defaults for precision prec. */
 irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec);
 
-/* Create a plan for N x M images.  Allocates and fills the orthonormal DCT-II
- * bases P_N, P_M and the Laplacian eigenvalues 2 - 2 cos(pi k / n) on the
- * current HIP device (Section 3.3, eq:eigendecompositions: computed once,
- * reused by every PCG iteration).  Synchronises the stream before returning.
+/* Create a plan for N x M images (Section 3.3, eq:eigendecompositions: what
+ * the preconditioner needs is computed once and reused by every PCG
+ * iteration).  The form is chosen as IRLSU_PLAN_AUTO describes; on the
+ * current HIP device the plan allocates and fills
+ *   fast form: the FFT twiddle tables of each side (about 3n/2 complex
+ *     values per side, shared when N = M) and the Laplacian eigenvalues
+ *     2 - 2 cos(pi k / n) in FP64;
+ *   dense form: the orthonormal DCT-II bases P_N, P_M and their transposes
+ *     in the operand type, and the eigenvalues;
+ *   folded form: the even / odd half bases and the eigenvalues.
+ * Synchronises the stream before returning.
  * Sizes: 2 <= N, M <= 32768.
  * Errors: ERR_INVALID_ARG (out null), ERR_SHAPE, ERR_UNSUPPORTED, ERR_OOM,
  * ERR_HIP.  On error *out is NULL and nothing is leaked. */
 irlsu_status irlsu_plan_create(irlsu_plan** out, int64_t N, int64_t M,
                                irlsu_precision prec, void* stream);
 
-/* As irlsu_plan_create, choosing the form of the preconditioner products
- * (IRLSU_PLAN_AUTO / _DENSE / _FOLDED); both forms compute the same map. */
+/* As irlsu_plan_create, choosing the form of the preconditioner
+ * (IRLSU_PLAN_AUTO / _DENSE / _FOLDED / _FAST); every form computes the
+ * same map. */
 irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M,
                                   irlsu_precision prec, int32_t form, void* stream);
 
@@ -338,12 +362,38 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
                             void* workspace, size_t workspace_bytes, void* stream);
 
 /* Preconditioner z = L^+ r (Section 3.3, Appendix B): orthonormal DCT-II of
- * both axes as dense products on MFMA, division by lambda_k + mu_l, mode
- * (0,0) set to zero, DCT-III back.  r, z device, internal layout, may not
- * alias.  rz (device double, nullable) receives sum r z in FP64.  For mixed
- * plans the products run in BF16 / FP16 with FP32 accumulation. */
+ * both axes, division by lambda_k + mu_l, mode (0,0) set to zero, DCT-III
+ * back.  How the transforms run is the plan's form: fast cosine transforms
+ * on the VALU in FP32 (FP64 for F64 plans) with the intermediates stored in
+ * the operand type (fast form), or products with the cosine bases on MFMA
+ * with FP32 accumulation (FP64 for F64 plans; dense and folded forms).
+ * r, z device, internal layout, may not alias.  rz (device double,
+ * nullable) receives sum r z in FP64. */
 irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, double* rz,
                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* PCG solve (Algorithm 2) of D^T Omega D x = b for given weights: the
+ * solve inside each IRLS iteration, on its own.  The preconditioner is the
+ * plan's L^+ (Section 3.3), the stopping rule ||r|| <= pcg_rtol ||b|| on the
+ * recursive residual, at most pcg_max iterations, the true residual
+ * recomputed every true_res_every iterations (params as irlsu_unwrap; NULL:
+ * defaults).  b is projected on the range of the operator (its mean over
+ * the N x M pixels removed), since D^T Omega D annihilates constants.
+ *   Ov, Oh, b  device, internal layout, plan element type (copied into the
+ *              workspace; weights of missing edges and padding zero).
+ *   x          device, Np x ld doubles (FP64 for every precision: the
+ *              iterate is FP64, each solve accumulates its correction in
+ *              the vector type and adds it once): warm start in, solution
+ *              out (not mean-adjusted); padding must be zero.
+ *   iters, relres  host, nullable: iterations performed and the final
+ *              ||r|| / ||b||.
+ * Synchronises the stream (polls the device convergence flag).  Returns
+ * OK, NOT_CONVERGED (pcg_max reached), ERR_BREAKDOWN (p^T A p <= 0 or
+ * rho < 0, e.g. for weights that are not positive), ERR_INVALID_ARG,
+ * ERR_WORKSPACE, ERR_HIP. */
+irlsu_status irlsu_pcg(irlsu_plan* plan, const void* Ov, const void* Oh, const void* b,
+                       double* x, const irlsu_params* params, int32_t* iters, double* relres,
+                       void* workspace, size_t workspace_bytes, void* stream);
 
 /* The paper's augmented form (Algorithm 1 in (U, V^v, V^h) with tau and
  * delta): closed-form weights W = sqrt(C^2 V^2 + delta^2), then Algorithm 2
