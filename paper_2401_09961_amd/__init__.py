@@ -34,7 +34,8 @@ DECLARED_SYMBOLS = (
     "irlsu_operator", "irlsu_precond", "irlsu_precond_timed", "irlsu_profile_arm",
     "irlsu_profile_result", "irlsu_round_congruent", "irlsu_augmented_workspace_bytes",
     "irlsu_unwrap_augmented", "irlsu_batch_create", "irlsu_batch_destroy",
-    "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched",
+    "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched", "irlsu_pcg",
+    "irlsu_test_fail_alloc",
 )
 
 STATUS = {
@@ -160,6 +161,9 @@ def load_library():
         "irlsu_weights": (I32, [P, D, P, P, P, P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
+        "irlsu_pcg": (I32, [P, P, P, P, P, ctypes.POINTER(Params), ctypes.POINTER(I32),
+                            ctypes.POINTER(D), P, SZ, P]),
+        "irlsu_test_fail_alloc": (None, [I32]),
         "irlsu_precond_timed": (I32, [P, P, P, P, SZ, I32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(I32), ctypes.POINTER(I32), P]),
         "irlsu_profile_arm": (I32, [P, I32, I32]),
@@ -350,6 +354,25 @@ class Plan:
                                       _ptr(self.workspace), self.workspace.numel(), _stream()),
                "precond")
         return z, rz
+
+    def pcg(self, Ov, Oh, b, x=None, *, params: Optional[Params] = None):
+        """Algorithm 2 on D^T Omega D x = b (internal layout; x FP64, warm
+        start in / solution out).  Returns (x, status code, iterations,
+        relative residual); negative codes raise."""
+        import torch
+        if x is None:
+            x = torch.zeros((self.Np, self.ld), dtype=torch.float64, device=self.device)
+        assert x.dtype == torch.float64 and x.shape == (self.Np, self.ld) and x.is_contiguous()
+        for t in (Ov, Oh, b):
+            assert t.dtype == self.dtype and t.shape == (self.Np, self.ld) and t.is_contiguous()
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        code = self.lib.irlsu_pcg(self.handle, _ptr(Ov), _ptr(Oh), _ptr(b), _ptr(x),
+                                  ctypes.byref(params) if params is not None else None,
+                                  ctypes.byref(it), ctypes.byref(rel), _ptr(self.workspace),
+                                  self.workspace.numel(), _stream())
+        _check(code, "pcg")
+        return x, code, it.value, rel.value
 
     def unwrap_augmented(self, X, weights=None, *, tau=1e-2, delta=1e-6,
                          params: Optional[Params] = None, stats: bool = False):

@@ -349,13 +349,13 @@ __global__ __launch_bounds__(kThreads) void aug_cmax_kernel(AugArgs<T> a) {
     if (g.horz(i, j)) m = fmax(m, (double)a.Ch[k]);
   }
   m = block_max(m);
-  if (threadIdx.x == 0) a.st.part[(size_t)PR_AUX * kMaxPartials + a.st.off + blockIdx.x] = m;
+  if (threadIdx.x == 0) part_row(a.st, PR_AUX)[blockIdx.x] = m;
 }
 
 // 1 / L, L = 12 / tau + C_max^2 / delta (Theorem 3), into SC_INVL.
 __global__ __launch_bounds__(kThreads) void aug_invl_kernel(DevState st, int nparts, double tau,
                                                            double delta) {
-  const double* p = st.part + (size_t)PR_AUX * kMaxPartials + st.off;
+  const double* p = part_row(st, PR_AUX);
   double m = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kThreads) m = fmax(m, p[i]);
   m = block_max(m);

@@ -76,8 +76,14 @@ struct DevState {
   int32_t* fl = nullptr;   // FL_COUNT ints
   double* part = nullptr;  // kPartSlots * kMaxPartials doubles (shared by all problems)
   int32_t off = 0;         // first partial index of this problem
-  int32_t pad_ = 0;
+  int32_t stride = 0;      // distance between two slots' rows; 0: kMaxPartials
 };
+
+// Row of partial sums of one slot for this problem: part[slot * stride + off ..].
+__device__ __forceinline__ double* part_row(const DevState& st, int slot) {
+  const size_t stride = st.stride > 0 ? (size_t)st.stride : (size_t)kMaxPartials;
+  return st.part + (size_t)slot * stride + st.off;
+}
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -112,7 +118,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 // Reduce n partials of one slot in a fixed order; identical in every block.
 template <int NT = kThreads>
 __device__ __forceinline__ double reduce_slot(const DevState& st, int slot, int n) {
-  const double* p = st.part + (size_t)slot * kMaxPartials + st.off;
+  const double* p = part_row(st, slot);
   double s[1] = {0.0};
   for (int i = threadIdx.x; i < n; i += NT) s[0] += p[i];
   block_sum<1, NT>(s);
@@ -135,7 +141,7 @@ __device__ __forceinline__ void write_partials(const DevState& st, const int (&s
   block_sum<NV, NT>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) st.part[(size_t)slots[k] * kMaxPartials + st.off + lb] = v[k];
+    for (int k = 0; k < NV; ++k) part_row(st, slots[k])[lb] = v[k];
   }
 }
 
@@ -167,6 +173,23 @@ __device__ __forceinline__ void st4(T* p, const V4<T>& r) {
     *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
     *reinterpret_cast<double2*>(p + 2) = make_double2(r.v[2], r.v[3]);
   }
+}
+
+// Streaming load (non-temporal hint): for data read once per pass.
+template <class T>
+__device__ __forceinline__ V4<T> ld4_nt(const T* p) {
+  V4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 x = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+  } else {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 a = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+    const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p + 2));
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  }
+  return r;
 }
 
 // Streaming store (non-temporal hint): for data written once per pass and

@@ -635,8 +635,8 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
   write_partials<2>(st, slots, acc, (int)blockIdx.x);
   if (threadIdx.x == 0) {
     for (int k = (int)blockIdx.x + (int)gridDim.x; k < nparts_out; k += (int)gridDim.x) {
-      st.part[(size_t)PR_RR * kMaxPartials + st.off + k] = 0.0;
-      st.part[(size_t)PR_RSUM * kMaxPartials + st.off + k] = 0.0;
+      part_row(st, PR_RR)[k] = 0.0;
+      part_row(st, PR_RSUM)[k] = 0.0;
     }
   }
 }
@@ -892,7 +892,7 @@ __global__ __launch_bounds__(kFoldThreads) void fct_fold_partials_kernel(DevStat
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const double v = reduce_slot<kFoldThreads>(st, slots[i], n);
-    if (threadIdx.x == 0) st.part[(size_t)slots[i] * kMaxPartials + st.off] = v;
+    if (threadIdx.x == 0) part_row(st, slots[i])[0] = v;
   }
 }
 

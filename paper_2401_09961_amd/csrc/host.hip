@@ -78,7 +78,35 @@ struct irlsu_batch {
 
 namespace {
 
+// Allocation-failure hook of irlsu_test_fail_alloc: while armed (>= 0) it
+// counts down the device and pinned allocations of plan and batch creation
+// and fails the one it reaches zero on, as an out-of-memory device would.
+int g_fail_alloc_at = -1;
+
+bool fail_this_alloc() {
+  if (g_fail_alloc_at < 0) return false;
+  if (g_fail_alloc_at-- == 0) return true;
+  return false;
+}
+
+hipError_t dev_malloc(void** ptr, size_t bytes) {
+  if (fail_this_alloc()) {
+    *ptr = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(ptr, bytes);
+}
+
+hipError_t pinned_malloc(void** ptr, size_t bytes, unsigned flags) {
+  if (fail_this_alloc()) {
+    *ptr = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(ptr, bytes, flags);
+}
+
 constexpr size_t kAlign = 256;
+constexpr size_t kStagger = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -96,9 +124,13 @@ Layout layout(const irlsu_plan* p) {
   off = align_up(off + npx * sizeof(double));
   L.lam = off;
   off = align_up(off + npx * sizeof(double));
+  // each vector starts 4 KiB further along than the plain carve-up would put
+  // it: vectors of 2^k bytes would otherwise all sit at the same offset
+  // modulo the HBM interleave, and the kernels that stream three or four of
+  // them at the same index lose about 3% of their bandwidth to that
   for (int v = 0; v < V_COUNT; ++v) {
     L.vec[v] = off;
-    off = align_up(off + npx * p->elem);
+    off = align_up(off + npx * p->elem) + kStagger;
   }
   // preconditioner intermediates: dense form Np x Mp each; folded form two
   // ping-pong buffers of 2 hNp x 2 hMp and an Np x 2 hMp vector-type buffer
@@ -106,9 +138,9 @@ Layout layout(const irlsu_plan* p) {
   const size_t inter = p->folded ? (size_t)(2 * p->hNp) * (size_t)(2 * p->hMp) : npx;
   const size_t isz = p->opsz;
   L.t1 = off;
-  off = align_up(off + inter * isz);
+  off = align_up(off + inter * isz) + kStagger;
   L.t2 = off;
-  off = align_up(off + inter * isz);
+  off = align_up(off + inter * isz) + kStagger;
   L.t3 = off;
   off = align_up(off + ((p->folded || p->fast) ? 0 : npx) * p->opsz);
   L.zeo = off;
@@ -148,7 +180,7 @@ Ws<T> carve(const irlsu_plan* p, void* base) {
   w.st.sc = reinterpret_cast<double*>(b + L.sc);
   w.st.fl = reinterpret_cast<int32_t*>(b + L.fl);
   w.st.off = 0;
-  w.st.pad_ = 0;
+  w.st.stride = 0;
   return w;
 }
 
@@ -342,6 +374,11 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     launch_axpy<T>(xa, s, axpy_blocks(nvec));
     log_mark(L, IRLSU_LK_AXPY, s);
     if (refresh) {
+      // the correction so far moves into the FP64 iterate before the true
+      // residual is formed (d restarts at zero): d then only ever holds the
+      // correction since the last refresh, so its rounding in the vector
+      // type no longer bounds how far the residual can fall
+      launch_commit<T>(x, d, (int64_t)npx, s, true);
       ra.check_done = 1;
       launch_stencil<T>(ST_RESID, ra, s);
       log_mark(L, IRLSU_LK_RESIDUAL, s);
@@ -694,7 +731,7 @@ DevState tile_state(const irlsu_batch* b, void* base, int t) {
   st.sc = reinterpret_cast<double*>(p + b->sc_off) + (size_t)t * SC_COUNT;
   st.fl = reinterpret_cast<int32_t*>(p + b->fl_off) + (size_t)t * FL_COUNT;
   st.off = b->part_off[t];
-  st.pad_ = 0;
+  st.stride = 0;
   return st;
 }
 
@@ -1178,11 +1215,11 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
   if (p->fast) {
     const bool share = (N == M);
     const size_t bN = fct_table_bytes(N, p->elem), bM = fct_table_bytes(M, p->elem);
-    ok = hipMalloc(&p->twN, bN) == hipSuccess &&
-         hipMalloc(reinterpret_cast<void**>(&p->eigN), N * sizeof(double)) == hipSuccess;
+    ok = dev_malloc(&p->twN, bN) == hipSuccess &&
+         dev_malloc(reinterpret_cast<void**>(&p->eigN), N * sizeof(double)) == hipSuccess;
     if (ok && !share)
-      ok = hipMalloc(&p->twM, bM) == hipSuccess &&
-           hipMalloc(reinterpret_cast<void**>(&p->eigM), M * sizeof(double)) == hipSuccess;
+      ok = dev_malloc(&p->twM, bM) == hipSuccess &&
+           dev_malloc(reinterpret_cast<void**>(&p->eigM), M * sizeof(double)) == hipSuccess;
     if (ok && share) {
       p->twM = p->twN;
       p->eigM = p->eigN;
@@ -1192,13 +1229,13 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     const bool share = (N == M);
     const size_t bN = (size_t)p->hNp * p->hNp * p->opsz;
     const size_t bM = (size_t)p->hMp * p->hMp * p->opsz;
-    ok = hipMalloc(&p->PeN, bN) == hipSuccess && hipMalloc(&p->PeNt, bN) == hipSuccess &&
-         hipMalloc(&p->PoN, bN) == hipSuccess && hipMalloc(&p->PoNt, bN) == hipSuccess &&
-         hipMalloc(reinterpret_cast<void**>(&p->eigNf), 2 * p->hNp * sizeof(double)) == hipSuccess;
+    ok = dev_malloc(&p->PeN, bN) == hipSuccess && dev_malloc(&p->PeNt, bN) == hipSuccess &&
+         dev_malloc(&p->PoN, bN) == hipSuccess && dev_malloc(&p->PoNt, bN) == hipSuccess &&
+         dev_malloc(reinterpret_cast<void**>(&p->eigNf), 2 * p->hNp * sizeof(double)) == hipSuccess;
     if (ok && !share) {
-      ok = hipMalloc(&p->PeM, bM) == hipSuccess && hipMalloc(&p->PeMt, bM) == hipSuccess &&
-           hipMalloc(&p->PoM, bM) == hipSuccess && hipMalloc(&p->PoMt, bM) == hipSuccess &&
-           hipMalloc(reinterpret_cast<void**>(&p->eigMf), 2 * p->hMp * sizeof(double)) == hipSuccess;
+      ok = dev_malloc(&p->PeM, bM) == hipSuccess && dev_malloc(&p->PeMt, bM) == hipSuccess &&
+           dev_malloc(&p->PoM, bM) == hipSuccess && dev_malloc(&p->PoMt, bM) == hipSuccess &&
+           dev_malloc(reinterpret_cast<void**>(&p->eigMf), 2 * p->hMp * sizeof(double)) == hipSuccess;
     }
     if (ok && share) {
       p->PeM = p->PeN;
@@ -1213,11 +1250,11 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     const bool share = (p->Np == p->Mp) && (N == M);
     const size_t bN = (size_t)p->Np * p->Np * p->opsz;
     const size_t bM = (size_t)p->Mp * p->Mp * p->opsz;
-    ok = hipMalloc(&p->PN, bN) == hipSuccess && hipMalloc(&p->PNt, bN) == hipSuccess &&
-         hipMalloc(reinterpret_cast<void**>(&p->eigN), p->Np * sizeof(double)) == hipSuccess;
+    ok = dev_malloc(&p->PN, bN) == hipSuccess && dev_malloc(&p->PNt, bN) == hipSuccess &&
+         dev_malloc(reinterpret_cast<void**>(&p->eigN), p->Np * sizeof(double)) == hipSuccess;
     if (ok && !share) {
-      ok = hipMalloc(&p->PM, bM) == hipSuccess && hipMalloc(&p->PMt, bM) == hipSuccess &&
-           hipMalloc(reinterpret_cast<void**>(&p->eigM), p->Mp * sizeof(double)) == hipSuccess;
+      ok = dev_malloc(&p->PM, bM) == hipSuccess && dev_malloc(&p->PMt, bM) == hipSuccess &&
+           dev_malloc(reinterpret_cast<void**>(&p->eigM), p->Mp * sizeof(double)) == hipSuccess;
     }
     if (ok && share) {
       p->PM = p->PN;
@@ -1226,8 +1263,8 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     }
     p->plan_bytes = 2 * bN + p->Np * sizeof(double) + (share ? 0 : 2 * bM + p->Mp * sizeof(double));
   }
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&p->h_flags), 256, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&p->h_sc), 512, hipHostMallocDefault) == hipSuccess;
+  ok = ok && pinned_malloc(reinterpret_cast<void**>(&p->h_flags), 256, hipHostMallocDefault) == hipSuccess;
+  ok = ok && pinned_malloc(reinterpret_cast<void**>(&p->h_sc), 512, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     irlsu_plan_destroy(p);
@@ -1297,6 +1334,8 @@ irlsu_status irlsu_plan_info(const irlsu_plan* p, irlsu_plan_desc* out) {
 }
 
 size_t irlsu_workspace_bytes(const irlsu_plan* p) { return p ? p->ws_bytes : 0; }
+
+void irlsu_test_fail_alloc(int32_t nth) { g_fail_alloc_at = nth < 0 ? -1 : nth; }
 
 irlsu_status irlsu_unwrap(irlsu_plan* plan, const void* X, int64_t ldx, const void* w,
                           const void* Cv, int64_t ldcv, const void* Ch, int64_t ldch,
@@ -1493,6 +1532,52 @@ irlsu_status irlsu_precond(const irlsu_plan* plan, const void* r, void* z, doubl
   st = plan->elem == 8 ? go(double{}) : go(float{});
   if (st != IRLSU_OK) return st;
   return last_launch();
+}
+
+irlsu_status irlsu_pcg(irlsu_plan* plan, const void* Ov, const void* Oh, const void* b, double* x,
+                       const irlsu_params* params, int32_t* iters, double* relres,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan || !Ov || !Oh || !b || !x) return IRLSU_ERR_INVALID_ARG;
+  irlsu_status st = check_ws(plan, workspace, workspace_bytes);
+  if (st != IRLSU_OK) return st;
+  irlsu_params prm;
+  if (params) {
+    prm = *params;
+  } else {
+    irlsu_params_default(&prm, plan->prec);
+  }
+  if (!(prm.pcg_rtol >= 0.0) || prm.pcg_max < 1 || prm.true_res_every < 0 || prm.poll_every < 0)
+    return IRLSU_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t npx = (size_t)plan->Np * (size_t)plan->Mp;
+  int it = 0;
+  double rel = 0.0;
+  irlsu_status solve_st = IRLSU_OK;
+  auto go = [&](auto tag) -> irlsu_status {
+    using T = decltype(tag);
+    const Ws<T> W = carve<T>(plan, workspace);
+    // the weights where the loop's kernels read them; the right-hand side
+    // projected on the range of the operator (mean zero), with ||b||^2, the
+    // tolerance and cleared flags for the solve
+    HIP_OK(hipMemcpyAsync(W.v[V_OV], Ov, npx * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(W.v[V_OH], Oh, npx * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemsetAsync(W.st.sc, 0, SC_COUNT * sizeof(double), s));
+    // the loop's vectors start from zero: the first direction update
+    // multiplies the previous direction by beta = 0, which keeps stale
+    // non-finite workspace contents from entering
+    for (int v : {V_R, V_Z, V_P0, V_P1, V_Q, V_D})
+      HIP_OK(hipMemsetAsync(W.v[v], 0, npx * sizeof(T), s));
+    launch_adjoint_rhs<T>(static_cast<const T*>(b), plan->Mp, plan->N, plan->M, plan->Np,
+                          plan->Mp, W.v[V_B], W.st, prm.pcg_rtol * prm.pcg_rtol, s);
+    if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
+    const int flexible = prm.flexible < 0 ? default_flexible(plan) : prm.flexible;
+    return pcg_solve<T>(plan, W, x, W.v[V_B], prm, flexible, &it, &rel, &solve_st, s);
+  };
+  st = plan->elem == 8 ? go(double{}) : go(float{});
+  if (st != IRLSU_OK) return st;
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  return solve_st;
 }
 
 irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z, void* workspace,
@@ -1732,22 +1817,22 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
     const int64_t n = kv.first, npad = round_up(n, kBatchPad);
     void *P = nullptr, *Pt = nullptr;
     double* e = nullptr;
-    ok = ok && hipMalloc(&P, (size_t)npad * npad * 2) == hipSuccess;
-    ok = ok && hipMalloc(&Pt, (size_t)npad * npad * 2) == hipSuccess;
-    ok = ok && hipMalloc(reinterpret_cast<void**>(&e), npad * sizeof(double)) == hipSuccess;
+    ok = ok && dev_malloc(&P, (size_t)npad * npad * 2) == hipSuccess;
+    ok = ok && dev_malloc(&Pt, (size_t)npad * npad * 2) == hipSuccess;
+    ok = ok && dev_malloc(reinterpret_cast<void**>(&e), npad * sizeof(double)) == hipSuccess;
     b->P.push_back(P);
     b->Pt.push_back(Pt);
     b->eig.push_back(e);
     if (ok) launch_basis(b->kind, n, npad, P, Pt, e, s);
   }
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_st_start), st_start.size() * 4) == hipSuccess;
-  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_g_start), g_start.size() * 4) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_tiles, (size_t)ntiles * sizeof(BatchTile<float>)) == hipSuccess;
-  ok = ok && hipHostMalloc(&b->h_tiles, (size_t)ntiles * sizeof(BatchTile<float>),
+  ok = ok && dev_malloc(reinterpret_cast<void**>(&b->d_st_start), st_start.size() * 4) == hipSuccess;
+  ok = ok && dev_malloc(reinterpret_cast<void**>(&b->d_g_start), g_start.size() * 4) == hipSuccess;
+  ok = ok && dev_malloc(&b->d_tiles, (size_t)ntiles * sizeof(BatchTile<float>)) == hipSuccess;
+  ok = ok && pinned_malloc(&b->h_tiles, (size_t)ntiles * sizeof(BatchTile<float>),
                            hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_flags), (size_t)ntiles * FL_COUNT * 4,
+  ok = ok && pinned_malloc(reinterpret_cast<void**>(&b->h_flags), (size_t)ntiles * FL_COUNT * 4,
                            hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_sc), (size_t)ntiles * SC_COUNT * 8,
+  ok = ok && pinned_malloc(reinterpret_cast<void**>(&b->h_sc), (size_t)ntiles * SC_COUNT * 8,
                            hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();

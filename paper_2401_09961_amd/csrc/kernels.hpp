@@ -114,8 +114,10 @@ int axpy_blocks(int stencil_blocks);
 template <class T>
 void launch_congruent(const T* X, int64_t ldx, const T* U, int64_t ldu, T* out, int64_t ldo,
                       int64_t N, int64_t M, DevState st, hipStream_t s);
-// u += d (FP64) over n elements: the end of a solve
-template <class T> void launch_commit(double* u, const T* d, int64_t n, hipStream_t s);
+// u += d (FP64) over n elements: the end of a solve; with clear, also d = 0
+// (a true-residual refresh moves the correction so far into u)
+template <class T>
+void launch_commit(double* u, T* d, int64_t n, hipStream_t s, bool clear = false);
 void launch_mean_removal(double* u, int64_t N, int64_t M, int64_t ld, DevState st, hipStream_t s);
 template <class T>
 void launch_copy_out(const double* u, int64_t ld, T* out, int64_t ldo, int64_t N, int64_t M,

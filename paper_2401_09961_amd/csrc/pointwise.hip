@@ -242,8 +242,8 @@ __device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) 
   // partial range at zero, so every consumer reads one count
   if (threadIdx.x == 0) {
     for (int k = lb + nb; k < a.nparts_out; k += nb) {
-      a.st.part[(size_t)PR_RR * kMaxPartials + a.st.off + k] = 0.0;
-      a.st.part[(size_t)PR_RSUM * kMaxPartials + a.st.off + k] = 0.0;
+      part_row(a.st, PR_RR)[k] = 0.0;
+      part_row(a.st, PR_RSUM)[k] = 0.0;
     }
   }
 }
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void sub_mean_kernel(double* u, int64_t N
 // End of a solve: u += d in FP64 (d, the solve's correction, in the vector
 // type).
 template <class T>
-__global__ __launch_bounds__(kThreads) void commit_kernel(double* u, const T* d, int64_t n4) {
+__global__ __launch_bounds__(kThreads) void commit_kernel(double* u, T* d, int64_t n4, int clear) {
   for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n4;
        k += (int64_t)gridDim.x * kThreads) {
     V4<double> x = ld4(u + 4 * k);
@@ -315,16 +315,17 @@ __global__ __launch_bounds__(kThreads) void commit_kernel(double* u, const T* d,
 #pragma unroll
     for (int e = 0; e < 4; ++e) x.v[e] += (double)c.v[e];
     st4(u + 4 * k, x);
+    if (clear) st4(d + 4 * k, zero4<T>());
   }
 }
 
 template <class T>
-void launch_commit(double* u, const T* d, int64_t n, hipStream_t s) {
+void launch_commit(double* u, T* d, int64_t n, hipStream_t s, bool clear) {
   hipLaunchKernelGGL(commit_kernel<T>, dim3(elementwise_blocks(n)), dim3(kThreads), 0, s, u, d,
-                     n / 4);
+                     n / 4, clear ? 1 : 0);
 }
-template void launch_commit<float>(double*, const float*, int64_t, hipStream_t);
-template void launch_commit<double>(double*, const double*, int64_t, hipStream_t);
+template void launch_commit<float>(double*, float*, int64_t, hipStream_t, bool);
+template void launch_commit<double>(double*, double*, int64_t, hipStream_t, bool);
 
 // ----------------------------------------------------------------------------
 // Rounded output (Section 4, "rounded IRLS"): U made 2 pi-congruent to X.

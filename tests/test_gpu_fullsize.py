@@ -27,6 +27,9 @@ pytestmark = pytest.mark.gpu
 N = M = 8192
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 REF = os.path.join(ROOT, "oracle", "reference", "c3_seed0_8192_float32.json")
+# one weight step from U = 0 and exactly 30 PCG iterations (no early stop),
+# with U at 10^4 seeded pixels (oracle/make_reference.py --tag onestep30)
+REF30 = os.path.join(ROOT, "oracle", "reference", "c3_seed0_8192_float32_onestep30.json")
 
 
 @pytest.fixture(scope="module")
@@ -136,17 +139,16 @@ def test_preconditioner_against_oracle_full_size(prec):
     assert abs(zn.mean()) <= 1e-6 * np.abs(zn).max()
 
 
-def test_fp64_first_iterates_match_oracle_reference(field, ref):
-    """Two IRLS iterations at full size in FP64 (fast form) against the
-    oracle's stored history.  Before any solve (k = 0: setup and weights)
-    the objectives agree to 1e-12.  After a solve the bar is 5e-3: each
-    solve stops at the 100-iteration cap with relative residual ~0.17, where
-    the CG iterate is not determined to more digits by FP64 arithmetic --
-    the oracle run twice on this field, with 6 and with 8 FFT threads (only
-    the DCT's summation order differs), gives L1 at k = 1 that differ by
-    1.6e-3; a 1e-15 relative perturbation of its preconditioner moves it by
-    2.5e-5.  A wrong operator, preconditioner or weight changes these
-    objectives at order one."""
+def test_fp64_capped_iterates_smoke(field, ref):
+    """Smoke check of two capped IRLS iterations at full size in FP64 (fast
+    form) against the oracle's stored history.  Before any solve (k = 0:
+    setup and weights) the objectives agree to 1e-12.  After a capped solve
+    only order-one agreement is asserted (5e-3): at the 100-iteration cap
+    the CG iterate is not determined to more digits by FP64 arithmetic (the
+    oracle run with 6 and with 8 FFT threads gives L1 at k = 1 that differ
+    by 1.6e-3).  The element-wise parity of a solve at this size is
+    test_one_weight_step_thirty_iterations, which stops at a fixed iteration
+    count well before that sensitivity sets in."""
     X, w = field
     plan = pkg.Plan(N, M, "f64")
     p = pkg.default_params("f64")
@@ -180,3 +182,53 @@ def test_mixed_fp16_reaches_reference_quality(field, ref):
     l1 = st["history"][st["irls_done"]]["L1"]
     print(f"mixed FP16: target at IRLS {st['irls_done']}, L1 {l1:.10g} (ref {L1_ref:.10g})")
     assert abs(l1 - L1_ref) <= 1e-3 * L1_ref
+
+
+# Bars of the one-step check: relative on L1 and H, and on the sampled U
+# relative to max |U|.  FP64: the GPU and the oracle run the same
+# arithmetic in different summation orders (the DCT's, the reductions'),
+# each rounding at 2^-53; 30 CG iterations amplify such differences by the
+# iteration's sensitivity, measured below 1e-11 on this field.  FP32:
+# vectors and transforms round at 2^-24.  FP16 storage of the
+# preconditioner's intermediates (2^-11) changes the preconditioner itself,
+# so its iterate is a different (equally valid) CG trajectory; the bar is
+# the mixed path's 1e-3 on the objectives.
+ONESTEP_BARS = {"f64": (1e-9, 1e-9), "f32": (1e-5, 1e-4), "f16": (1e-3, 1e-1)}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_one_weight_step_thirty_iterations(field, prec):
+    """From U = 0: one weight step (Section 3.1 closed-form weights) and
+    exactly 30 PCG iterations (Algorithm 2, no early stop: pcg_rtol = 0),
+    then mean removal, against the oracle's record of the same steps in
+    FP64: L1 and H of U^1, and U^1 itself at 10^4 seeded pixels."""
+    with open(REF30) as fh:
+        ref = json.load(fh)
+    assert ref["complete"] and ref["maxit"] == 30 and ref["tol"] == 0.0 and ref["iters"] == 1
+    X, w = field
+    plan = pkg.Plan(N, M, prec)
+    assert plan.form == "fast"
+    p = pkg.default_params(prec)
+    p.irls_iters, p.pcg_max, p.pcg_rtol, p.eps = 1, 30, 0.0, ref["eps"]
+    p.true_res_every = 0
+    dt = np.float64 if prec == "f64" else np.float32
+    U, st = plan.unwrap(torch.from_numpy(X.astype(dt)).cuda(), torch.from_numpy(w.astype(dt)).cuda(),
+                        params=p, stats=True)
+    torch.cuda.synchronize()
+    si = torch.from_numpy(np.asarray(ref["samples"]["i"])).cuda()
+    sj = torch.from_numpy(np.asarray(ref["samples"]["j"])).cuda()
+    Us = U[si, sj].double().cpu().numpy()
+    Umax = float(U.abs().max().item())
+    plan.close()
+    assert st["pcg_total"] == 30
+    Uo = np.asarray(ref["samples"]["U"])
+    dL1 = abs(st["L1_final"] - ref["L1_final"]) / ref["L1_final"]
+    dH = abs(st["H_final"] - ref["H_final"]) / ref["H_final"]
+    dU = float(np.max(np.abs(Us - Uo))) / ref["U_maxabs"]
+    print(f"one step, 30 PCG, {prec}: L1 {st['L1_final']:.12g} (oracle {ref['L1_final']:.12g}, "
+          f"rel {dL1:.2e}), H rel {dH:.2e}, sampled U max|dU|/max|U| {dU:.2e}, "
+          f"max|U| {Umax:.6g} (oracle {ref['U_maxabs']:.6g})")
+    bar_obj, bar_u = ONESTEP_BARS[prec]
+    assert dL1 <= bar_obj and dH <= bar_obj
+    assert dU <= bar_u
+    assert abs(Umax - ref["U_maxabs"]) <= bar_u * ref["U_maxabs"]
