@@ -361,6 +361,23 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
                             const void* p, void* q, double* pq,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* irlsu_operator for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernel and the same result, bit for bit, with no workspace.  The
+ * per-block partial sums of p . q live in a scratch array of the library
+ * (96 KiB of device memory on each GPU it runs on, held until the process
+ * ends); the call allocates nothing, neither device nor host memory.
+ * Arguments and layout as irlsu_operator; the plan must belong to the
+ * current device.  Limit: images whose operator launch has at most 4096
+ * blocks -- ceil(ld / 1024) * ceil(Np / 64) <= 4096, e.g. up to
+ * 16384 x 16384 -- larger plans return ERR_SHAPE.  Every call on one GPU
+ * shares that GPU's scratch: calls that overlap in time on one GPU (on
+ * different streams, or from several threads) race and must be serialised
+ * by the caller.  Errors: ERR_INVALID_ARG (null pointer, p == q, plan of
+ * another device), ERR_SHAPE, ERR_HIP. */
+irlsu_status irlsu_operator_noalloc(const irlsu_plan* plan, const void* Ov, const void* Oh,
+                                    const void* p, void* q, double* pq, void* stream);
+
 /* Preconditioner z = L^+ r (Section 3.3, Appendix B): orthonormal DCT-II of
  * both axes, division by lambda_k + mu_l, mode (0,0) set to zero, DCT-III
  * back.  How the transforms run is the plan's form: fast cosine transforms

@@ -35,7 +35,7 @@ DECLARED_SYMBOLS = (
     "irlsu_profile_result", "irlsu_round_congruent", "irlsu_augmented_workspace_bytes",
     "irlsu_unwrap_augmented", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched", "irlsu_pcg",
-    "irlsu_test_fail_alloc",
+    "irlsu_test_fail_alloc", "irlsu_operator_noalloc",
 )
 
 STATUS = {
@@ -160,6 +160,7 @@ def load_library():
                                        ctypes.POINTER(Stats), P]),
         "irlsu_weights": (I32, [P, D, P, P, P, P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
+        "irlsu_operator_noalloc": (I32, [P, P, P, P, P, P, P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
         "irlsu_pcg": (I32, [P, P, P, P, P, ctypes.POINTER(Params), ctypes.POINTER(I32),
                             ctypes.POINTER(D), P, SZ, P]),
@@ -344,6 +345,17 @@ class Plan:
         _check(self.lib.irlsu_operator(self.handle, _ptr(Ov), _ptr(Oh), _ptr(p), _ptr(q), _ptr(pq),
                                        _ptr(self.workspace), self.workspace.numel(), _stream()),
                "operator")
+        return q, pq
+
+    def operator_noalloc(self, Ov, Oh, p, q=None, pq=None):
+        """irlsu_operator without workspace (the library's scratch holds the
+        partial sums); q and pq may be passed in so that nothing is
+        allocated by this call."""
+        import torch
+        q = torch.empty_like(p) if q is None else q
+        pq = torch.zeros(1, dtype=torch.float64, device=self.device) if pq is None else pq
+        _check(self.lib.irlsu_operator_noalloc(self.handle, _ptr(Ov), _ptr(Oh), _ptr(p), _ptr(q),
+                                               _ptr(pq), _stream()), "operator_noalloc")
         return q, pq
 
     def precond(self, r):

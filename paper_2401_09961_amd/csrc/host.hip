@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -76,7 +77,38 @@ struct irlsu_batch {
   size_t part_off_bytes = 0, sc_off = 0, fl_off = 0;
 };
 
+// ---- Scratch of the operator without allocation -------------------------
+// irlsu_operator_noalloc keeps the per-block partial sums of p . q in this
+// file-scope device array instead of a workspace: slot PR_PQ of a
+// partial-sum table with kNoAllocParts entries per slot (96 KiB).  Every
+// GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the name itself is a host-side stand-in).
+constexpr int kNoAllocParts = 4096;
+constexpr int kNoAllocSlots = PR_PQ + 1;
+static __device__ __align__(256) double scratch[kNoAllocSlots * kNoAllocParts];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current:
+// resolved once per device (at plan creation), then read from the table.
+double* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
 
 // Allocation-failure hook of irlsu_test_fail_alloc: while armed (>= 0) it
 // counts down the device and pinned allocations of plan and batch creation
@@ -1211,6 +1243,9 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     return IRLSU_ERR_SHAPE;
   }
   (void)hipGetDevice(&p->device);
+  // set-up of irlsu_operator_noalloc on this device (its scratch address);
+  // a failure here surfaces as ERR_HIP from that entry point
+  (void)scratch_address(p->device);
   bool ok = true;
   if (p->fast) {
     const bool share = (N == M);
@@ -1503,6 +1538,37 @@ irlsu_status irlsu_operator(const irlsu_plan* plan, const void* Ov, const void* 
     a.check_done = 0;
     const int n = launch_stencil<T>(ST_APPLY, a, s);
     if (pq) launch_reduce_to(W.st, PR_PQ, n, pq, s);
+  };
+  if (plan->elem == 8) go(double{}); else go(float{});
+  return last_launch();
+}
+
+irlsu_status irlsu_operator_noalloc(const irlsu_plan* plan, const void* Ov, const void* Oh,
+                                    const void* p, void* q, double* pq, void* stream) {
+  if (!plan || !Ov || !Oh || !p || !q) return IRLSU_ERR_INVALID_ARG;
+  if (p == q) return IRLSU_ERR_INVALID_ARG;
+  int rows = 0;
+  const dim3 g = stencil_grid(plan->Np, plan->Mp, &rows);
+  if ((int64_t)g.x * (int64_t)g.y > kNoAllocParts) return IRLSU_ERR_SHAPE;
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev != plan->device) return IRLSU_ERR_INVALID_ARG;
+  double* sp = scratch_address(dev);
+  if (!sp) return IRLSU_ERR_HIP;
+  DevState st;
+  st.part = sp;
+  st.off = 0;
+  st.stride = kNoAllocParts;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    StencilArgs<T> a = stencil_base<T>(plan, static_cast<const T*>(Ov), static_cast<const T*>(Oh),
+                                       st);
+    a.p_in = static_cast<const T*>(p);
+    a.q = static_cast<T*>(q);
+    a.check_done = 0;
+    const int n = launch_stencil<T>(ST_APPLY, a, s);
+    if (pq) launch_reduce_to(st, PR_PQ, n, pq, s);
   };
   if (plan->elem == 8) go(double{}); else go(float{});
   return last_launch();
