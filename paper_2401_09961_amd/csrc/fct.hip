@@ -385,6 +385,17 @@ struct Vec16 {
   typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
 };
 
+// 16-byte streaming accesses (non-temporal hint) for data a pass reads or
+// writes once
+template <class V, class T>
+__device__ __forceinline__ V ld_nt(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+}
+template <class V, class T>
+__device__ __forceinline__ void st_nt(T* p, const V& v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
 template <class TI, int H>
 struct RowChunks {
   static constexpr int N = 2 * H, ROWS = rows_per_block<H>();
@@ -404,7 +415,7 @@ __device__ __forceinline__ void load_rows(const TI* __restrict__ in, int64_t ld,
   for (int i = 0; i < RC::NCH; ++i) {
     const int e0 = (tid + i * kThreads) * RC::W;
     const int row = e0 / RC::N, c = e0 % RC::N;
-    ch.d[i] = *reinterpret_cast<const V*>(in + (row0 + row) * ld + c);
+    ch.d[i] = ld_nt<V>(in + (row0 + row) * ld + c);
   }
 }
 
@@ -588,10 +599,10 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
       for (int u = 0; u < UN; ++u) {
         const int e0 = (tid + (i0 + u) * kThreads) * W;
         const int64_t o = (row0 + e0 / N) * ld + e0 % N;
-        pv[u] = *reinterpret_cast<const V*>(p + o);
-        qv[u] = *reinterpret_cast<const V*>(q + o);
-        rv[u] = *reinterpret_cast<const V*>(r + o);
-        dv[u] = *reinterpret_cast<const V*>(d + o);
+        pv[u] = ld_nt<V>(p + o);
+        qv[u] = ld_nt<V>(q + o);
+        rv[u] = ld_nt<V>(r + o);
+        dv[u] = ld_nt<V>(d + o);
       }
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
@@ -823,7 +834,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
 #pragma unroll
       for (int b = 0; b < BATCH; ++b) {
         const int e0 = (tid + (i0 + b) * kThreads) * W;
-        if (!first) pv[b] = *reinterpret_cast<const V*>(q + (row0 + e0 / N) * ld + e0 % N);
+        if (!first) pv[b] = ld_nt<V>(q + (row0 + e0 / N) * ld + e0 % N);
       }
 #pragma unroll
       for (int b = 0; b < BATCH; ++b) {
@@ -839,7 +850,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
         V o;
 #pragma unroll
         for (int t = 0; t < W; ++t) o[t] = first ? zo[t] : zo[t] + beta * pv[b][t];
-        *reinterpret_cast<V*>(z + (row0 + row) * ld + c) = o;
+        st_nt<V>(z + (row0 + row) * ld + c, o);
       }
     }
     return;
@@ -852,8 +863,8 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
     for (int b = 0; b < BATCH; ++b) {
       const int e0 = (tid + (i0 + b) * kThreads) * W;
       const int64_t o = (row0 + e0 / N) * ld + e0 % N;
-      rv[b] = *reinterpret_cast<const V*>(r + o);
-      if constexpr (FLEX) qv[b] = *reinterpret_cast<const V*>(q + o);
+      rv[b] = ld_nt<V>(r + o);
+      if constexpr (FLEX) qv[b] = ld_nt<V>(q + o);
     }
 #pragma unroll
     for (int b = 0; b < BATCH; ++b) {
@@ -876,7 +887,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
         if constexpr (FLEX) acc[1] += zd * (double)qv[b][t];
         acc[2] += zd;
       }
-      *reinterpret_cast<V*>(z + (row0 + row) * ld + c) = zv;
+      st_nt<V>(z + (row0 + row) * ld + c, zv);
     }
   }
   const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
@@ -926,7 +937,7 @@ __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict
   V d[NPASS];
 #pragma unroll
   for (int i = 0; i < NPASS; ++i)
-    d[i] = *reinterpret_cast<const V*>(in + (r0 + rr + i * RPP) * ldin + c0 + cq * W);
+    d[i] = ld_nt<V>(in + (r0 + rr + i * RPP) * ldin + c0 + cq * W);
 #pragma unroll
   for (int i = 0; i < NPASS; ++i)
 #pragma unroll
@@ -938,7 +949,7 @@ __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict
     V o;
 #pragma unroll
     for (int t = 0; t < W; ++t) o[t] = tile[cq * W + t][jrow];
-    *reinterpret_cast<V*>(out + (c0 + jrow) * ldout + r0 + cq * W) = o;
+    st_nt<V>(out + (c0 + jrow) * ldout + r0 + cq * W, o);
   }
 }
 
