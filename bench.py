@@ -10,13 +10,21 @@ within 1e-3 of the stored oracle value.
 Also reported on the same JSON line:
 * kernels: every launch of one PCG iteration recorded with HIP events
   inside the first warm-up unwrap, with its algorithmic bytes (HBM-bound
-  kernels) or dense-equivalent flops 4NM(N+M) per application (MFMA
-  products); roofline: the dominant one, with HBM traffic from the
-  committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this workload;
+  kernels) or flops (MFMA products); roofline: the dominant one, with HBM
+  traffic from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
+  this workload; MFMA products are rated on the flops they execute (the
+  folded form: half the dense-equivalent 4NM(N+M) per application);
+* hbm_ceilings: measured streaming ceilings of this GPU (the library's own
+  copy, read-only and three-read / one-write kernels), against which each
+  HBM-bound kernel is also rated;
 * mfma_form: the same workload with the folded MFMA preconditioner;
 * cg_adaptive / augmented_form: the Section 4.3 schedule and the paper's
   (U, V) form on the same workload;
-* precisions: the other plan precisions on the same workload (median of up to 5 unwraps);
+* precisions: the other plan precisions on the same workload (median of up to 3 unwraps);
+* c1, c2, c4: the other configurations (256^2 FP64 against the oracle's U,
+  with the oracle timed on one core; 2048^2 plain FP32 under the converged
+  schedule against the stored oracle history; 64 uneven tiles batched
+  against one FP32 plan per tile);
 * cpu_baseline: the FP64 oracle on a bounded sample of the same workload,
   scaled by its recorded iteration counts to the same target.
 
@@ -73,6 +81,17 @@ def oracle_counts_to_target(ref, target):
     return len(hist) - 1, pcg
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(field, ref, target, max_pcg=3):
     """Time the FP64 oracle (as it stands) for one IRLS weight step plus a
     few PCG iterations at full size; scale to the oracle's own counts to the
@@ -98,7 +117,9 @@ def cpu_baseline(field, ref, target, max_pcg=3):
     est = t_setup + (k_t + 1) * t_weight + pcg_t * t_pcg
     return {
         "value": round(N * M / 1e6 / est, 6), "unit": "Mpixel/s", "cores": workers,
-        "kind": "oracle",
+        "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+        "cores_note": ("FFT workers capped at 16, the host-CPU share of one GPU on this box "
+                       "(numpy's element-wise passes run on one core)"),
         "sample": (f"FP64 oracle on the same {N}x{M} field: setup + 1 IRLS weight step + "
                    f"{info['iters']} PCG iterations timed ({t3 - t0:.1f} s), scaled by the oracle's "
                    f"recorded {k_t} IRLS / {pcg_t} PCG iterations to the same L1 target "
@@ -215,14 +236,19 @@ def roofline(kern, prec, traffic=None):
     name, ent = max(cand, key=lambda kv: kv[1]["ms"])
     ms_launch = ent["ms"] / ent["launches"]
     if ent["bound"] == "mfma":
-        # the folded form executes half of the dense-equivalent flops
-        ach = ent["flops_per_launch"] / (ms_launch * 1e-3) / 1e12
-        ex = ach / (2.0 if ent["folded"] else 1.0)
+        # achieved on the flops the products execute: the folded form does
+        # half of the dense-equivalent 4NM(N+M) per application
+        dense = ent["flops_per_launch"] / (ms_launch * 1e-3) / 1e12
+        ex_flops = ent["flops_per_launch"] / (2.0 if ent["folded"] else 1.0)
+        ach = ex_flops / (ms_launch * 1e-3) / 1e12
         return {"bound": "mfma", "kernel": name, "achieved": round(ach, 2), "peak": PEAK[prec],
                 "unit": "TFLOP/s", "frac": round(ach / PEAK[prec], 4), "traffic": None,
-                "flops_per_launch": ent["flops_per_launch"],
-                "flops_basis": "dense-equivalent 4NM(N+M) per application / launches",
-                "executed_TFLOPs": round(ex, 2), "executed_frac": round(ex / PEAK[prec], 4),
+                "flops_per_launch": ex_flops,
+                "flops_basis": ("executed: 2NM(N+M) per folded application (half the dense "
+                                "products) / launches" if ent["folded"] else
+                                "executed: 4NM(N+M) per application / launches"),
+                "dense_equivalent_TFLOPs": round(dense, 2),
+                "dense_equivalent_frac": round(dense / PEAK[prec], 4),
                 "ms_per_launch": round(ms_launch, 4), "launches_per_iter": ent["launches"]}
     ach = ent["bytes_per_launch"] / (ms_launch * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"],
@@ -342,7 +368,7 @@ def paper_shapes(pkg, torch, synth, a, prec):
     return 0
 
 
-def batched(pkg, torch, synth, a):
+def batched(pkg, torch, synth, a, return_line=False):
     """64 uneven tiles (c1-generator fields, seeds 1000 + t) unwrapped as one
     batch (mixed BF16, one grouped launch per PCG phase) and one plan per
     tile in FP32, same schedule (20 IRLS x 100 PCG, pcg_rtol 1e-6); HIP
@@ -392,8 +418,92 @@ def batched(pkg, torch, synth, a):
                                "L1_per_edge_max_looped": max(l1l),
                                "max_abs_U_difference": du},
             "data": "synthetic (c1-generator tiles)"}
+    if return_line:
+        return line
     print(json.dumps(line), flush=True)
     return 0
+
+
+def hbm_ceilings(pkg):
+    """Measured streaming ceilings of this GPU (the library's own kernel,
+    256 MiB per array, best over the swept grids)."""
+    return {k: pkg.stream_probe(k) for k in ("copy", "read", "3r1w")}
+
+
+def c1_case(pkg, torch, synth, steps=5):
+    """Config 1: the 256^2 Gaussian-sum field in FP64, 20 IRLS x <= 100 PCG at
+    tolerance 1e-8.  The field meets the Itoh condition (no residues), so U
+    is unique up to a constant and is compared pointwise with the oracle's,
+    which is timed on one core (threadpoolctl caps every thread pool)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import reduced as R
+    f = synth.field_c1(0, 256, 256)
+    X = torch.from_numpy(f.X).to(device="cuda", dtype=torch.float64)
+    plan = pkg.Plan(256, 256, "f64")
+    p = pkg.default_params("f64")
+    p.irls_iters, p.pcg_max, p.pcg_rtol, p.eps = 20, 100, 1e-8, 1e-3
+    U = torch.empty((256, 256), dtype=torch.float64, device="cuda")
+    plan.unwrap(X, params=p, out=U)
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    for i in range(steps):
+        _, st = plan.unwrap(X, params=p, out=U, stats=True)
+        ev[i + 1].record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
+    Ug = U.cpu().numpy()
+    plan.close()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Uo, hist = R.irls(f.X, iters=20, tol=1e-8, maxit=100, eps=1e-3, workers=1)
+        t_o = time.perf_counter() - t0
+    du = float(np.max(np.abs((Ug - Ug.mean()) - (Uo - Uo.mean()))))
+    return {"workload": "c1 seed 0: 256x256 FP64, 8 Gaussians (+-20 rad), ramp, N(0,0.3^2) noise, "
+                        "unit weights; 20 IRLS x <= 100 PCG, tol 1e-8",
+            "precision": "f64", "ms_per_unwrap": round(ms, 3),
+            "value": round(256 * 256 / 1e6 / (ms * 1e-3), 3), "unit": "Mpixel/s",
+            "pcg_iters": st["pcg_total"], "L1_final": st["L1_final"],
+            "max_abs_U_difference_vs_oracle": du,
+            "oracle_1core": {"seconds": round(t_o, 3), "value": round(256 * 256 / 1e6 / t_o, 5),
+                             "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+                             "pcg_iters": int(sum(h.get("iters", 0) for h in hist))}}
+
+
+def c2_case(pkg, torch, synth):
+    """Config 2: the 2048^2 field (3 pi step, decorrelated band, Beta(2,2)
+    weights) in plain FP32 under the schedule of the stored converged oracle
+    reference (every solve to 1e-6): Mpixel/s for the whole schedule and the
+    largest relative L1 gap over its iterates (the plain path's bar is
+    1e-5)."""
+    ref = load_reference("c2_seed0_2048_float32_conv.json")
+    n = ref["N"]
+    f = synth.field_c2(ref["seed"], n, n)
+    X = torch.from_numpy(f.X).to(device="cuda", dtype=torch.float32)
+    w = torch.from_numpy(f.w).to(device="cuda", dtype=torch.float32)
+    plan = pkg.Plan(n, n, "f32")
+    p = pkg.default_params("f32")
+    p.irls_iters, p.pcg_max, p.pcg_rtol, p.eps = ref["iters"], ref["maxit"], ref["tol"], ref["eps"]
+    U = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    plan.unwrap(X, w, params=p, out=U)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    plan.close()
+    gaps = [abs(st["history"][k]["L1"] - ref["history"][k]["L1"]) / ref["history"][k]["L1"]
+            for k in range(ref["iters"] + 1)]
+    return {"workload": f"c2 seed 0: {n}x{n} plain FP32, {ref['iters']} IRLS, every solve to "
+                        f"relres {ref['tol']:g}",
+            "precision": "f32", "form": "fast", "ms_per_unwrap": round(ms, 2),
+            "value": round(n * n / 1e6 / (ms * 1e-3), 3), "unit": "Mpixel/s",
+            "pcg_iters": st["pcg_total"], "oracle_pcg_iters": ref["pcg_total"],
+            "max_rel_L1_gap_vs_oracle": max(gaps), "bar": 1e-5, "status": st["status"]}
 
 
 def kernels_only(pkg, torch, N, M, prec):
@@ -432,6 +542,11 @@ def main(argv=None):
     ap.add_argument("--gap", type=float, default=1e-3)
     ap.add_argument("--max-irls", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the streaming-ceiling probes (copy, read, 3 reads + 1 write)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (c1 256^2 FP64, c2 2048^2 FP32, "
+                         "c4 64 uneven tiles)")
     ap.add_argument("--flexible", type=int, choices=[-1, 0, 1], default=-1,
                     help="CG beta: 0 plain, 1 flexible, -1 the plan's default")
     ap.add_argument("--no-precisions", action="store_true",
@@ -500,7 +615,8 @@ def main(argv=None):
     if plan.form == "fast" and not a.no_mfma_form:
         plan.close()
         form = "folded" if (N % 2 == 0 and M % 2 == 0) else "dense"
-        sec = measure(pkg, torch, N, M, prec, form, X, w, ref, target, a)
+        sec = measure(pkg, torch, N, M, prec, form, X, w, ref, target, a,
+                      steps=min(max(1, a.steps), 2))
         mfma = {"form": form, "value": round(N * M / 1e6 / (sec["ms"] * 1e-3), 4),
                 "ms_per_step": round(sec["ms"], 3), "target_hit": sec["hit"],
                 "irls_iters": sec["last"]["irls_done"], "pcg_iters": sec["last"]["pcg_total"],
@@ -545,7 +661,7 @@ def main(argv=None):
                 continue
             dtp = torch.float64 if pr == "f64" else torch.float32
             sec = measure(pkg, torch, N, M, pr, "auto", X.to(dtp), w.to(dtp), ref, target, a,
-                          steps=min(max(1, a.steps), 5))
+                          steps=min(max(1, a.steps), 3))
             lst = sec["last"]
             med = float(np.median(sec["step_ms"]))
             precs[pr] = {"value": round(N * M / 1e6 / (med * 1e-3), 4),
@@ -585,6 +701,26 @@ def main(argv=None):
         "augmented_form": aug,
         "precisions": precs,
     }
+    if not a.no_ceilings:
+        print("[bench] streaming ceilings", file=sys.stderr, flush=True)
+        ceil = hbm_ceilings(pkg)
+        line["hbm_ceilings"] = ceil
+        if roof and roof["bound"] == "hbm":
+            roof["frac_of_measured_copy"] = round(roof["achieved"] / ceil["copy"]["best_GBps"], 4)
+            roof["frac_of_measured_3r1w"] = round(roof["achieved"] / ceil["3r1w"]["best_GBps"], 4)
+        for name, ent in kern.items():
+            if ent["bound"] == "hbm" and ent["ms"] > 0:
+                gbs = ent["bytes_per_launch"] * ent["launches"] / (ent["ms"] * 1e-3) / 1e9
+                ent["GBps"] = round(gbs, 1)
+                ent["frac_of_8TBps"] = round(gbs / PEAK["hbm_GBps"], 4)
+                ent["frac_of_measured_3r1w"] = round(gbs / ceil["3r1w"]["best_GBps"], 4)
+    if not a.no_configs:
+        print("[bench] config 1 (256^2 FP64)", file=sys.stderr, flush=True)
+        line["c1"] = c1_case(pkg, torch, synth)
+        print("[bench] config 2 (2048^2 FP32, converged schedule)", file=sys.stderr, flush=True)
+        line["c2"] = c2_case(pkg, torch, synth)
+        print("[bench] config 4 (64 uneven tiles)", file=sys.stderr, flush=True)
+        line["c4"] = batched(pkg, torch, synth, a, return_line=True)
     if not a.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(field, ref, target)

@@ -96,6 +96,10 @@ typedef struct irlsu_params {
                               condition of Theorem 3. IRLSU_GUARD_CHECK */
   double cg_eps_tol;       /* adaptive: significance threshold of Delta. 1e-3 */
   double cg_alpha;         /* adaptive: cap growth factor. 1.7 */
+  int32_t graph;           /* 1: replay each PCG iteration's launches from a captured HIP graph
+                              (one graph launch instead of 5-12 kernel launches; identical
+                              results); 0: launch directly. 1 */
+  int32_t reserved_;
 } irlsu_params;
 
 /* CG iteration schedules (irlsu_params.cg_schedule).  The adaptive one is
@@ -480,6 +484,20 @@ irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z,
                                  void* workspace, size_t workspace_bytes, int32_t reps,
                                  double* ms_launch, int32_t* kind, int32_t* n_launches,
                                  void* stream);
+
+/* Measurement aid: the HBM ceilings that the kernels' bandwidth is reported
+ * against.  Streams `bytes` (a multiple of 16) with the library's own
+ * streaming kernel: IRLSU_PROBE_COPY reads a and writes d, IRLSU_PROBE_READ
+ * reads a only (d may be NULL), IRLSU_PROBE_3R1W reads a, b, c and writes
+ * d (the operator's mix).  grid blocks of 256 threads, 16-byte
+ * non-temporal accesses; one warm-up launch, then reps launches timed with
+ * HIP events on `stream`; *ms gets the mean per launch.  All buffers are
+ * device memory of at least `bytes`.  Synchronises the stream.  Errors:
+ * ERR_INVALID_ARG, ERR_HIP. */
+enum { IRLSU_PROBE_COPY = 0, IRLSU_PROBE_READ = 1, IRLSU_PROBE_3R1W = 2 };
+irlsu_status irlsu_stream_probe(int32_t kind, const void* a, const void* b, const void* c, void* d,
+                                size_t bytes, int32_t grid, int32_t reps, double* ms,
+                                void* stream);
 
 /* Timing aid for one iteration of Algorithm 2 inside irlsu_unwrap: arms the
  * plan so that the next irlsu_unwrap records a HIP event on its stream after

@@ -17,6 +17,11 @@ Usage:
     # capped schedule's sensitivity
     python -m oracle.make_reference c3 --seed 0 --dtype float32 --iters 1 \
         --tol 0 --maxit 30 --samples 10000 --tag onestep30
+    # the paper's running-time shape 4000 x M (Section 4.5): a c2-type field
+    # of 4000 x 2000, the capped schedule and the one-step record
+    python -m oracle.make_reference c2 --seed 0 --dtype float32 --shape 4000 2000
+    python -m oracle.make_reference c2 --seed 0 --dtype float32 --shape 4000 2000 \
+        --iters 1 --tol 0 --maxit 30 --samples 10000 --tag onestep30
 
 ``--dtype float32`` rounds the inputs (X and the weights) to float32 before
 the FP64 solve, which is what the FP32 and mixed GPU paths receive.
@@ -44,9 +49,11 @@ OUT_DIR = os.path.join(HERE, "reference")
 SAMPLE_SEED = 12345
 
 
-def reference_path(gen, seed, size, dtype, tag=""):
+def reference_path(gen, seed, size, dtype, tag="", cols=None):
+    """size: the side of a square grid, or the row count when cols is given."""
     suffix = f"_{tag}" if tag else ""
-    return os.path.join(OUT_DIR, f"{gen}_seed{seed}_{size}_{dtype}{suffix}.json")
+    shape = f"{size}" if cols is None or cols == size else f"{size}x{cols}"
+    return os.path.join(OUT_DIR, f"{gen}_seed{seed}_{shape}_{dtype}{suffix}.json")
 
 
 def sample_positions(N, M, k):
@@ -61,6 +68,8 @@ def main(argv=None):
     ap.add_argument("gen", choices=["c1", "c2", "c3"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--size", type=int, default=None)
+    ap.add_argument("--shape", type=int, nargs=2, default=None, metavar=("N", "M"),
+                    help="a non-square grid of N rows and M columns")
     ap.add_argument("--dtype", choices=["float32", "float64"], default="float32")
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -73,14 +82,17 @@ def main(argv=None):
     a = ap.parse_args(argv)
     default = {"c1": 256, "c2": 2048, "c3": 8192}[a.gen]
     n = a.size or default
-    f = getattr(synth, "field_" + a.gen)(a.seed, n, n)
+    m = n
+    if a.shape is not None:
+        n, m = a.shape
+    f = getattr(synth, "field_" + a.gen)(a.seed, n, m)
     X, w = f.X, f.w
     if a.dtype == "float32":
         X = X.astype(np.float32).astype(np.float64)
         w = None if w is None else w.astype(np.float32).astype(np.float64)
     os.makedirs(OUT_DIR, exist_ok=True)
-    path = reference_path(a.gen, a.seed, n, a.dtype, a.tag)
-    rec = dict(gen=a.gen, seed=a.seed, N=n, M=n, input_dtype=a.dtype,
+    path = reference_path(a.gen, a.seed, n, a.dtype, a.tag, cols=m)
+    rec = dict(gen=a.gen, seed=a.seed, N=n, M=m, input_dtype=a.dtype,
                iters=a.iters, tol=a.tol, maxit=a.maxit, eps=a.eps,
                workers=a.workers, host=platform.node(),
                cpu=platform.processor() or platform.machine(),
@@ -106,7 +118,7 @@ def main(argv=None):
     rec["H_final"] = final["H"]
     rec["pcg_total"] = int(sum(h.get("iters", 0) for h in hist))
     if a.samples > 0:
-        i, j = sample_positions(n, n, a.samples)
+        i, j = sample_positions(n, m, a.samples)
         rec["samples"] = dict(seed=SAMPLE_SEED, i=i.tolist(), j=j.tolist(),
                               U=[float(v) for v in U[i, j]])
         rec["U_norm2"] = float(np.sqrt(np.sum(U * U)))

@@ -35,7 +35,7 @@ DECLARED_SYMBOLS = (
     "irlsu_profile_result", "irlsu_round_congruent", "irlsu_augmented_workspace_bytes",
     "irlsu_unwrap_augmented", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched", "irlsu_pcg",
-    "irlsu_test_fail_alloc", "irlsu_operator_noalloc",
+    "irlsu_test_fail_alloc", "irlsu_operator_noalloc", "irlsu_stream_probe",
 )
 
 STATUS = {
@@ -60,7 +60,8 @@ class Params(ctypes.Structure):
         ("poll_every", ctypes.c_int32), ("flexible", ctypes.c_int32),
         ("cg_schedule", ctypes.c_int32), ("cg_m0", ctypes.c_int32),
         ("sd_guard", ctypes.c_int32), ("cg_eps_tol", ctypes.c_double),
-        ("cg_alpha", ctypes.c_double),
+        ("cg_alpha", ctypes.c_double), ("graph", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
     ]
 
 
@@ -161,6 +162,7 @@ def load_library():
         "irlsu_weights": (I32, [P, D, P, P, P, P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator_noalloc": (I32, [P, P, P, P, P, P, P]),
+        "irlsu_stream_probe": (I32, [I32, P, P, P, P, SZ, I32, I32, ctypes.POINTER(D), P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
         "irlsu_pcg": (I32, [P, P, P, P, P, ctypes.POINTER(Params), ctypes.POINTER(I32),
                             ctypes.POINTER(D), P, SZ, P]),
@@ -196,6 +198,35 @@ def _ptr(t):
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+PROBES = {"copy": 0, "read": 1, "3r1w": 2}
+
+
+def stream_probe(kind, nbytes=256 << 20, grids=(256, 512, 1024, 2048), reps=10):
+    """Measured HBM ceiling of one streaming mix (the library's own kernel):
+    {grid: GB/s of algorithmic bytes} and the best, for 'copy' (1 read +
+    1 write), 'read' and '3r1w' (3 reads + 1 write) over nbytes per array."""
+    import torch
+    lib = load_library()
+    narr = {"copy": 2, "read": 1, "3r1w": 4}[kind]
+    bufs = [torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+            for _ in range(narr)]
+    a = bufs[0]
+    b = bufs[1] if kind == "3r1w" else None
+    c = bufs[2] if kind == "3r1w" else None
+    d = bufs[-1] if kind != "read" else None
+    moved = {"copy": 2, "read": 1, "3r1w": 4}[kind] * nbytes
+    out = {}
+    for g in grids:
+        ms = ctypes.c_double()
+        _check(lib.irlsu_stream_probe(PROBES[kind], _ptr(a), _ptr(b), _ptr(c), _ptr(d), nbytes,
+                                      int(g), int(reps), ctypes.byref(ms), _stream()),
+               "stream_probe")
+        out[g] = moved / (ms.value * 1e-3) / 1e9
+    del bufs
+    return {"GBps_by_grid": {str(g): round(v, 1) for g, v in out.items()},
+            "best_GBps": round(max(out.values()), 1), "bytes_per_array": nbytes}
 
 
 def default_params(precision="f32") -> Params:

@@ -560,7 +560,7 @@ __global__ __launch_bounds__(1024) void cg_alpha_kernel(DevState st, int nparts_
   const double alpha = rho / pq;
   st.sc[SC_ALPHA + (iter & 1)] = alpha;
   st.sc[SC_PQ] = pq;
-  st.fl[FL_ITERS] = iter + 1;
+  st.fl[FL_ITERS] += 1;  // counted on the device: iteration-independent launches
   if (f16) {
     const double bound = sqrt(st.sc[SC_RR]) + fabs(alpha) * sqrt(qq);
     st.sc[SC_SCALE] = bound > 0.0 ? 1e-3 * sqrt(npix) / bound : 1.0;
@@ -798,9 +798,28 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   const CT inv_h = (CT)(0.5 / H) / (use_scale ? (CT)st.sc[SC_SCALE] : (CT)1);
   const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  using V = typename Vec16<TO>::type;
+  constexpr int W = Vec16<TO>::W;
+  constexpr int NCH = ROWS * N / W / kThreads;
+  // OUT 2: the previous direction, loaded with the stored coefficients so
+  // that its latency hides behind the transform (NCH 16-byte chunks per
+  // thread, 8 at h = 4096 in FP32; rows longer than that load it after the
+  // transform instead, to keep the registers for the butterflies)
+  constexpr bool PRE = OUT == 2 && NCH <= 8;
+  constexpr int NPV = OUT == 2 ? NCH : 1;
+  V pv[NPV];
   {
     RowChunks<SI, H> ch;
     load_rows<SI, H>(in, ld, row0, ch, tid);
+    if constexpr (PRE) {
+      if (iter != 0) {
+#pragma unroll
+        for (int b = 0; b < NCH; ++b) {
+          const int e0 = (tid + b * kThreads) * W;
+          pv[b] = ld_nt<V>(q + (row0 + e0 / N) * ld + e0 % N);
+        }
+      }
+    }
     put_rows_inv<CT, SI, H>(ch, buf, tid);
   }
   __syncthreads();
@@ -820,38 +839,29 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   }
   __syncthreads();
   fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
-  using V = typename Vec16<TO>::type;
-  constexpr int W = Vec16<TO>::W;
-  constexpr int NCH = ROWS * N / W / kThreads;
   constexpr int BATCH = NCH < 8 ? NCH : 8;
   static_assert(NCH % BATCH == 0, "output batches");
   if constexpr (OUT == 2) {
     const TO beta = (TO)st.sc[SC_BETA];
     const bool first = iter == 0;
 #pragma unroll
-    for (int i0 = 0; i0 < NCH; i0 += BATCH) {
-      V pv[BATCH];
-#pragma unroll
-      for (int b = 0; b < BATCH; ++b) {
-        const int e0 = (tid + (i0 + b) * kThreads) * W;
-        if (!first) pv[b] = ld_nt<V>(q + (row0 + e0 / N) * ld + e0 % N);
+    for (int b = 0; b < NCH; ++b) {
+      const int e0 = (tid + b * kThreads) * W;
+      const int row = e0 / N, c = e0 % N;
+      if constexpr (!PRE) {
+        if (!first) pv[b] = ld_nt<V>(q + (row0 + row) * ld + c);
       }
+      TO zo[W];
+      if constexpr (W >= 4) {
+        inv_chunk<CT, H, W, TO>(buf, row, c, inv_h, zo);
+      } else {
 #pragma unroll
-      for (int b = 0; b < BATCH; ++b) {
-        const int e0 = (tid + (i0 + b) * kThreads) * W;
-        const int row = e0 / N, c = e0 % N;
-        TO zo[W];
-        if constexpr (W >= 4) {
-          inv_chunk<CT, H, W, TO>(buf, row, c, inv_h, zo);
-        } else {
-#pragma unroll
-          for (int t = 0; t < W; ++t) zo[t] = (TO)inv_value<CT, N>(v, row, c + t, inv_h);
-        }
-        V o;
-#pragma unroll
-        for (int t = 0; t < W; ++t) o[t] = first ? zo[t] : zo[t] + beta * pv[b][t];
-        st_nt<V>(z + (row0 + row) * ld + c, o);
+        for (int t = 0; t < W; ++t) zo[t] = (TO)inv_value<CT, N>(v, row, c + t, inv_h);
       }
+      V o;
+#pragma unroll
+      for (int t = 0; t < W; ++t) o[t] = first ? zo[t] : zo[t] + beta * pv[b][t];
+      st_nt<V>(z + (row0 + row) * ld + c, o);
     }
     return;
   }

@@ -45,6 +45,12 @@ struct irlsu_plan {
   // timing aid: events of one armed PCG iteration (irlsu_profile_arm)
   int prof_k = -1, prof_l = -1;
   LaunchLog* prof = nullptr;
+  // stream on which PCG iterations are captured into graphs (non-blocking,
+  // default priority); null when it could not be created
+  hipStream_t cap_stream = nullptr;
+  // events of the convergence polls read one block behind (null: each poll
+  // synchronises the stream)
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   // folded preconditioner (even N and M)
   int folded = 0;
   int64_t hNp = 0, hMp = 0;
@@ -75,6 +81,8 @@ struct irlsu_batch {
   size_t ws_bytes = 0;
   std::vector<size_t> tile_off;    // workspace offset of each tile's vectors
   size_t part_off_bytes = 0, sc_off = 0, fl_off = 0;
+  hipStream_t cap_stream = nullptr;  // capture stream of the PCG graphs (null: direct launches)
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};  // polls read one block behind (null: synchronous)
 };
 
 // ---- Scratch of the operator without allocation -------------------------
@@ -301,6 +309,50 @@ irlsu_status read_back(irlsu_plan* pl, const Ws<T>& W, hipStream_t s) {
   return IRLSU_OK;
 }
 
+// Captured graphs of PCG iterations, by variant key, for one solve.  The
+// launches are captured on the plan's own capture stream (the caller's may
+// be the legacy default stream, which cannot be captured) and replayed on
+// the caller's.  Nothing but kernel launches is captured.
+class PcgGraphs {
+ public:
+  explicit PcgGraphs(hipStream_t cap) : cap_(cap) {}
+  ~PcgGraphs() {
+    for (auto& e : exec_)
+      if (e.second) (void)hipGraphExecDestroy(e.second);
+  }
+  bool ok() const { return cap_ != nullptr; }
+  template <class F>
+  irlsu_status launch(uint64_t key, F&& record, hipStream_t s) {
+    auto it = exec_.find(key);
+    if (it == exec_.end()) {
+      hipStream_t q = cap_;
+      if (hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return IRLSU_ERR_HIP;
+      record(q);
+      hipGraph_t g = nullptr;
+      const hipError_t e1 = hipStreamEndCapture(q, &g);
+      if (e1 != hipSuccess || !g) {
+        (void)hipGetLastError();
+        return IRLSU_ERR_HIP;
+      }
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess || !ex) {
+        (void)hipGetLastError();
+        return IRLSU_ERR_HIP;
+      }
+      it = exec_.emplace(key, ex).first;
+    }
+    HIP_OK(hipGraphLaunch(it->second, s));
+    return IRLSU_OK;
+  }
+
+ private:
+  hipStream_t cap_;
+  std::map<uint64_t, hipGraphExec_t> exec_;
+};
+
 // PCG (Algorithm 2) on D^T Omega D x = rhs with the Omega currently in the
 // workspace, warm-started at x (FP64).  ||rhs||^2 and tol^2 must already be in
 // SC_BB / SC_TOL2 and the flags cleared (finalize_weights / adjoint rhs).
@@ -353,12 +405,9 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     pa.nparts_rr = nrr;
   }
   const int nprec = launch_precond(pa, s);
-  for (int l = 0; l < prm.pcg_max; ++l) {
-    LaunchLog* L = (pl->prof && irls_k == pl->prof_k && l == pl->prof_l) ? pl->prof : nullptr;
-    if (L) {
-      L->n = 0;
-      log_start(L, s);
-    }
+  // The launches of iteration l on stream q (no host work, no memset): the
+  // loop issues them directly, or replays a captured graph of them.
+  auto issue = [&](int l, LaunchLog* L, hipStream_t q) {
     StencilArgs<T> fa = stencil_base<T>(pl, W.v[V_OV], W.v[V_OH], st);
     fa.z = W.v[V_Z];
     fa.p_in = spectral ? P[l & 1] : P[(l + 1) & 1];
@@ -370,8 +419,8 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     fa.nparts_res = nvec;
     fa.check_done = 1;
     fa.want_qq = spectral ? 1 : 0;
-    const int npq = launch_stencil<T>(spectral ? ST_APPLY : ST_FUSED, fa, s);
-    log_mark(L, IRLSU_LK_STENCIL, s);
+    const int npq = launch_stencil<T>(spectral ? ST_APPLY : ST_FUSED, fa, q);
+    log_mark(L, IRLSU_LK_STENCIL, q);
     const bool refresh =
         prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max;
     if (spectral && !refresh && l + 1 < prm.pcg_max) {
@@ -381,16 +430,9 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
       fused.p_in = P[l & 1];
       fused.p_out = P[(l + 1) & 1];
       fused.fused_head = 1;
-      launch_cg_update_fast<T>(fused, W.v[V_R], d, P[l & 1], W.v[V_Q], npq, l, nrr, s);
-      launch_precond(fused, s);
-      if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
-      if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
-        HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        if (pl->h_flags[FL_DONE]) break;
-      }
-      continue;
+      launch_cg_update_fast<T>(fused, W.v[V_R], d, P[l & 1], W.v[V_Q], npq, l, nrr, q);
+      launch_precond(fused, q);
+      return;
     }
     AxpyArgs<T> xa;
     xa.u = x;
@@ -403,17 +445,18 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     xa.nparts_out = nrr;
     xa.iter = l;
     xa.st = st;
-    launch_axpy<T>(xa, s, axpy_blocks(nvec));
-    log_mark(L, IRLSU_LK_AXPY, s);
+    launch_axpy<T>(xa, q, axpy_blocks(nvec));
+    log_mark(L, IRLSU_LK_AXPY, q);
     if (refresh) {
       // the correction so far moves into the FP64 iterate before the true
       // residual is formed (d restarts at zero): d then only ever holds the
       // correction since the last refresh, so its rounding in the vector
       // type no longer bounds how far the residual can fall
-      launch_commit<T>(x, d, (int64_t)npx, s, true);
-      ra.check_done = 1;
-      launch_stencil<T>(ST_RESID, ra, s);
-      log_mark(L, IRLSU_LK_RESIDUAL, s);
+      launch_commit<T>(x, d, (int64_t)npx, q, true);
+      StencilArgs<T> rb = ra;
+      rb.check_done = 1;
+      launch_stencil<T>(ST_RESID, rb, q);
+      log_mark(L, IRLSU_LK_RESIDUAL, q);
     }
     if (l + 1 < prm.pcg_max) {
       PrecondArgs pl_args = pa;
@@ -423,14 +466,67 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
         pl_args.p_in = P[l & 1];
         pl_args.p_out = P[(l + 1) & 1];
       }
-      launch_precond(pl_args, s);
+      launch_precond(pl_args, q);
+    }
+  };
+  // The loop runs in blocks of iterations, one per convergence poll.  A
+  // block is replayed from a captured graph: every launch argument of
+  // iteration l depends on l only through its parity, whether a
+  // true-residual refresh follows it and whether it is the last (the
+  // iteration count is kept on the device; beta = 0 at l = 0 only matters
+  // to the fused stencil, whose first block runs directly), so a few graphs
+  // serve a whole solve.  The poll of block b is read after block b + 1 has
+  // been enqueued: the device never waits for the host, and a block enqueued
+  // after convergence costs only kernels that return at once.
+  PcgGraphs graphs(pl->cap_stream);
+  const bool use_graph = prm.graph != 0 && graphs.ok();
+  const int B = prm.poll_every > 0 ? prm.poll_every : 8;
+  const bool ahead = pl->poll_ev[0] && pl->poll_ev[1];
+  int pending = -1;
+  for (int l0 = 0, blk = 0; l0 < prm.pcg_max; ++blk) {
+    const int len = std::min(B, prm.pcg_max - l0);
+    bool prof = false;
+    for (int l = l0; l < l0 + len; ++l)
+      prof = prof || (pl->prof && irls_k == pl->prof_k && l == pl->prof_l);
+    if (!use_graph || prof || (!spectral && l0 == 0)) {
+      for (int l = l0; l < l0 + len; ++l) {
+        LaunchLog* L = (pl->prof && irls_k == pl->prof_k && l == pl->prof_l) ? pl->prof : nullptr;
+        if (L) {
+          L->n = 0;
+          log_start(L, s);
+        }
+        issue(l, L, s);
+      }
+    } else {
+      uint64_t key = (uint64_t)(l0 & 1) | ((uint64_t)len << 1);
+      for (int i = 0; i < len; ++i) {
+        const int l = l0 + i;
+        const bool refresh =
+            prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max;
+        if (refresh) key |= (uint64_t)1 << (16 + i);
+      }
+      if (l0 + len >= prm.pcg_max) key |= (uint64_t)1 << 15;
+      irlsu_status gs = graphs.launch(key, [&](hipStream_t q) {
+        for (int l = l0; l < l0 + len; ++l) issue(l, nullptr, q);
+      }, s);
+      if (gs != IRLSU_OK) return gs;
     }
     if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
-    if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
-      HIP_OK(hipMemcpyAsync(pl->h_flags, st.fl, FL_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            s));
-      HIP_OK(hipStreamSynchronize(s));
-      if (pl->h_flags[FL_DONE]) break;
+    l0 += len;
+    if (prm.poll_every > 0) {
+      int32_t* slot = pl->h_flags + (ahead ? (blk & 1) * FL_COUNT : 0);
+      HIP_OK(hipMemcpyAsync(slot, st.fl, FL_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      if (!ahead) {
+        HIP_OK(hipStreamSynchronize(s));
+        if (slot[FL_DONE]) break;
+        continue;
+      }
+      HIP_OK(hipEventRecord(pl->poll_ev[blk & 1], s));
+      if (pending >= 0) {
+        HIP_OK(hipEventSynchronize(pl->poll_ev[pending & 1]));
+        if (pl->h_flags[(pending & 1) * FL_COUNT + FL_DONE]) break;
+      }
+      pending = blk;
     }
   }
   launch_finalize_rr(st, nrr, s);
@@ -881,6 +977,8 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
     }
   };
 
+  PcgGraphs graphs(b->cap_stream);
+  const bool use_graph = prm.graph != 0 && graphs.ok();
   for (int k = 0; k < prm.irls_iters; ++k) {
     weights_all();
     if (stats) {
@@ -894,23 +992,67 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
     launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, 0, flexible, 0, s);
     launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
                            b->st_total, s);
-    for (int l = 0; l < prm.pcg_max; ++l) {
+    // one PCG step over all tiles: grouped stencil, update, refresh,
+    // preconditioner products; replayed from captured graphs for l >= 1
+    // (the arguments depend on l only through its parity, the refresh and
+    // the last iteration; iteration counts are kept on the device)
+    auto step = [&](int l, hipStream_t q) {
       launch_stencil_batched<float>(ST_FUSED, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
-                                    s);
-      launch_axpy_batched<float>(dt, b->d_st_start, nt, b->st_total, l, s);
+                                    q);
+      launch_axpy_batched<float>(dt, b->d_st_start, nt, b->st_total, l, q);
       if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max)
         launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
-                                      s);
-      if (l + 1 < prm.pcg_max) launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
-                           b->st_total, s);
+                                      q);
+      if (l + 1 < prm.pcg_max)
+        launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
+                               b->st_total, q);
+    };
+    // blocks of iterations between polls, as in the single-image loop
+    // (graphs for the blocks after the first; each poll read one block
+    // behind)
+    const int B = prm.poll_every > 0 ? prm.poll_every : 8;
+    const size_t fbytes = (size_t)nt * FL_COUNT * sizeof(int32_t);
+    const bool ahead = b->poll_ev[0] && b->poll_ev[1];
+    int pending = -1;
+    for (int l0 = 0, blk = 0; l0 < prm.pcg_max; ++blk) {
+      const int len = std::min(B, prm.pcg_max - l0);
+      if (l0 == 0 || !use_graph) {
+        for (int l = l0; l < l0 + len; ++l) step(l, s);
+      } else {
+        uint64_t key = (uint64_t)(l0 & 1) | ((uint64_t)len << 1);
+        for (int i = 0; i < len; ++i) {
+          const int l = l0 + i;
+          if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max)
+            key |= (uint64_t)1 << (16 + i);
+        }
+        if (l0 + len >= prm.pcg_max) key |= (uint64_t)1 << 15;
+        rs = graphs.launch(key, [&](hipStream_t q) {
+          for (int l = l0; l < l0 + len; ++l) step(l, q);
+        }, s);
+        if (rs != IRLSU_OK) return rs;
+      }
       if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
-      if (prm.poll_every > 0 && (l + 1) % prm.poll_every == 0) {
-        HIP_OK(hipMemcpyAsync(b->h_flags, base + b->fl_off, (size_t)nt * FL_COUNT * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        bool all = true;
-        for (int t = 0; t < nt; ++t) all = all && b->h_flags[t * FL_COUNT + FL_DONE];
-        if (all) break;
+      l0 += len;
+      if (prm.poll_every > 0) {
+        int32_t* slot = b->h_flags + (ahead ? (size_t)(blk & 1) * nt * FL_COUNT : 0);
+        HIP_OK(hipMemcpyAsync(slot, base + b->fl_off, fbytes, hipMemcpyDeviceToHost, s));
+        int32_t* check = nullptr;
+        if (!ahead) {
+          HIP_OK(hipStreamSynchronize(s));
+          check = slot;
+        } else {
+          HIP_OK(hipEventRecord(b->poll_ev[blk & 1], s));
+          if (pending >= 0) {
+            HIP_OK(hipEventSynchronize(b->poll_ev[pending & 1]));
+            check = b->h_flags + (size_t)(pending & 1) * nt * FL_COUNT;
+          }
+          pending = blk;
+        }
+        if (check) {
+          bool all = true;
+          for (int t = 0; t < nt; ++t) all = all && check[t * FL_COUNT + FL_DONE];
+          if (all) break;
+        }
       }
     }
     for (int t = 0; t < nt; ++t) launch_finalize_rr(ht[t].st, ht[t].st_nblk, s);
@@ -1195,6 +1337,7 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec) {
   p->cg_eps_tol = 1e-3;
   p->cg_alpha = 1.7;
   p->sd_guard = IRLSU_GUARD_CHECK;
+  p->graph = 1;
   return IRLSU_OK;
 }
 
@@ -1321,12 +1464,27 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     return IRLSU_ERR_HIP;
   }
   p->ws_bytes = layout(p).total;
+  // the capture stream of the PCG graphs; without it the loop launches
+  // directly (irlsu_params.graph is then ignored)
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    p->cap_stream = nullptr;
+  }
+  for (hipEvent_t& e : p->poll_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+    }
+  }
   *out = p;
   return IRLSU_OK;
 }
 
 irlsu_status irlsu_plan_destroy(irlsu_plan* p) {
   if (!p) return IRLSU_OK;
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipEvent_t e : p->poll_ev)
+    if (e) (void)hipEventDestroy(e);
   if (p->prof) {
     for (int i = 0; i <= LaunchLog::kMax; ++i) (void)hipEventDestroy(p->prof->ev[i]);
     delete p->prof;
@@ -1646,6 +1804,22 @@ irlsu_status irlsu_pcg(irlsu_plan* plan, const void* Ov, const void* Oh, const v
   return solve_st;
 }
 
+irlsu_status irlsu_stream_probe(int32_t kind, const void* a, const void* b, const void* c, void* d,
+                                size_t bytes, int32_t grid, int32_t reps, double* ms,
+                                void* stream) {
+  if (kind < IRLSU_PROBE_COPY || kind > IRLSU_PROBE_3R1W || !a || !ms || grid < 1 || reps < 1 ||
+      bytes < 16 || bytes % 16 != 0)
+    return IRLSU_ERR_INVALID_ARG;
+  if (kind != IRLSU_PROBE_READ && !d) return IRLSU_ERR_INVALID_ARG;
+  if (kind == IRLSU_PROBE_3R1W && (!b || !c)) return IRLSU_ERR_INVALID_ARG;
+  float t = 0.f;
+  if (launch_stream_probe(kind, a, b, c, d, bytes, grid, reps, &t,
+                          static_cast<hipStream_t>(stream)) != 0)
+    return IRLSU_ERR_HIP;
+  *ms = (double)t;
+  return IRLSU_OK;
+}
+
 irlsu_status irlsu_precond_timed(const irlsu_plan* plan, const void* r, void* z, void* workspace,
                                  size_t workspace_bytes, int32_t reps, double* ms_launch,
                                  int32_t* kind, int32_t* n_launches, void* stream) {
@@ -1803,6 +1977,9 @@ irlsu_status irlsu_unwrap_augmented(irlsu_plan* plan, const void* X, int64_t ldx
 
 irlsu_status irlsu_batch_destroy(irlsu_batch* b) {
   if (!b) return IRLSU_OK;
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (hipEvent_t e : b->poll_ev)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : b->P) if (p) (void)hipFree(p);
   for (void* p : b->Pt) if (p) (void)hipFree(p);
   for (double* p : b->eig) if (p) (void)hipFree(p);
@@ -1896,7 +2073,7 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
   ok = ok && dev_malloc(&b->d_tiles, (size_t)ntiles * sizeof(BatchTile<float>)) == hipSuccess;
   ok = ok && pinned_malloc(&b->h_tiles, (size_t)ntiles * sizeof(BatchTile<float>),
                            hipHostMallocDefault) == hipSuccess;
-  ok = ok && pinned_malloc(reinterpret_cast<void**>(&b->h_flags), (size_t)ntiles * FL_COUNT * 4,
+  ok = ok && pinned_malloc(reinterpret_cast<void**>(&b->h_flags), (size_t)ntiles * FL_COUNT * 8,
                            hipHostMallocDefault) == hipSuccess;
   ok = ok && pinned_malloc(reinterpret_cast<void**>(&b->h_sc), (size_t)ntiles * SC_COUNT * 8,
                            hipHostMallocDefault) == hipSuccess;
@@ -1912,6 +2089,16 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
       hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     irlsu_batch_destroy(b);
     return IRLSU_ERR_HIP;
+  }
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    b->cap_stream = nullptr;
+  }
+  for (hipEvent_t& e : b->poll_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+    }
   }
   *out = b;
   return IRLSU_OK;

@@ -130,6 +130,10 @@ template <class T> int launch_sumsq(const T* x, int64_t n, DevState st, hipStrea
 
 template <class T> int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s);
 
+// streaming bandwidth probe (kind 0 copy, 1 read, 2 three reads + one write)
+int launch_stream_probe(int kind, const void* a, const void* b, const void* c, void* d,
+                        size_t bytes, int grid, int reps, float* ms, hipStream_t s);
+
 template <class T>
 __device__ __forceinline__ StencilArgs<T> batch_stencil_args(const BatchTile<T>& bt, int mode,
                                                             int iter, int flexible, int check_done) {

@@ -195,7 +195,7 @@ __device__ __forceinline__ void axpy_body(const AxpyArgs<T>& a, int lb, int nb) 
   if (lb == 0 && threadIdx.x == 0) {
     a.st.sc[SC_ALPHA + (a.iter & 1)] = alpha;
     a.st.sc[SC_PQ] = pq;
-    a.st.fl[FL_ITERS] = a.iter + 1;
+    a.st.fl[FL_ITERS] += 1;  // counted on the device: iteration-independent launches
   }
   const T al = (T)alpha;
   double acc[2] = {0.0, 0.0};

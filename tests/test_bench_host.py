@@ -24,17 +24,21 @@ def test_fast_form_table_and_dominant_kernel():
     assert roof["peak"] == 8000.0
 
 
-def test_folded_form_reports_dense_equivalent_and_executed():
+def test_folded_form_rated_on_executed_flops():
+    """The folded form executes 2NM(N+M) per application (half the dense
+    4NM(N+M)); achieved and frac follow the executed flops, the dense
+    equivalent is a side field."""
     N = M = 8192
     launches = ([("stencil", 0.35), ("axpy", 0.36), ("prologue", 0.004), ("butterfly", 0.05)]
                 + [("product", 0.4)] * 8 + [("dots", 0.1)])
     kern = bench.kernel_table(launches, "bf16", "folded", N, M, flexible=True)
     roof = bench.roofline(kern, "bf16")
     assert roof["kernel"] == "gemm_nt_kernel" and roof["bound"] == "mfma"
-    dense = 4.0 * N * M * (N + M) / 8
-    assert roof["flops_per_launch"] == dense
-    assert abs(roof["achieved"] - dense / 0.4e-3 / 1e12) < 0.01
-    assert abs(roof["executed_TFLOPs"] - roof["achieved"] / 2) < 0.01
+    executed = 2.0 * N * M * (N + M) / 8
+    assert roof["flops_per_launch"] == executed
+    assert abs(roof["achieved"] - executed / 0.4e-3 / 1e12) < 0.01
+    assert abs(roof["frac"] - roof["achieved"] / 2500.0) < 1e-4
+    assert abs(roof["dense_equivalent_TFLOPs"] - 2 * roof["achieved"]) < 0.02
 
 
 def test_f64_bytes_double():
