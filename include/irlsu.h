@@ -332,6 +332,51 @@ irlsu_status irlsu_adjoint_implicit(irlsu_plan* plan, const void* gU, int64_t ld
                                     void* workspace, size_t workspace_bytes,
                                     irlsu_stats* stats, void* stream);
 
+/* ---- Launch-shape autotuner ------------------------------------------- */
+
+/* Launch shapes of a plan.  0 everywhere: the library's default rules. */
+typedef struct irlsu_tune {
+  int32_t stencil_rows;   /* rows of the image per operator workgroup (its band height) */
+  int32_t update_blocks;  /* workgroups of the CG update (at most the operator's) */
+  int32_t small_tiles;    /* 16-bit MFMA products: 1 = 128 x 128 tiles, 0 = 256 x 256 where
+                             they divide the padded sides */
+  int32_t from_cache;     /* out: 1 if the shapes came from the cache file */
+  double stencil_us;      /* out: measured time of the chosen shapes, microseconds */
+  double update_us;
+  double precond_us;      /* 16-bit MFMA forms only, else 0 */
+} irlsu_tune;
+
+/* Choose the launch shapes of a plan by measurement: every candidate band
+ * height of the operator (8 .. 256 rows), update block count (64 .. 4096)
+ * and, for 16-bit MFMA forms, product tile, timed with HIP events on
+ * `stream` on the plan's workspace (its contents are overwritten); the
+ * fastest of each is applied to the plan.  With cache_path non-NULL the
+ * choice is first looked up in that JSON file, keyed by N, M, precision,
+ * form and the GPU's architecture name, and a new measurement is stored
+ * there (the file is rewritten whole).  Results of the solves do not
+ * depend on the shapes beyond the summation order of the FP64 partial
+ * sums.  Synchronises the stream.  out (host, nullable) gets the choice.
+ * Errors: ERR_INVALID_ARG (null plan, or the cache file cannot be written),
+ * ERR_WORKSPACE, ERR_HIP. */
+irlsu_status irlsu_plan_autotune(irlsu_plan* plan, const char* cache_path, irlsu_tune* out,
+                                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Force a plan's launch shapes (NULL: back to the default rules).  Errors:
+ * ERR_INVALID_ARG (null plan, negative fields, small_tiles not 0 or 1). */
+irlsu_status irlsu_plan_set_tune(irlsu_plan* plan, const irlsu_tune* tune);
+
+/* The plan's current launch shapes (0: default rule).  Errors:
+ * ERR_INVALID_ARG. */
+irlsu_status irlsu_plan_get_tune(const irlsu_plan* plan, irlsu_tune* out);
+
+/* The batch's operator band heights, one per distinct tile shape, chosen by
+ * measurement of each tile's operator alone (cached like
+ * irlsu_plan_autotune's, as kind "batch_tile"); the grouped launches then
+ * use them.  The workspace's contents are overwritten.  Errors:
+ * ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP. */
+irlsu_status irlsu_batch_autotune(irlsu_batch* batch, const char* cache_path, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
 /* ---- Step-level entry points (internal layout, see top of file) -------- */
 
 /* Setup (Section 2): Gv, Gh = wrapped differences W(d) = d - 2 pi

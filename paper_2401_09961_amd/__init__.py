@@ -36,6 +36,7 @@ DECLARED_SYMBOLS = (
     "irlsu_unwrap_augmented", "irlsu_batch_create", "irlsu_batch_destroy",
     "irlsu_batch_workspace_bytes", "irlsu_unwrap_batched", "irlsu_pcg",
     "irlsu_test_fail_alloc", "irlsu_operator_noalloc", "irlsu_stream_probe",
+    "irlsu_plan_autotune", "irlsu_plan_set_tune", "irlsu_plan_get_tune", "irlsu_batch_autotune",
 )
 
 STATUS = {
@@ -106,6 +107,16 @@ class Tile(ctypes.Structure):
                 ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("stencil_rows", ctypes.c_int32), ("update_blocks", ctypes.c_int32),
+                ("small_tiles", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("stencil_us", ctypes.c_double), ("update_us", ctypes.c_double),
+                ("precond_us", ctypes.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64),
                 ("Np", ctypes.c_int64), ("ld", ctypes.c_int64),
@@ -163,6 +174,10 @@ def load_library():
         "irlsu_operator": (I32, [P, P, P, P, P, P, P, SZ, P]),
         "irlsu_operator_noalloc": (I32, [P, P, P, P, P, P, P]),
         "irlsu_stream_probe": (I32, [I32, P, P, P, P, SZ, I32, I32, ctypes.POINTER(D), P]),
+        "irlsu_plan_autotune": (I32, [P, ctypes.c_char_p, ctypes.POINTER(Tune), P, SZ, P]),
+        "irlsu_plan_set_tune": (I32, [P, ctypes.POINTER(Tune)]),
+        "irlsu_plan_get_tune": (I32, [P, ctypes.POINTER(Tune)]),
+        "irlsu_batch_autotune": (I32, [P, ctypes.c_char_p, P, SZ, P]),
         "irlsu_precond": (I32, [P, P, P, P, P, SZ, P]),
         "irlsu_pcg": (I32, [P, P, P, P, P, ctypes.POINTER(Params), ctypes.POINTER(I32),
                             ctypes.POINTER(D), P, SZ, P]),
@@ -398,6 +413,24 @@ class Plan:
                "precond")
         return z, rz
 
+    def autotune(self, cache_path=None):
+        """Measure and apply the fastest launch shapes (cached in the JSON
+        file cache_path when given); returns the choice as a dict."""
+        t = Tune()
+        path = None if cache_path is None else os.fsencode(str(cache_path))
+        _check(self.lib.irlsu_plan_autotune(self.handle, path, ctypes.byref(t), _ptr(self.workspace),
+                                            self.workspace.numel(), _stream()), "plan_autotune")
+        return t.to_dict()
+
+    def set_tune(self, stencil_rows=0, update_blocks=0, small_tiles=0):
+        t = Tune(stencil_rows, update_blocks, small_tiles, 0, 0.0, 0.0, 0.0)
+        _check(self.lib.irlsu_plan_set_tune(self.handle, ctypes.byref(t)), "plan_set_tune")
+
+    def get_tune(self):
+        t = Tune()
+        _check(self.lib.irlsu_plan_get_tune(self.handle, ctypes.byref(t)), "plan_get_tune")
+        return t.to_dict()
+
     def pcg(self, Ov, Oh, b, x=None, *, params: Optional[Params] = None):
         """Algorithm 2 on D^T Omega D x = b (internal layout; x FP64, warm
         start in / solution out).  Returns (x, status code, iterations,
@@ -509,6 +542,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, cache_path=None):
+        """Measured operator band heights per tile shape (cached in the JSON
+        file cache_path when given)."""
+        path = None if cache_path is None else os.fsencode(str(cache_path))
+        _check(self.lib.irlsu_batch_autotune(self.handle, path, _ptr(self.workspace),
+                                             self.workspace.numel(), _stream()), "batch_autotune")
 
     def unwrap(self, Xs, weights=None, *, params: Optional[Params] = None, stats: bool = False):
         import torch

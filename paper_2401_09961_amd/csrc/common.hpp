@@ -80,10 +80,11 @@ struct DevState {
 };
 
 // Row of partial sums of one slot for this problem: part[slot * stride + off ..].
-__device__ __forceinline__ double* part_row(const DevState& st, int slot) {
+__host__ __device__ __forceinline__ double* part_row(const DevState& st, int slot) {
   const size_t stride = st.stride > 0 ? (size_t)st.stride : (size_t)kMaxPartials;
   return st.part + (size_t)slot * stride + st.off;
 }
+inline double* part_row_host(const DevState& st, int slot) { return part_row(st, slot); }
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll

@@ -101,6 +101,7 @@ struct GemmCtl {
   int nparts_rr;
   int scale_in;     // G1 (FP16 operands): scale r by s = 1e-3 sqrt(N M / ||r||^2)
   int64_t npix;     // N M of the problem (for the scale)
+  int small_tiles = 0;  // host-side choice of the tile configuration (not read by kernels)
 };
 
 // Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
@@ -439,7 +440,7 @@ static int gemm(const AT* A, int64_t lda, const OT* B, int64_t ldb, int64_t Mg, 
                 int64_t K, float ascale, const Epi& epi, const GemmCtl& ctl, hipStream_t s) {
   if constexpr (sizeof(OT) == 2 && kBig) {
     using CB = CfgBig16;
-    if (Mg % CB::BM == 0 && Ng % CB::BN == 0 && K % CB::BK == 0) {
+    if (!ctl.small_tiles && Mg % CB::BM == 0 && Ng % CB::BN == 0 && K % CB::BK == 0) {
       const int ntm = (int)(Mg / CB::BM), ntn = (int)(Ng / CB::BN);
       hipLaunchKernelGGL((gemm_nt_kernel<OT, AT, CB, Epi>), dim3(ntm * ntn), dim3(CB::THREADS), 0,
                          s, A, lda, B, ldb, K, ntm, ntn, 4, ascale, epi, ctl);
@@ -465,8 +466,8 @@ static int precond_impl(const PrecondArgs& a, hipStream_t s) {
   OT* T3 = static_cast<OT*>(a.T3);
   const T* r = static_cast<const T*>(a.r);
   const int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
-  GemmCtl c1{a.st, 1, a.check_conv, a.nparts_rr, f16, a.N * a.M};
-  GemmCtl cn{a.st, 1, 0, 0, 0, 0};
+  GemmCtl c1{a.st, 1, a.check_conv, a.nparts_rr, f16, a.N * a.M, a.small_tiles};
+  GemmCtl cn{a.st, 1, 0, 0, 0, 0, a.small_tiles};
   LaunchLog* L = a.log;
   log_start(L, s);
   // G1: T1^T = (r P_M)^T
@@ -527,7 +528,7 @@ static int precond_folded_impl(const PrecondArgs& a, hipStream_t s) {
   const T* r = static_cast<const T*>(a.r);
   const int f16 = std::is_same<OT, _Float16>::value ? 1 : 0;
   const int32_t* done = a.st.fl + FL_DONE;
-  GemmCtl cn{a.st, 1, 0, 0, 0, 0};
+  GemmCtl cn{a.st, 1, 0, 0, 0, 0, a.small_tiles};
   LaunchLog* L = a.log;
   auto prod = [&]() { log_mark(L, IRLSU_LK_PRODUCT, s); };
   auto pass = [&]() { log_mark(L, IRLSU_LK_BUTTERFLY, s); };
@@ -594,19 +595,25 @@ int launch_precond(const PrecondArgs& a, hipStream_t s) {
 
 // ---- grouped products over the tiles of a batch ------------------------
 // The configuration of each product is fixed per launch: tiles are padded to
-// multiples of 256 so that G1..G3 use the 256 x 256 tile, G4 the 128 x 128.
+// multiples of 256, so 16-bit operands use the 256 x 256 tile and FP32
+// operands the 128 x 128 one throughout.  Tiles in the fast form have no
+// blocks here (their preconditioner runs its own passes).
 template <class OT, int G>
 struct BatchCfg {
   using type = CfgBig16;
 };
-
 template <int G>
+struct BatchCfg<float, G> {
+  using type = CfgF32;
+};
+
+template <class OT>
 constexpr int batch_threads() {
-  return CfgBig16::THREADS;
+  return BatchCfg<OT, 1>::type::THREADS;
 }
 
 template <class OT, class T, int G>
-__global__ __launch_bounds__(batch_threads<G>()) void gemm_batched_kernel(
+__global__ __launch_bounds__(batch_threads<OT>()) void gemm_batched_kernel(
     const BatchTile<T>* tiles, const int32_t* start, int ntiles, int check_conv) {
   using C = typename BatchCfg<OT, G>::type;
   const int t = find_tile(start, ntiles, (int)blockIdx.x);
@@ -635,8 +642,7 @@ __global__ __launch_bounds__(batch_threads<G>()) void gemm_batched_kernel(
 }
 
 void precond_blocks(int kind, int64_t Np, int64_t Mp, int out[4]) {
-  (void)kind;
-  const int64_t B = CfgBig16::BM;
+  const int64_t B = kind == OK_F32 ? CfgF32::BM : CfgBig16::BM;
   out[0] = (int)((Np / B) * (Mp / B));
   out[1] = (int)((Mp / B) * (Np / B));
   out[2] = out[1];
@@ -650,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void zdots_batched_kernel(const BatchTile
                                                                  const int32_t* start, int ntiles) {
   const int t = find_tile(start, ntiles, (int)blockIdx.x);
   const BatchTile<T>& bt = tiles[t];
-  if (bt.st.fl[FL_DONE]) return;
+  if (bt.fast || bt.st.fl[FL_DONE]) return;
   zdots_body<T>(bt.z, bt.r, bt.flexible_q ? bt.q : nullptr, bt.Np * bt.ld, bt.st,
                 (int)blockIdx.x - start[t], bt.st_nblk);
 }
@@ -659,24 +665,29 @@ template <class OT>
 static void precond_batched_impl(const BatchTile<float>* tiles, const int32_t* starts, int ntiles,
                                  const int* totals, int check_conv, hipStream_t s) {
   const int n1 = ntiles + 1;
-  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 1>), dim3(totals[0]),
-                     dim3(BatchCfg<OT, 1>::type::THREADS), 0, s, tiles, starts, ntiles, check_conv);
-  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 2>), dim3(totals[1]),
-                     dim3(BatchCfg<OT, 2>::type::THREADS), 0, s, tiles, starts + n1, ntiles, 0);
-  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 3>), dim3(totals[2]),
-                     dim3(BatchCfg<OT, 3>::type::THREADS), 0, s, tiles, starts + 2 * n1, ntiles, 0);
-  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 4>), dim3(totals[3]),
-                     dim3(BatchCfg<OT, 4>::type::THREADS), 0, s, tiles, starts + 3 * n1, ntiles, 0);
+  constexpr int TH = batch_threads<OT>();
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 1>), dim3(totals[0]), dim3(TH), 0, s, tiles,
+                     starts, ntiles, check_conv);
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 2>), dim3(totals[1]), dim3(TH), 0, s, tiles,
+                     starts + n1, ntiles, 0);
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 3>), dim3(totals[2]), dim3(TH), 0, s, tiles,
+                     starts + 2 * n1, ntiles, 0);
+  hipLaunchKernelGGL((gemm_batched_kernel<OT, float, 4>), dim3(totals[3]), dim3(TH), 0, s, tiles,
+                     starts + 3 * n1, ntiles, 0);
 }
 
 void launch_precond_batched(int kind, const void* tiles, const int32_t* starts, int ntiles,
                             const int* totals, int check_conv, const int32_t* st_start,
                             int st_total, hipStream_t s) {
   const BatchTile<float>* t = static_cast<const BatchTile<float>*>(tiles);
-  if (kind == OK_F16)
-    precond_batched_impl<_Float16>(t, starts, ntiles, totals, check_conv, s);
-  else
-    precond_batched_impl<__bf16>(t, starts, ntiles, totals, check_conv, s);
+  if (totals[0] > 0) {  // no grouped products when every tile is in the fast form
+    if (kind == OK_F16)
+      precond_batched_impl<_Float16>(t, starts, ntiles, totals, check_conv, s);
+    else if (kind == OK_F32)
+      precond_batched_impl<float>(t, starts, ntiles, totals, check_conv, s);
+    else
+      precond_batched_impl<__bf16>(t, starts, ntiles, totals, check_conv, s);
+  }
   hipLaunchKernelGGL(zdots_batched_kernel<float>, dim3(st_total), dim3(kThreads), 0, s, t, st_start,
                      ntiles);
 }

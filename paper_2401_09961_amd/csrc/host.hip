@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "tune.hpp"
 
 using namespace irlsu;
 
@@ -45,6 +46,9 @@ struct irlsu_plan {
   // timing aid: events of one armed PCG iteration (irlsu_profile_arm)
   int prof_k = -1, prof_l = -1;
   LaunchLog* prof = nullptr;
+  // tuned launch shapes (0: the default rules): stencil band rows, blocks of
+  // the CG update, 128 x 128 product tiles for 16-bit operands
+  int tune_rows = 0, tune_update = 0, tune_small = 0;
   // stream on which PCG iterations are captured into graphs (non-blocking,
   // default priority); null when it could not be created
   hipStream_t cap_stream = nullptr;
@@ -63,6 +67,12 @@ struct irlsu_batch {
   int32_t ntiles = 0;
   irlsu_precision prec = IRLSU_MIXED_BF16;
   int kind = OK_BF16;
+  size_t opsz = 2;                 // preconditioner operand / intermediate bytes
+  std::vector<int> fast;           // per tile: fast-form preconditioner (sides powers of two)
+  // twiddle and FP64 eigenvalue tables per side length of the fast tiles
+  std::map<int64_t, int> fast_side_index;
+  std::vector<void*> tw;
+  std::vector<double*> eigf;
   std::vector<int64_t> N, M, Np, Mp;
   // basis tables per distinct side length
   std::map<int64_t, int> side_index;
@@ -276,6 +286,7 @@ PrecondArgs precond_args(const irlsu_plan* pl, const Ws<T>& W, const T* r, T* z,
   a.fast = pl->fast;
   a.twN = pl->twN;
   a.twM = pl->twM;
+  a.small_tiles = pl->tune_small;
   return a;
 }
 
@@ -289,15 +300,22 @@ StencilArgs<T> stencil_base(const irlsu_plan* pl, const T* Ov, const T* Oh, DevS
   a.M = pl->M;
   a.Np = pl->Np;
   a.ld = pl->Mp;
+  a.rows = pl->tune_rows;
   a.st = st;
   return a;
 }
 
-// Axpy grid: exactly as many blocks as the residual stencil, so that both
-// producers of the ||r||^2 partials write the same count.
+// Blocks of the CG update (axpy): the tuned count, at most the stencil's
+// (the consumers read that many ||r||^2 partials, zero padded).
+int update_blocks(const irlsu_plan* pl, int nvec) {
+  if (pl->tune_update > 0) return std::min(pl->tune_update, nvec);
+  return axpy_blocks(nvec);
+}
+
+// Blocks of the stencil (also the partial count of the residual producers).
 int stencil_blocks(const irlsu_plan* pl) {
   int rows = 0;
-  const dim3 g = stencil_grid(pl->Np, pl->Mp, &rows);
+  const dim3 g = stencil_grid(pl->Np, pl->Mp, &rows, pl->tune_rows);
   return (int)(g.x * g.y);
 }
 
@@ -445,7 +463,7 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
     xa.nparts_out = nrr;
     xa.iter = l;
     xa.st = st;
-    launch_axpy<T>(xa, q, axpy_blocks(nvec));
+    launch_axpy<T>(xa, q, update_blocks(pl, nvec));
     log_mark(L, IRLSU_LK_AXPY, q);
     if (refresh) {
       // the correction so far moves into the FP64 iterate before the true
@@ -822,10 +840,16 @@ irlsu_status adjoint_impl(irlsu_plan* pl, const T* gU, int64_t ldg, const irlsu_
 constexpr int64_t kBatchPad = 256;
 constexpr int kBatchVecs = 12;  // r z p0 p1 q b Gv Gh Cv Ch Ov Oh
 
-size_t batch_tile_bytes(int64_t Np, int64_t Mp) {
+size_t batch_tile_bytes(int64_t Np, int64_t Mp, size_t opsz) {
   const size_t npx = (size_t)Np * (size_t)Mp;
   return align_up(npx * sizeof(double)) + kBatchVecs * align_up(npx * sizeof(float)) +
-         3 * align_up(npx * 2);
+         3 * align_up(npx * opsz);
+}
+
+// A tile runs the fast form when both sides are powers of two that the fast
+// transforms take and that the batch padding leaves unpadded.
+bool batch_tile_fast(int64_t N, int64_t M) {
+  return fct_supported(N) && fct_supported(M) && N % kBatchPad == 0 && M % kBatchPad == 0;
 }
 
 struct TileWs {
@@ -845,9 +869,9 @@ TileWs carve_tile(const irlsu_batch* b, void* base, int t) {
     p += align_up(npx * sizeof(float));
   }
   w.T1 = p;
-  p += align_up(npx * 2);
+  p += align_up(npx * b->opsz);
   w.T2 = p;
-  p += align_up(npx * 2);
+  p += align_up(npx * b->opsz);
   w.T3 = p;
   return w;
 }
@@ -926,17 +950,22 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
     bt.st_nblk = b->st_nblk[t];
     bt.g4_nparts = b->g4_nparts[t];
     bt.flexible_q = 0;
-    bt.pad_ = 0;
+    bt.fast = b->fast[t];
     bt.T1 = w.T1;
     bt.T2 = w.T2;
     bt.T3 = w.T3;
-    const int in = b->side_index.at(b->N[t]), im = b->side_index.at(b->M[t]);
-    bt.PN = b->P[in];
-    bt.PNt = b->Pt[in];
-    bt.PM = b->P[im];
-    bt.PMt = b->Pt[im];
-    bt.eigN = b->eig[in];
-    bt.eigM = b->eig[im];
+    if (b->fast[t]) {
+      bt.PN = bt.PNt = bt.PM = bt.PMt = nullptr;
+      bt.eigN = bt.eigM = nullptr;
+    } else {
+      const int in = b->side_index.at(b->N[t]), im = b->side_index.at(b->M[t]);
+      bt.PN = b->P[in];
+      bt.PNt = b->Pt[in];
+      bt.PM = b->P[im];
+      bt.PMt = b->Pt[im];
+      bt.eigN = b->eig[in];
+      bt.eigM = b->eig[im];
+    }
   }
   if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
   irlsu_status rs = batch_read_back(b, ws, s);
@@ -947,9 +976,42 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
   }
   const int flexible = prm.flexible < 0 ? 1 : prm.flexible;
   for (int t = 0; t < nt; ++t) ht[t].flexible_q = flexible;
+  // the fast-form tiles' own preconditioner launches (the single-image
+  // passes on the tile's vectors; z with its dots folded into one partial)
+  std::vector<PrecondArgs> fastp;
+  for (int t = 0; t < nt; ++t) {
+    if (!b->fast[t]) continue;
+    const BatchTile<float>& bt = ht[t];
+    PrecondArgs a{};
+    a.kind = b->kind;
+    a.N = bt.N;
+    a.M = bt.M;
+    a.Np = bt.Np;
+    a.Mp = bt.ld;
+    a.T1 = bt.T1;
+    a.T2 = bt.T2;
+    a.T3 = bt.T3;
+    a.r = bt.r;
+    a.z = bt.z;
+    a.q = flexible ? bt.q : nullptr;
+    a.check_conv = 1;
+    a.nparts_rr = bt.st_nblk;
+    a.st = bt.st;
+    a.fast = 1;
+    a.twN = b->tw[b->fast_side_index.at(bt.N)];
+    a.twM = b->tw[b->fast_side_index.at(bt.M)];
+    a.eigN = b->eigf[b->fast_side_index.at(bt.N)];
+    a.eigM = b->eigf[b->fast_side_index.at(bt.M)];
+    fastp.push_back(a);
+  }
   HIP_OK(hipMemcpyAsync(b->d_tiles, b->h_tiles, (size_t)nt * sizeof(BatchTile<float>),
                         hipMemcpyHostToDevice, s));
   const BatchTile<float>* dt = static_cast<const BatchTile<float>*>(b->d_tiles);
+  auto precond_all = [&](hipStream_t q) {
+    launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
+                           b->st_total, q);
+    for (const PrecondArgs& a : fastp) launch_precond(a, q);
+  };
   const double tol2 = prm.pcg_rtol * prm.pcg_rtol;
   std::vector<int> pcg_total(nt, 0);
   std::vector<irlsu_status> overall(nt, IRLSU_OK);
@@ -990,8 +1052,7 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
       }
     }
     launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, 0, flexible, 0, s);
-    launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
-                           b->st_total, s);
+    precond_all(s);
     // one PCG step over all tiles: grouped stencil, update, refresh,
     // preconditioner products; replayed from captured graphs for l >= 1
     // (the arguments depend on l only through its parity, the refresh and
@@ -1003,9 +1064,7 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
       if (prm.true_res_every > 0 && (l + 1) % prm.true_res_every == 0 && l + 1 < prm.pcg_max)
         launch_stencil_batched<float>(ST_RESID, dt, b->d_st_start, nt, b->st_total, l, flexible, 1,
                                       q);
-      if (l + 1 < prm.pcg_max)
-        launch_precond_batched(b->kind, dt, b->d_g_start, nt, b->g_total, 1, b->d_st_start,
-                               b->st_total, q);
+      if (l + 1 < prm.pcg_max) precond_all(q);
     };
     // blocks of iterations between polls, as in the single-image loop
     // (graphs for the blocks after the first; each poll read one block
@@ -1101,6 +1160,46 @@ irlsu_status unwrap_batched_impl(irlsu_batch* b, const irlsu_tile* tiles, const 
   if (last_launch() != IRLSU_OK) return IRLSU_ERR_HIP;
   if (stats) HIP_OK(hipStreamSynchronize(s));
   return worst;
+}
+
+// Stencil grids of the tiles (band rows: rows[t], 0 for the default rule),
+// the partial-sum ranges they imply and the block prefix st_start; returns
+// the partials the batch needs (at most kMaxPartials for a valid layout).
+int64_t batch_grids(irlsu_batch* b, const std::vector<int>& rows, std::vector<int32_t>& st_start) {
+  const int nt = b->ntiles;
+  b->st_gx.assign(nt, 0);
+  b->st_rows.assign(nt, 0);
+  b->st_nblk.assign(nt, 0);
+  b->g4_nparts.assign(nt, 0);
+  b->part_off.assign(nt, 0);
+  st_start.assign(nt + 1, 0);
+  int64_t part = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t N = b->N[t], M = b->M[t], Np = b->Np[t], Mp = b->Mp[t];
+    int r = 0;
+    const dim3 g = stencil_grid(Np, Mp, &r, rows[t]);
+    const int32_t nblk = (int32_t)(g.x * g.y);
+    b->st_gx[t] = (int32_t)g.x;
+    b->st_rows[t] = r;
+    b->st_nblk[t] = nblk;
+    // partials of z . r etc. that the stencil reads: the grouped dots kernel
+    // writes one per stencil block; the fast passes fold theirs into one
+    b->g4_nparts[t] = b->fast[t] ? 1 : nblk;
+    int gb[4] = {0, 0, 0, 0};
+    if (!b->fast[t]) precond_blocks(b->kind, Np, Mp, gb);
+    int wrows = 1;
+    const dim3 wg = weights_grid(Np, Mp, &wrows);
+    const int32_t need = std::max({nblk, gb[3], (int32_t)(wg.x * wg.y),
+                                   (int32_t)elementwise_blocks(Np * Mp),
+                                   b->fast[t] ? (int32_t)std::max(fct_row_blocks(N, M),
+                                                                  fct_row_blocks(M, N))
+                                              : 0});
+    b->part_off[t] = (int32_t)part;
+    part += need;
+    st_start[t + 1] = st_start[t] + nblk;
+  }
+  b->st_total = st_start[nt];
+  return part;
 }
 
 irlsu_status check_ws(const irlsu_plan* pl, const void* ws, size_t bytes) {
@@ -1706,7 +1805,7 @@ irlsu_status irlsu_operator_noalloc(const irlsu_plan* plan, const void* Ov, cons
   if (!plan || !Ov || !Oh || !p || !q) return IRLSU_ERR_INVALID_ARG;
   if (p == q) return IRLSU_ERR_INVALID_ARG;
   int rows = 0;
-  const dim3 g = stencil_grid(plan->Np, plan->Mp, &rows);
+  const dim3 g = stencil_grid(plan->Np, plan->Mp, &rows, plan->tune_rows);
   if ((int64_t)g.x * (int64_t)g.y > kNoAllocParts) return IRLSU_ERR_SHAPE;
   int dev = -1;
   HIP_OK(hipGetDevice(&dev));
@@ -1983,6 +2082,8 @@ irlsu_status irlsu_batch_destroy(irlsu_batch* b) {
   for (void* p : b->P) if (p) (void)hipFree(p);
   for (void* p : b->Pt) if (p) (void)hipFree(p);
   for (double* p : b->eig) if (p) (void)hipFree(p);
+  for (void* p : b->tw) if (p) (void)hipFree(p);
+  for (double* p : b->eigf) if (p) (void)hipFree(p);
   if (b->d_st_start) (void)hipFree(b->d_st_start);
   if (b->d_g_start) (void)hipFree(b->d_g_start);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
@@ -1997,7 +2098,8 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
                                 irlsu_precision prec, void* stream) {
   if (!out || !shapes || ntiles < 1) return IRLSU_ERR_INVALID_ARG;
   *out = nullptr;
-  if (prec != IRLSU_MIXED_BF16 && prec != IRLSU_MIXED_F16) return IRLSU_ERR_UNSUPPORTED;
+  if (prec != IRLSU_MIXED_BF16 && prec != IRLSU_MIXED_F16 && prec != IRLSU_F32)
+    return IRLSU_ERR_UNSUPPORTED;
   for (int t = 0; t < ntiles; ++t)
     if (shapes[2 * t] < 2 || shapes[2 * t + 1] < 2 || shapes[2 * t] > kMaxSide ||
         shapes[2 * t + 1] > kMaxSide)
@@ -2007,9 +2109,9 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
   hipStream_t s = static_cast<hipStream_t>(stream);
   b->ntiles = ntiles;
   b->prec = prec;
-  b->kind = prec == IRLSU_MIXED_F16 ? OK_F16 : OK_BF16;
-  std::vector<int32_t> st_start(ntiles + 1, 0), g_start(4 * (ntiles + 1), 0);
-  int32_t part = 0;
+  b->kind = prec == IRLSU_MIXED_F16 ? OK_F16 : (prec == IRLSU_F32 ? OK_F32 : OK_BF16);
+  b->opsz = prec == IRLSU_F32 ? 4 : 2;
+  std::vector<int32_t> st_start, g_start(4 * (ntiles + 1), 0);
   size_t off = 0;
   for (int t = 0; t < ntiles; ++t) {
     const int64_t N = shapes[2 * t], M = shapes[2 * t + 1];
@@ -2018,33 +2120,29 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
     b->M.push_back(M);
     b->Np.push_back(Np);
     b->Mp.push_back(Mp);
-    int rows = 0;
-    const dim3 g = stencil_grid(Np, Mp, &rows);
-    b->st_gx.push_back((int32_t)g.x);
-    b->st_rows.push_back(rows);
-    b->st_nblk.push_back((int32_t)(g.x * g.y));
     int gb[4];
-    precond_blocks(b->kind, Np, Mp, gb);
-    b->g4_nparts.push_back((int32_t)(g.x * g.y));
-    int wrows = 1;
-    const dim3 wg = weights_grid(Np, Mp, &wrows);
-    const int32_t wblocks = (int32_t)(wg.x * wg.y);
-    const int32_t need = std::max({(int32_t)(g.x * g.y), gb[3], wblocks,
-                                   (int32_t)elementwise_blocks(Np * Mp)});
-    b->part_off.push_back(part);
-    part += need;
-    st_start[t + 1] = st_start[t] + (int32_t)(g.x * g.y);
+    const bool fast = batch_tile_fast(N, M);
+    b->fast.push_back(fast ? 1 : 0);
+    if (fast) {
+      gb[0] = gb[1] = gb[2] = gb[3] = 0;  // no grouped products: its own passes
+    } else {
+      precond_blocks(b->kind, Np, Mp, gb);
+    }
     for (int q = 0; q < 4; ++q) g_start[q * (ntiles + 1) + t + 1] = g_start[q * (ntiles + 1) + t] + gb[q];
     b->tile_off.push_back(off);
-    off += align_up(batch_tile_bytes(Np, Mp));
-    b->side_index.emplace(N, 0);
-    b->side_index.emplace(M, 0);
+    off += align_up(batch_tile_bytes(Np, Mp, b->opsz));
+    if (fast) {
+      b->fast_side_index.emplace(N, 0);
+      b->fast_side_index.emplace(M, 0);
+    } else {
+      b->side_index.emplace(N, 0);
+      b->side_index.emplace(M, 0);
+    }
   }
-  if (part > kMaxPartials) {
+  if (batch_grids(b, std::vector<int>(ntiles, 0), st_start) > kMaxPartials) {
     irlsu_batch_destroy(b);
     return IRLSU_ERR_SHAPE;
   }
-  b->st_total = st_start[ntiles];
   for (int q = 0; q < 4; ++q) b->g_total[q] = g_start[q * (ntiles + 1) + ntiles];
   b->part_off_bytes = off;
   off = align_up(off + (size_t)kPartSlots * kMaxPartials * sizeof(double));
@@ -2060,13 +2158,25 @@ irlsu_status irlsu_batch_create(irlsu_batch** out, const int64_t* shapes, int32_
     const int64_t n = kv.first, npad = round_up(n, kBatchPad);
     void *P = nullptr, *Pt = nullptr;
     double* e = nullptr;
-    ok = ok && dev_malloc(&P, (size_t)npad * npad * 2) == hipSuccess;
-    ok = ok && dev_malloc(&Pt, (size_t)npad * npad * 2) == hipSuccess;
+    ok = ok && dev_malloc(&P, (size_t)npad * npad * b->opsz) == hipSuccess;
+    ok = ok && dev_malloc(&Pt, (size_t)npad * npad * b->opsz) == hipSuccess;
     ok = ok && dev_malloc(reinterpret_cast<void**>(&e), npad * sizeof(double)) == hipSuccess;
     b->P.push_back(P);
     b->Pt.push_back(Pt);
     b->eig.push_back(e);
     if (ok) launch_basis(b->kind, n, npad, P, Pt, e, s);
+  }
+  idx = 0;
+  for (auto& kv : b->fast_side_index) {
+    kv.second = idx++;
+    const int64_t n = kv.first;
+    void* tw = nullptr;
+    double* e = nullptr;
+    ok = ok && dev_malloc(&tw, fct_table_bytes(n, 4)) == hipSuccess;
+    ok = ok && dev_malloc(reinterpret_cast<void**>(&e), n * sizeof(double)) == hipSuccess;
+    b->tw.push_back(tw);
+    b->eigf.push_back(e);
+    if (ok) launch_fct_tables(4, n, tw, e, s);
   }
   ok = ok && dev_malloc(reinterpret_cast<void**>(&b->d_st_start), st_start.size() * 4) == hipSuccess;
   ok = ok && dev_malloc(reinterpret_cast<void**>(&b->d_g_start), g_start.size() * 4) == hipSuccess;
@@ -2127,3 +2237,251 @@ irlsu_status irlsu_unwrap_batched(irlsu_batch* b, const irlsu_tile* tiles,
 }
 
 }  // extern "C"
+
+// ---- autotuner -------------------------------------------------------------
+namespace {
+
+int plan_form(const irlsu_plan* p) {
+  return p->fast ? IRLSU_PLAN_FAST : (p->folded ? IRLSU_PLAN_FOLDED : IRLSU_PLAN_DENSE);
+}
+
+void put_tune(irlsu_tune* out, int rows, int upd, int small, int from_cache, double su, double uu,
+              double pu) {
+  if (!out) return;
+  out->stencil_rows = rows;
+  out->update_blocks = upd;
+  out->small_tiles = small;
+  out->from_cache = from_cache;
+  out->stencil_us = su;
+  out->update_us = uu;
+  out->precond_us = pu;
+}
+
+constexpr int kRowCands[] = {8, 16, 32, 64, 128, 256};
+constexpr int kUpdateCands[] = {64, 128, 256, 512, 1024, 2048, 4096};
+
+}  // namespace
+
+irlsu_status irlsu_plan_set_tune(irlsu_plan* plan, const irlsu_tune* t) {
+  if (!plan) return IRLSU_ERR_INVALID_ARG;
+  if (t && (t->stencil_rows < 0 || t->update_blocks < 0 || t->small_tiles < 0 ||
+            t->small_tiles > 1))
+    return IRLSU_ERR_INVALID_ARG;
+  plan->tune_rows = t ? t->stencil_rows : 0;
+  plan->tune_update = t ? t->update_blocks : 0;
+  plan->tune_small = t ? t->small_tiles : 0;
+  return IRLSU_OK;
+}
+
+irlsu_status irlsu_plan_get_tune(const irlsu_plan* plan, irlsu_tune* out) {
+  if (!plan || !out) return IRLSU_ERR_INVALID_ARG;
+  put_tune(out, plan->tune_rows, plan->tune_update, plan->tune_small, 0, 0.0, 0.0, 0.0);
+  return IRLSU_OK;
+}
+
+irlsu_status irlsu_plan_autotune(irlsu_plan* plan, const char* cache_path, irlsu_tune* out,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return IRLSU_ERR_INVALID_ARG;
+  irlsu_status st = check_ws(plan, workspace, workspace_bytes);
+  if (st != IRLSU_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TuneEntry key;
+  key.kind = "plan";
+  key.arch = device_arch(plan->device);
+  key.N = plan->N;
+  key.M = plan->M;
+  key.precision = plan->prec;
+  key.form = plan_form(plan);
+  std::vector<TuneEntry> cache = tune_cache_read(cache_path);
+  if (const TuneEntry* e = tune_cache_find(cache, key)) {
+    plan->tune_rows = e->stencil_rows;
+    plan->tune_update = e->update_blocks;
+    plan->tune_small = e->small_tiles;
+    put_tune(out, e->stencil_rows, e->update_blocks, e->small_tiles, 1, e->stencil_us,
+             e->update_us, e->precond_us);
+    return IRLSU_OK;
+  }
+  double su = 0.0, uu = 0.0, pu = 0.0;
+  auto go = [&](auto tag) -> irlsu_status {
+    using T = decltype(tag);
+    const Ws<T> W = carve<T>(plan, workspace);
+    const size_t npx = (size_t)plan->Np * (size_t)plan->Mp;
+    for (int v : {V_OV, V_OH, V_P0, V_Q, V_R, V_Z, V_D})
+      HIP_OK(hipMemsetAsync(W.v[v], 0, npx * sizeof(T), s));
+    HIP_OK(hipMemsetAsync(W.U, 0, npx * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(W.st.sc, 0, SC_COUNT * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(W.st.fl, 0, FL_COUNT * sizeof(int32_t), s));
+    // 1) band height of the operator (its plain apply form)
+    int best_rows = 0;
+    double best = 0.0;
+    for (int cand = -1; cand < (int)(sizeof(kRowCands) / sizeof(int)); ++cand) {
+      const int rows = cand < 0 ? 0 : kRowCands[cand];
+      int r = 0;
+      (void)stencil_grid(plan->Np, plan->Mp, &r, rows);
+      if (rows > 0 && r != rows) continue;   // grid beyond the partials table
+      StencilArgs<T> a = stencil_base<T>(plan, W.v[V_OV], W.v[V_OH], W.st);
+      a.p_in = W.v[V_P0];
+      a.q = W.v[V_Q];
+      a.check_done = 0;
+      a.rows = rows;
+      const double us = time_launches([&] { launch_stencil<T>(ST_APPLY, a, s); }, 10, s);
+      if (us < 0) return IRLSU_ERR_HIP;
+      if (cand < 0 || us < best) {
+        best = us;
+        best_rows = rows;
+      }
+    }
+    plan->tune_rows = best_rows;
+    su = best;
+    // 2) blocks of the CG update, with a state under which it runs through
+    //    (rho = 1 and a single p.q partial of 1)
+    const int nvec = stencil_blocks(plan);
+    static const double one = 1.0;
+    HIP_OK(hipMemcpyAsync(W.st.sc + SC_RHO, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(part_row_host(W.st, PR_PQ), &one, sizeof(double), hipMemcpyHostToDevice,
+                          s));
+    int best_upd = 0;
+    best = 0.0;
+    for (int cand = -1; cand < (int)(sizeof(kUpdateCands) / sizeof(int)); ++cand) {
+      const int nb = cand < 0 ? axpy_blocks(nvec) : kUpdateCands[cand];
+      if (nb > nvec) break;
+      AxpyArgs<T> xa;
+      xa.u = W.U;
+      xa.d = W.v[V_D];
+      xa.r = W.v[V_R];
+      xa.p = W.v[V_P0];
+      xa.q = W.v[V_Q];
+      xa.n = (int64_t)npx;
+      xa.nparts_pq = 1;
+      xa.nparts_out = nvec;
+      xa.iter = 0;
+      xa.st = W.st;
+      const double us = time_launches([&] { launch_axpy<T>(xa, s, nb); }, 10, s);
+      if (us < 0) return IRLSU_ERR_HIP;
+      if (cand < 0 || us < best) {
+        best = us;
+        best_upd = cand < 0 ? 0 : nb;
+      }
+    }
+    plan->tune_update = best_upd;
+    uu = best;
+    // 3) product tiles of the 16-bit MFMA forms
+    plan->tune_small = 0;
+    if (!plan->fast && plan->opsz == 2) {
+      best = 0.0;
+      int best_small = 0;
+      for (int small = 0; small < 2; ++small) {
+        plan->tune_small = small;
+        const PrecondArgs pa = precond_args<T>(plan, W, W.v[V_R], W.v[V_Z], nullptr, 0, 0);
+        const double us = time_launches([&] { launch_precond(pa, s); }, 5, s);
+        if (us < 0) return IRLSU_ERR_HIP;
+        if (small == 0 || us < best) {
+          best = us;
+          best_small = small;
+        }
+      }
+      plan->tune_small = best_small;
+      pu = best;
+    }
+    HIP_OK(hipMemsetAsync(W.st.sc, 0, SC_COUNT * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(W.st.fl, 0, FL_COUNT * sizeof(int32_t), s));
+    HIP_OK(hipStreamSynchronize(s));
+    return IRLSU_OK;
+  };
+  st = plan->elem == 8 ? go(double{}) : go(float{});
+  if (st != IRLSU_OK) return st;
+  TuneEntry e = key;
+  e.stencil_rows = plan->tune_rows;
+  e.update_blocks = plan->tune_update;
+  e.small_tiles = plan->tune_small;
+  e.stencil_us = su;
+  e.update_us = uu;
+  e.precond_us = pu;
+  if (cache_path) {
+    tune_cache_put(cache, e);
+    if (!tune_cache_write(cache_path, cache)) return IRLSU_ERR_INVALID_ARG;
+  }
+  put_tune(out, e.stencil_rows, e.update_blocks, e.small_tiles, 0, su, uu, pu);
+  return IRLSU_OK;
+}
+
+irlsu_status irlsu_batch_autotune(irlsu_batch* b, const char* cache_path, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  if (!b) return IRLSU_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < b->ws_bytes) return IRLSU_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  const std::string arch = device_arch(dev);
+  std::vector<TuneEntry> cache = tune_cache_read(cache_path);
+  const int nt = b->ntiles;
+  std::vector<int> rows(nt, 0);
+  std::map<std::pair<int64_t, int64_t>, int> chosen;
+  for (int t = 0; t < nt; ++t) {
+    const auto shape = std::make_pair(b->N[t], b->M[t]);
+    auto it = chosen.find(shape);
+    if (it != chosen.end()) {
+      rows[t] = it->second;
+      continue;
+    }
+    TuneEntry key;
+    key.kind = "batch_tile";
+    key.arch = arch;
+    key.N = b->N[t];
+    key.M = b->M[t];
+    key.precision = b->prec;
+    key.form = b->fast[t] ? IRLSU_PLAN_FAST : 0;
+    if (const TuneEntry* e = tune_cache_find(cache, key)) {
+      rows[t] = e->stencil_rows;
+      chosen[shape] = rows[t];
+      continue;
+    }
+    // the tile's stencil alone on its own (zeroed) vectors; partials from 0
+    const TileWs w = carve_tile(b, workspace, t);
+    const size_t npx = (size_t)b->Np[t] * (size_t)b->Mp[t];
+    for (int v : {2, 4, 10, 11}) HIP_OK(hipMemsetAsync(w.v[v], 0, npx * sizeof(float), s));
+    DevState st = tile_state(b, workspace, t);
+    st.off = 0;
+    StencilArgs<float> a;
+    std::memset(&a, 0, sizeof(a));
+    a.Ov = w.v[10];
+    a.Oh = w.v[11];
+    a.p_in = w.v[2];
+    a.q = w.v[4];
+    a.N = b->N[t];
+    a.M = b->M[t];
+    a.Np = b->Np[t];
+    a.ld = b->Mp[t];
+    a.st = st;
+    int best_rows = 0;
+    double best = 0.0;
+    for (int cand = -1; cand < (int)(sizeof(kRowCands) / sizeof(int)); ++cand) {
+      const int r0 = cand < 0 ? 0 : kRowCands[cand];
+      int r = 0;
+      (void)stencil_grid(a.Np, a.ld, &r, r0);
+      if (r0 > 0 && r != r0) continue;
+      a.rows = r0;
+      const double us = time_launches([&] { launch_stencil<float>(ST_APPLY, a, s); }, 10, s);
+      if (us < 0) return IRLSU_ERR_HIP;
+      if (cand < 0 || us < best) {
+        best = us;
+        best_rows = r0;
+      }
+    }
+    rows[t] = best_rows;
+    chosen[shape] = best_rows;
+    TuneEntry e = key;
+    e.stencil_rows = best_rows;
+    e.stencil_us = best;
+    tune_cache_put(cache, e);
+  }
+  std::vector<int32_t> st_start;
+  if (batch_grids(b, rows, st_start) > kMaxPartials) {
+    // the tuned grids need more partials than the table holds: defaults
+    (void)batch_grids(b, std::vector<int>(nt, 0), st_start);
+  }
+  HIP_OK(hipMemcpy(b->d_st_start, st_start.data(), st_start.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+  if (cache_path && !tune_cache_write(cache_path, cache)) return IRLSU_ERR_INVALID_ARG;
+  return IRLSU_OK;
+}

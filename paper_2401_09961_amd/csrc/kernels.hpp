@@ -68,6 +68,7 @@ struct StencilArgs {
   int check_done;      // skip when the PCG done flag is set
   int want_qq = 0;     // APPLY: also the partial ||q||^2 (slot PR_AUX)
   int nparts_out = 0;  // RESID: partial count the consumers read (zero padded)
+  int rows = 0;        // band height of a block (0: the default rule of stencil_grid)
   DevState st;
 };
 
@@ -84,7 +85,7 @@ struct BatchTile {
   int32_t st_gx, st_rows, st_nblk;   // stencil grid: column blocks, rows per band, blocks
   int32_t g4_nparts;                 // partials of the last preconditioner product
   int32_t flexible_q;                // pass q to the preconditioner epilogue
-  int32_t pad_;
+  int32_t fast;                      // preconditioner in the fast form (its own launches)
   void* T1; void* T2; void* T3;
   const void* PN; const void* PNt; const void* PM; const void* PMt;
   const double* eigN; const double* eigM;
@@ -168,7 +169,7 @@ template <class T>
 void launch_axpy_batched(const BatchTile<T>* tiles, const int32_t* start, int ntiles,
                          int total_blocks, int iter, hipStream_t s);
 // Grid of the stencil (and of the axpy, which must write as many partials).
-dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out);
+dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out, int force_rows = 0);
 
 // ---- adjoint (frozen-weight) -------------------------------------------
 template <class T>
@@ -268,6 +269,7 @@ struct PrecondArgs {
   // the row DCT-II of r already ran, fused with the CG update that produced r
   // (launch_cg_update_fast); the prologue then only tests convergence
   int fused_head = 0;
+  int small_tiles = 0;        // 16-bit products: 128 x 128 tiles even where 256 x 256 divide
   LaunchLog* log = nullptr;   // nullable: per-launch events
 };
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s);

@@ -268,12 +268,16 @@ __global__ __launch_bounds__(kThreads) void stencil_batched_kernel(const BatchTi
   stencil_body<T, MODE>(a, lb % bt.st_gx, lb / bt.st_gx, bt.st_rows, lb);
 }
 
-// Enough blocks to fill 256 CUs several times over, within the partials table.
-dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out) {
+// Enough blocks to fill 256 CUs several times over, within the partials
+// table; force_rows > 0 (a tuned band height) replaces the rule when its
+// grid fits the table.
+dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out, int force_rows) {
   const int64_t bx = (ld + 4 * kThreads - 1) / (4 * kThreads);
   int64_t rows = 64;
   while (rows > 4 && bx * ((Np + rows - 1) / rows) < 1024) rows /= 2;
   while (bx * ((Np + rows - 1) / rows) > kMaxPartials) rows *= 2;
+  if (force_rows > 0 && bx * ((Np + force_rows - 1) / force_rows) <= kMaxPartials)
+    rows = force_rows;
   *rows_out = (int)rows;
   return dim3((unsigned)bx, (unsigned)((Np + rows - 1) / rows));
 }
@@ -281,7 +285,7 @@ dim3 stencil_grid(int64_t Np, int64_t ld, int* rows_out) {
 template <class T>
 int launch_stencil(int mode, const StencilArgs<T>& a, hipStream_t s) {
   int rows = 0;
-  const dim3 grid = stencil_grid(a.Np, a.ld, &rows);
+  const dim3 grid = stencil_grid(a.Np, a.ld, &rows, a.rows);
   switch (mode) {
     case ST_FUSED:
       hipLaunchKernelGGL((stencil_kernel<T, ST_FUSED>), grid, dim3(kThreads), 0, s, a, rows);
