@@ -475,17 +475,27 @@ def frozen_weights(U, Gv, Gh, eps):
     return 1.0 / np.maximum(np.abs(rv), eps), 1.0 / np.maximum(np.abs(rh), eps)
 
 
-def frozen_solve(Cv, Ch, Gv, Gh, wv, wh, tol=1e-14, maxit=5000, x0=None):
-    """U = argmin over mean-zero U of sum C omega_bar (DU - G)^2."""
+def frozen_solve(Cv, Ch, Gv, Gh, wv, wh, tol=1e-14, maxit=5000, x0=None, workers=None):
+    """U = argmin over mean-zero U of sum C omega_bar (DU - G)^2.
+
+    With x0 given, the correction from x0 is solved instead, to tol relative
+    to its own right-hand side (the residual at x0): a small change of the
+    weights then still gets a solve converged relative to that change."""
     Ov, Oh = Cv * wv, Ch * wh
     b = div(Ov * Gv, Oh * Gh)
     N, M = b.shape
-    x0 = np.zeros((N, M)) if x0 is None else x0
-    U, _ = pcg(lambda p: apply_A(Ov, Oh, p), apply_precond, b, x0, tol, maxit)
+    A = lambda p: apply_A(Ov, Oh, p)  # noqa: E731
+    Minv = lambda r: apply_precond(r, workers=workers)  # noqa: E731
+    if x0 is None:
+        U, _ = pcg(A, Minv, b, np.zeros((N, M)), tol, maxit)
+    else:
+        res = b - A(x0)
+        dU, _ = pcg(A, Minv, res - res.mean(), np.zeros((N, M)), tol, maxit)
+        U = x0 + dU
     return U - U.mean()
 
 
-def adjoint(U, Gv, Gh, Cv, Ch, eps, gU, tol=1e-14, maxit=5000, weights=None):
+def adjoint(U, Gv, Gh, Cv, Ch, eps, gU, tol=1e-14, maxit=5000, weights=None, workers=None):
     """Gradients of a loss with dL/dU = gU through the frozen map.
 
     U must solve the frozen system for the weights omega_bar, which are
@@ -500,7 +510,7 @@ def adjoint(U, Gv, Gh, Cv, Ch, eps, gU, tol=1e-14, maxit=5000, weights=None):
     Ov, Oh = Cv * wv, Ch * wh
     g = np.asarray(gU, np.float64)
     g = g - g.mean()
-    lam, _ = pcg(lambda p: apply_A(Ov, Oh, p), apply_precond, g,
+    lam, _ = pcg(lambda p: apply_A(Ov, Oh, p), lambda r: apply_precond(r, workers=workers), g,
                  np.zeros_like(g), tol, maxit)
     lam -= lam.mean()
     dv, dh = diff_v(lam), diff_h(lam)

@@ -854,3 +854,29 @@ def test_irls_returns_mean_zero_from_any_start():
     f = synth.field_c2(1, 20, 18)
     U, _ = R.irls(f.X, w=f.w, iters=2, tol=1e-10, maxit=50, U0=np.full((20, 18), 5.0))
     assert abs(U.mean()) < 1e-12
+
+
+def test_frozen_solve_correction_from_a_start_point():
+    """frozen_solve with x0 solves the correction from x0 (to tol of its own
+    right-hand side): for any start point it gives the cold solve's mean-zero
+    minimiser, and for a perturbed weight started at the unperturbed
+    solution it gives the dense bordered solve of the perturbed problem."""
+    N, M = 20, 17
+    rng = np.random.default_rng(41)
+    X = R.wrap(rng.normal(0, 2.0, (N, M)))
+    Gv, Gh = R.wrapped_gradients(X)
+    Cv = rng.uniform(0.2, 1.0, (N - 1, M))
+    Ch = rng.uniform(0.2, 1.0, (N, M - 1))
+    wv = 1.0 / np.maximum(np.abs(rng.normal(0, 1, (N - 1, M))), 1e-3)
+    wh = 1.0 / np.maximum(np.abs(rng.normal(0, 1, (N, M - 1))), 1e-3)
+    cold = R.frozen_solve(Cv, Ch, Gv, Gh, wv, wh, tol=1e-14, maxit=5000)
+    assert np.abs(cold - dense_frozen_solve(Cv, Ch, Gv, Gh, wv, wh)).max() < 1e-9
+    warm = R.frozen_solve(Cv, Ch, Gv, Gh, wv, wh, tol=1e-14, maxit=5000,
+                          x0=rng.normal(0, 5.0, (N, M)))
+    assert np.abs(warm - cold).max() < 1e-9
+    Cp = Cv.copy()
+    Cp[3, 4] += 1e-3
+    pert = R.frozen_solve(Cp, Ch, Gv, Gh, wv, wh, tol=1e-14, maxit=5000, x0=cold)
+    dense = dense_frozen_solve(Cp, Ch, Gv, Gh, wv, wh)
+    # the change itself (not only the solution) is resolved
+    assert np.abs((pert - cold) - (dense - cold)).max() <= 1e-6 * np.abs(dense - cold).max()
