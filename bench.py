@@ -370,9 +370,10 @@ def paper_shapes(pkg, torch, synth, a, prec):
 
 def batched(pkg, torch, synth, a, return_line=False):
     """64 uneven tiles (c1-generator fields, seeds 1000 + t) unwrapped as one
-    batch (mixed BF16, one grouped launch per PCG phase) and one plan per
-    tile in FP32, same schedule (20 IRLS x 100 PCG, pcg_rtol 1e-6); HIP
-    events, inputs resident, one warm-up each."""
+    batch (mixed BF16 and FP32, one grouped launch per PCG phase, PCG
+    blocks replayed from captured graphs, launch shapes autotuned per tile
+    shape) and one plan per tile in FP32, same schedule (20 IRLS x 100 PCG,
+    pcg_rtol 1e-6); HIP events, inputs resident, one warm-up each."""
     torch.cuda.set_device(0)
     shapes = [tuple(int(v) for v in sh) for sh in synth.tile_shapes_c4(0)]
     print(f"[bench] generating {len(shapes)} tiles", file=sys.stderr, flush=True)
@@ -393,8 +394,15 @@ def batched(pkg, torch, synth, a, return_line=False):
 
     pb = pkg.default_params("bf16")
     batch = pkg.Batch(shapes, "bf16")
+    batch.autotune()
     ms_b, (Ub, stb) = timed(lambda: batch.unwrap(Xs, params=pb, stats=True))
     batch.close()
+    p32 = pkg.default_params("f32")
+    batch = pkg.Batch(shapes, "f32")
+    batch.autotune()
+    ms_b32, (Ub32, stb32) = timed(lambda: batch.unwrap(Xs, params=p32, stats=True))
+    batch.close()
+    n_fast = sum(1 for n, m in shapes if n & (n - 1) == 0 and m & (m - 1) == 0)
     plans = [pkg.Plan(n, m, "f32") for n, m in shapes]
     pf = pkg.default_params("f32")
     ms_l, res = timed(lambda: [pl.unwrap(X, params=pf, stats=True) for pl, X in zip(plans, Xs)])
@@ -404,16 +412,25 @@ def batched(pkg, torch, synth, a, return_line=False):
     edges = [(n - 1) * m + n * (m - 1) for n, m in shapes]
     l1b = [st["L1_final"] / e for st, e in zip(stb, edges)]
     l1l = [r[1]["L1_final"] / e for r, e in zip(res, edges)]
+    l1b32 = [st["L1_final"] / e for st, e in zip(stb32, edges)]
     du = max(float((ub - ub.mean() - (r[0] - r[0].mean())).abs().max()) for ub, r in zip(Ub, res))
+    du32 = max(float((ub - ub.mean() - (r[0] - r[0].mean())).abs().max())
+               for ub, r in zip(Ub32, res))
     line = {"metric": "Mpixel/s, 64 uneven tiles (sides 512..3072) unwrapped, 20 IRLS x 100 PCG",
             "unit": "Mpixel/s", "tiles": len(shapes), "pixels": px,
+            "fast_form_tiles": n_fast, "launch_shapes": "autotuned per tile shape",
             "batched": {"precision": "bf16", "value": round(px / 1e6 / (ms_b * 1e-3), 3),
                         "ms": round(ms_b, 1), "pcg_total": sum(st["pcg_total"] for st in stb)},
+            "batched_f32": {"precision": "f32", "value": round(px / 1e6 / (ms_b32 * 1e-3), 3),
+                            "ms": round(ms_b32, 1),
+                            "pcg_total": sum(st["pcg_total"] for st in stb32),
+                            "L1_per_edge_max": max(l1b32), "max_abs_U_difference_vs_looped": du32},
             "looped_single_tile": {"precision": "f32", "forms": forms,
                                    "value": round(px / 1e6 / (ms_l * 1e-3), 3),
                                    "ms": round(ms_l, 1),
                                    "pcg_total": sum(r[1]["pcg_total"] for r in res)},
             "speedup": round(ms_l / ms_b, 3),
+            "speedup_f32": round(ms_l / ms_b32, 3),
             "equal_accuracy": {"L1_per_edge_max_batched": max(l1b),
                                "L1_per_edge_max_looped": max(l1l),
                                "max_abs_U_difference": du},

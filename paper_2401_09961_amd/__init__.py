@@ -613,7 +613,8 @@ def _autograd_function():
     import torch
 
     class UnwrapFn(torch.autograd.Function):
-        """U = unwrap(X, Cv, Ch) with a hand-written adjoint.
+        """U = unwrap(X, Cv, Ch) with a hand-written adjoint (X, Cv, Ch may
+        carry a leading batch dimension: one unwrap and one adjoint per grid).
 
         forward runs the IRLS + PCG path on a workspace of its own; backward
         runs one extra PCG solve on the converged system with the weights
@@ -624,17 +625,32 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, X, Cv, Ch, plan, params=None, adj_params=None, implicit=False):
-            ws = plan.new_workspace()
-            U = plan.unwrap(X, Cv=Cv, Ch=Ch, params=params, workspace=ws)
-            ctx.plan, ctx.ws, ctx.adj_params = plan, ws, adj_params if adj_params is not None else params
+            # a leading batch dimension runs one unwrap per grid, each on a
+            # workspace of its own that its backward reuses
+            batched = X.dim() == 3
+            Xs = list(X) if batched else [X]
+            Cvs = list(Cv) if batched else [Cv]
+            Chs = list(Ch) if batched else [Ch]
+            wss, Us = [], []
+            for x, cv, ch in zip(Xs, Cvs, Chs):
+                ws = plan.new_workspace()
+                Us.append(plan.unwrap(x, Cv=cv, Ch=ch, params=params, workspace=ws))
+                wss.append(ws)
+            ctx.plan, ctx.wss, ctx.batched = plan, wss, batched
+            ctx.adj_params = adj_params if adj_params is not None else params
             ctx.implicit = bool(implicit)
-            return U
+            return torch.stack(Us) if batched else Us[0]
 
         @staticmethod
         def backward(ctx, gU):
-            gCv, gCh, gX = ctx.plan.adjoint(gU.contiguous(), params=ctx.adj_params, workspace=ctx.ws,
-                                            implicit=ctx.implicit)
-            ctx.ws = None
+            gs = list(gU) if ctx.batched else [gU]
+            outs = [ctx.plan.adjoint(g.contiguous(), params=ctx.adj_params, workspace=ws,
+                                     implicit=ctx.implicit) for g, ws in zip(gs, ctx.wss)]
+            ctx.wss = None
+            if ctx.batched:
+                gCv, gCh, gX = (torch.stack([o[i] for o in outs]) for i in range(3))
+            else:
+                gCv, gCh, gX = outs[0]
             return gX, gCv, gCh, None, None, None, None
 
     return UnwrapFn

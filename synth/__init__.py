@@ -141,6 +141,14 @@ def field_c4_tile(t: int, N: int, M: int) -> Field:
     return f
 
 
+def field_c5_truth(seed: int, N: int = 1024, M: int = 1024) -> np.ndarray:
+    """The noise-free phase of field_c5(seed): the same Gaussians and ramp
+    (the noise is the last draw of the phase, so the same stream without it
+    gives the signal the noise was added to)."""
+    rng = np.random.default_rng(seed)
+    return gaussian_sum_field(rng, N, M, amp=20.0, noise=0.0)
+
+
 def field_c5(seed: int, N: int = 1024, M: int = 1024) -> Field:
     """Differentiation case: small-case generator plus per-edge weights
     sigmoid(z), z ~ N(0, 1), drawn after the phase."""

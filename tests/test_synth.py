@@ -31,3 +31,11 @@ def test_weights_and_shapes():
     s = synth.tile_shapes_c4(0)
     assert s.shape == (64, 2) and s.min() >= 512 and s.max() <= 3072
     assert np.array_equal(s, synth.tile_shapes_c4(0))
+
+
+def test_c5_truth_is_the_noise_free_phase():
+    f = synth.field_c5(3, 64, 48)
+    t = synth.field_c5_truth(3, 64, 48)
+    d = f.phi - t
+    # the difference is the N(0, 0.3^2) noise: no structure, the right spread
+    assert abs(d.std() - 0.3) < 0.02 and abs(d.mean()) < 0.03
