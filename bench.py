@@ -177,17 +177,21 @@ def kernel_table(launches, prec, form, N, M, flexible):
     # direction p (rho from the column pass's spectral sum), the stencil
     # applies the operator only
     spectral = form == "fast" and not flexible
+    # fused head: the iterate update d += alpha p rides on the last pass
+    # (which reads p for the new direction), not on the fused CG update
+    fused = spectral and any(k == "update_dct2" for k, _ in launches)
     bpp = {  # kind -> (kernel, bytes per pixel)
         "stencil": ("stencil_kernel", 4 * e if spectral else 6 * e),  # (z,) p, Ov, Oh in; (p,) q out
         "axpy": ("axpy_kernel", 6 * e),                    # p, q, r, d in; r, d out
         "residual": ("stencil_kernel(residual)", 8 + 5 * e),  # u, d, b, Ov, Oh in; r out
         "rows_dct2": ("fct_rows_fwd_kernel", e + s),        # r in; T1 out
-        # CG update fused with the row DCT-II: p, q, r, d in; r, d, T1 out
-        "update_dct2": ("fct_rows_fwd_cg_kernel", 6 * e + s),
+        # CG update fused with the row DCT-II: q, r in; r, T1 out
+        "update_dct2": ("fct_rows_fwd_cg_kernel", 3 * e + s),
         "transpose": ("transpose_kernel", 2 * s),
         "cols": ("fct_cols_kernel", 2 * s),
-        # T, r, (q) in; z out -- spectral: T, p_old in; p out
-        "rows_dct3": ("fct_rows_inv_kernel", s + (3 if flexible else 2) * e),
+        # T, r, (q) in; z out -- spectral: T, p_old in; p out (fused head:
+        # also d in and out)
+        "rows_dct3": ("fct_rows_inv_kernel", s + (4 if fused else 3 if flexible else 2) * e),
     }
     n_prod = sum(1 for k, _ in launches if k == "product")
     out = {}
@@ -224,6 +228,42 @@ def profiled_traffic(config, N, prec, form):
                 f = line.split()
                 if len(f) == 3 and f[0] == "traffic":
                     out[f[1]] = int(f[2])
+    return out
+
+
+# Issue rate of the vector ALUs without packed FP32 (kept out of the code):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-instruction per lane per
+# cycle; a wave64 instruction occupies a 16-lane SIMD for 4 cycles), in
+# 10^12 lane-instructions per second.
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def profiled_valu(config, N, prec, form):
+    """VALU instructions per launch of each kernel (wave-level count x 64
+    lanes) from the committed rocprofv3 SQ_INSTS_VALU summary, if any."""
+    path = os.path.join(ROOT, "profiles", f"{config}_{N}_{prec}_{form}_valu.md")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 3 and f[0] == "valu":
+                    out[f[1]] = float(f[2])
+    return out
+
+
+def alu_roofline(kern, valu):
+    """Roofline of the kernels bound by instruction issue: lane-instructions
+    per second (the profile's VALU count) against VALU_PEAK_T."""
+    out = {}
+    for name, ent in kern.items():
+        if ent["bound"] != "alu" or name not in valu or ent["ms"] <= 0:
+            continue
+        per_launch = valu[name] * 64.0
+        ach = per_launch / (ent["ms"] / ent["launches"] * 1e-3) / 1e12
+        out[name] = {"bound": "alu", "achieved": round(ach, 2), "peak": round(VALU_PEAK_T, 2),
+                     "unit": "T lane-instructions/s", "frac": round(ach / VALU_PEAK_T, 4),
+                     "lane_instructions_per_launch": per_launch}
     return out
 
 
@@ -533,10 +573,7 @@ def kernels_only(pkg, torch, N, M, prec):
     launches = plan.precond_timed(r, reps=3)
     ms_st = time_stencil(plan, torch, reps=3)   # plain operator form, 16 B/px
     nbytes = 256 << 20
-    x = torch.empty(nbytes // 4, dtype=torch.float32, device=plan.device).uniform_()
-    y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
+    pkg.stream_probe("copy", nbytes=nbytes, grids=(1024,), reps=3)
     torch.cuda.synchronize()
     out = {"N": N, "M": M, "precision": prec, "form": plan.form,
            "launches": [[k, round(ms, 4)] for k, ms in launches], "stencil_ms": round(ms_st, 4),
@@ -578,14 +615,14 @@ def main(argv=None):
     ap.add_argument("--no-mfma-form", action="store_true",
                     help="skip the second measurement with the MFMA preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="3 device copies of 256 MiB first (hardware-counter byte calibration)")
+                    help="4 streaming copies of 256 MiB first (hardware-counter byte calibration)")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="the running-time study of the paper: 4000 x M, M = 2000..16000, "
                          "c2-type fields, fixed 20 x 100 schedule; one JSON line")
     ap.add_argument("--kernels-only", action="store_true",
                     help="a short fixed launch sequence for hardware-counter runs: "
-                         "3 preconditioner applications, 3 stencil applications and 3 "
-                         "copies of 256 MiB (the byte-count calibration)")
+                         "3 preconditioner applications, 3 stencil applications and 4 "
+                         "streaming copies of 256 MiB (the byte-count calibration)")
     a = ap.parse_args(argv)
     a.warmup = max(1, a.warmup)
     if a.gpus != 1:
@@ -607,13 +644,11 @@ def main(argv=None):
     if a.batched:
         return batched(pkg, torch, synth, a)
     if a.copy_calibration:
+        # four dispatches of the library's own streaming copy (256 MiB read
+        # and written each): the byte calibration of the traffic counters
         torch.cuda.set_device(0)
-        xc = torch.empty((256 << 20) // 4, dtype=torch.float32, device="cuda").uniform_()
-        yc = torch.empty_like(xc)
-        for _ in range(3):
-            yc.copy_(xc)
+        pkg.stream_probe("copy", grids=(1024,), reps=3)
         torch.cuda.synchronize()
-        del xc, yc
     ref = load_reference(cfg["ref"])
     L1_ref = ref["L1_final"]
     target = L1_ref * (1.0 + a.gap)
@@ -709,6 +744,7 @@ def main(argv=None):
                    "ms_per_pcg_iter": round(ms / max(1, pcg_per_step), 4),
                    "plan_create_s": round(primary["plan_s"], 3)},
         "roofline": roof,
+        "alu_roofline": alu_roofline(kern, profiled_valu(a.config, N, prec, form_used)),
         "kernels": kern,
         "precond_form": form_used,
         "precond_ms": primary["precond_ms"],

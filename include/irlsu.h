@@ -62,10 +62,12 @@ typedef enum irlsu_status {
 /* Precision of a plan.  The vectors, scalars and FP64 reductions are fixed
  * by the precision alone; where the preconditioner's arithmetic runs depends
  * on the plan's form (IRLSU_PLAN_*, below):
- *   fast form (the default for power-of-two sides): FP32 VALU transforms
+ *   fast form (the default where it applies: power-of-two sides, or sides
+ *     that are multiples of 8 whose halves have only the factors 2, 3, 5):
+ *     FP32 VALU transforms
  *     (FP64 for F64 plans), the two stored intermediates in the operand
  *     type (FP16 / BF16 for the mixed plans, FP32 / FP64 otherwise);
- *   dense and folded forms (every other side, or forced through
+ *   dense and folded forms (the other sides, or forced through
  *     irlsu_plan_create_ex): MFMA products with the cosine bases in the
  *     operand type, FP32 accumulation (FP64 for F64 plans). */
 typedef enum irlsu_precision {
@@ -161,7 +163,7 @@ typedef struct irlsu_plan_desc {
 
 /* Form of the preconditioner products (irlsu_plan_create_ex). */
 enum {
-  IRLSU_PLAN_AUTO = 0,   /* fast when N, M are powers of two in [128, 16384];
+  IRLSU_PLAN_AUTO = 0,   /* fast where the fast form applies (below);
                             else folded when N, M are even and N M >= 2^20;
                             else dense */
   IRLSU_PLAN_DENSE = 1,  /* four dense MFMA products (Section 3.3 as written) */
@@ -171,7 +173,10 @@ enum {
   IRLSU_PLAN_FAST = 3    /* the same products by fast cosine transforms
                             (half-length FFTs in LDS, FP32 arithmetic for FP32
                             and mixed plans, FP64 for FP64 plans); N and M
-                            powers of two in [128, 16384] (else ERR_SHAPE) */
+                            both powers of two in [128, 16384], or each a
+                            multiple of 8 whose half is at most 8192 and has
+                            no prime factor above 5 (4000, 6000, 16000, ...);
+                            else ERR_SHAPE */
 };
 
 /* Testing hook for the ERR_OOM path (for callers that test their own error
@@ -192,7 +197,9 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec);
  * iteration).  The form is chosen as IRLSU_PLAN_AUTO describes; on the
  * current HIP device the plan allocates and fills
  *   fast form: the FFT twiddle tables of each side (about 3n/2 complex
- *     values per side, shared when N = M) and the Laplacian eigenvalues
+ *     values per side -- the stage twiddles for power-of-two plans, the
+ *     n/2-th roots of unity otherwise -- shared when N = M) and the
+ *     Laplacian eigenvalues
  *     2 - 2 cos(pi k / n) in FP64;
  *   dense form: the orthonormal DCT-II bases P_N, P_M and their transposes
  *     in the operand type, and the eigenvalues;
@@ -511,8 +518,9 @@ enum {
   IRLSU_LK_STENCIL = 9,    /* p = z + beta p, q = D^T Omega D p, p.q (PCG loop form) */
   IRLSU_LK_AXPY = 10,      /* alpha, d += alpha p, r -= alpha q, ||r||^2 */
   IRLSU_LK_RESIDUAL = 11,  /* true-residual refresh r = b - A (u + d) */
-  IRLSU_LK_UPDATE_DCT2 = 12, /* fast form: r -= alpha q, d += alpha p fused with the
-                                DCT-II along rows of the new r */
+  IRLSU_LK_UPDATE_DCT2 = 12, /* fast form: r -= alpha q fused with the DCT-II along
+                                rows of the new r (d += alpha p then rides on the
+                                DCT-III along rows, which reads p anyway) */
   IRLSU_LK_ALPHA = 13      /* alpha = rho / p.q and the FP16 input scale */
 };
 

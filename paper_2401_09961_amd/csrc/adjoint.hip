@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kThreads) void adj_finalize_kernel(DevState st, int
     st.sc[SC_BB] = bb;
     st.sc[SC_TOL2] = tol2;
     st.fl[FL_DONE] = 0;
+    st.fl[FL_DPEND] = 0;
     st.fl[FL_ITERS] = 0;
     st.fl[FL_STATUS] = 0;
   }

@@ -430,6 +430,7 @@ __global__ __launch_bounds__(kThreads) void aug_start_kernel(DevState st, int np
     if (nparts > 0) st.sc[SC_BB] = bb;
     st.sc[SC_TOL2] = tol2;
     st.fl[FL_DONE] = 0;
+    st.fl[FL_DPEND] = 0;
     st.fl[FL_ITERS] = 0;
   }
 }

@@ -40,6 +40,8 @@ enum Flag : int {
   FL_STATUS = 2,   // bit 0: breakdown
   FL_INPUT = 3,    // bit 0: non-finite input, bit 1: weight <= 0
   FL_GUARD = 4,    // augmented form: outcome of the sufficient-decrease guard
+  FL_DPEND = 5,    // fast form: the iterate update of the iteration that
+                   // converged is still owed by the row DCT-III pass
   FL_COUNT = 16
 };
 

@@ -25,174 +25,16 @@
 // With plain beta (spectral path): cols also sums rhat^2 / (lambda + mu) =
 // r.z (Parseval), a one-block kernel forms rho and beta, and rows_inv writes
 // the direction p = z + beta p_old instead of z and its dots; the CG update
-// r -= alpha q, d += alpha p runs fused with rows_fwd of the next application
-// (fct_rows_fwd_cg_kernel, alpha from cg_alpha_kernel).
+// r -= alpha q runs fused with rows_fwd of the next application
+// (fct_rows_fwd_cg_kernel, alpha from cg_alpha_kernel) and d += alpha p with
+// rows_inv, which reads p_old anyway.  Sides that are not powers of two run
+// the same passes with run-time sizes (fctg.hip).
 #include <type_traits>
 
+#include "fft.hpp"
 #include "kernels.hpp"
 
 namespace irlsu {
-
-template <class CT>
-struct Cx {
-  CT x, y;
-};
-
-template <class CT>
-__device__ __forceinline__ Cx<CT> cadd(Cx<CT> a, Cx<CT> b) {
-  return {a.x + b.x, a.y + b.y};
-}
-template <class CT>
-__device__ __forceinline__ Cx<CT> csub(Cx<CT> a, Cx<CT> b) {
-  return {a.x - b.x, a.y - b.y};
-}
-template <class CT>
-__device__ __forceinline__ Cx<CT> cmul(Cx<CT> a, Cx<CT> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-// a * conj(b)
-template <class CT>
-__device__ __forceinline__ Cx<CT> cmulc(Cx<CT> a, Cx<CT> b) {
-  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
-}
-template <class CT>
-__device__ __forceinline__ Cx<CT> conjg(Cx<CT> a) {
-  return {a.x, -a.y};
-}
-// -i a
-template <class CT>
-__device__ __forceinline__ Cx<CT> mul_mi(Cx<CT> a) {
-  return {a.y, -a.x};
-}
-// i a
-template <class CT>
-__device__ __forceinline__ Cx<CT> mul_i(Cx<CT> a) {
-  return {-a.y, a.x};
-}
-template <class CT>
-__device__ __forceinline__ Cx<CT> cscale(Cx<CT> a, CT s) {
-  return {a.x * s, a.y * s};
-}
-// 1 / x: correctly rounded in FP64; in FP32 the hardware reciprocal (1 ulp),
-// well inside the FP32 transform's own rounding
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Calls f(std::integral_constant<int, I>) for I = B .. E-1.
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
-// ---- small forward DFTs in registers (natural order in and out) ----------
-template <class CT>
-__device__ __forceinline__ void dft4(Cx<CT>& a0, Cx<CT>& a1, Cx<CT>& a2, Cx<CT>& a3) {
-  const Cx<CT> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
-  a0 = cadd(t0, t2);
-  a2 = csub(t0, t2);
-  a1 = cadd(t1, t3);
-  a3 = csub(t1, t3);
-}
-
-// e^{-2 pi i j / 16}, j = 0..15 (the twiddles of the 4 x 4 split)
-template <class CT>
-__device__ __forceinline__ Cx<CT> w16(int j) {
-  // cos(2 pi j / 16) for j = 0..15; sin is the cosine a quarter turn back
-  constexpr double c[16] = {1.0,
-                            0.92387953251128675613,
-                            0.70710678118654752440,
-                            0.38268343236508977173,
-                            0.0,
-                            -0.38268343236508977173,
-                            -0.70710678118654752440,
-                            -0.92387953251128675613,
-                            -1.0,
-                            -0.92387953251128675613,
-                            -0.70710678118654752440,
-                            -0.38268343236508977173,
-                            0.0,
-                            0.38268343236508977173,
-                            0.70710678118654752440,
-                            0.92387953251128675613};
-  return {(CT)c[j & 15], (CT)(-c[(j + 12) & 15])};
-}
-
-// a * e^{-2 pi i J / 16} for a compile-time J: quarter turns by swaps and
-// sign changes, odd eighth turns by one add and one multiply per part, the
-// rest by a complex product with the constant.
-template <class CT, int J>
-__device__ __forceinline__ Cx<CT> mul_w16(Cx<CT> a) {
-  constexpr int j = J & 15;
-  constexpr CT h = (CT)0.70710678118654752440;
-  if constexpr (j == 0) {
-    return a;
-  } else if constexpr (j == 4) {
-    return mul_mi(a);
-  } else if constexpr (j == 8) {
-    return {-a.x, -a.y};
-  } else if constexpr (j == 12) {
-    return mul_i(a);
-  } else if constexpr (j == 2) {   // h (1 - i)
-    return {(a.x + a.y) * h, (a.y - a.x) * h};
-  } else if constexpr (j == 6) {   // h (-1 - i)
-    return {(a.y - a.x) * h, -(a.x + a.y) * h};
-  } else if constexpr (j == 10) {  // h (-1 + i)
-    return {-(a.x + a.y) * h, (a.x - a.y) * h};
-  } else if constexpr (j == 14) {  // h (1 + i)
-    return {(a.x - a.y) * h, (a.x + a.y) * h};
-  } else {
-    return cmul(a, w16<CT>(j));
-  }
-}
-
-template <class CT, int R>
-__device__ __forceinline__ void dft(Cx<CT> (&a)[R]) {
-  if constexpr (R == 2) {
-    const Cx<CT> t = a[0];
-    a[0] = cadd(t, a[1]);
-    a[1] = csub(t, a[1]);
-  } else if constexpr (R == 4) {
-    dft4(a[0], a[1], a[2], a[3]);
-  } else if constexpr (R == 8) {
-    // n = 4 n1 + n2, k = k1 + 2 k2: length-2 DFTs over n1, twiddle
-    // e^{-2 pi i n2 k1 / 8}, length-4 DFTs over n2
-    Cx<CT> b0[4], b1[4];
-    static_for<0, 4>([&](auto c) {
-      constexpr int n2 = decltype(c)::value;
-      b0[n2] = cadd(a[n2], a[4 + n2]);
-      b1[n2] = mul_w16<CT, 2 * n2>(csub(a[n2], a[4 + n2]));
-    });
-    dft4(b0[0], b0[1], b0[2], b0[3]);
-    dft4(b1[0], b1[1], b1[2], b1[3]);
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {
-      a[2 * k2] = b0[k2];
-      a[1 + 2 * k2] = b1[k2];
-    }
-  } else {
-    static_assert(R == 16, "radix");
-    // n = 4 n1 + n2, k = k1 + 4 k2
-    Cx<CT> b[4][4];
-    static_for<0, 4>([&](auto c) {
-      constexpr int n2 = decltype(c)::value;
-      Cx<CT> c0 = a[n2], c1 = a[4 + n2], c2 = a[8 + n2], c3 = a[12 + n2];
-      dft4(c0, c1, c2, c3);
-      b[0][n2] = c0;
-      b[1][n2] = mul_w16<CT, n2>(c1);
-      b[2][n2] = mul_w16<CT, 2 * n2>(c2);
-      b[3][n2] = mul_w16<CT, 3 * n2>(c3);
-    });
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) {
-      dft4(b[k1][0], b[k1][1], b[k1][2], b[k1][3]);
-#pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = b[k1][k2];
-    }
-  }
-}
 
 // ---- Stockham FFT of ROWS rows of H complex points held in LDS ----------
 // LDS holds complex point x at slot pc(x) = x + x / 16: one pad slot per 16
@@ -379,23 +221,6 @@ __device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<C
 // ---- row staging ----------------------------------------------------------
 // Every thread moves whole 16-byte chunks of the block's rows; all of a
 // thread's global loads are issued before its first LDS write.
-template <class T>
-struct Vec16 {
-  static constexpr int W = 16 / (int)sizeof(T);
-  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
-};
-
-// 16-byte streaming accesses (non-temporal hint) for data a pass reads or
-// writes once
-template <class V, class T>
-__device__ __forceinline__ V ld_nt(const T* p) {
-  return __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-}
-template <class V, class T>
-__device__ __forceinline__ void st_nt(T* p, const V& v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
-}
-
 template <class TI, int H>
 struct RowChunks {
   static constexpr int N = 2 * H, ROWS = rows_per_block<H>();
@@ -567,14 +392,15 @@ __global__ __launch_bounds__(1024) void cg_alpha_kernel(DevState st, int nparts_
   }
 }
 
-// Per row group: r -= alpha q, d += alpha p (written back, streaming), the
-// new r (times the input scale) transformed like pass 1 into out; partials
-// ||r||^2 and sum r, zero padded to nparts_out.
+// Per row group: r -= alpha q (written back, streaming), the new r (times
+// the input scale) transformed like pass 1 into out; partials ||r||^2 and
+// sum r, zero padded to nparts_out.  (d += alpha p waits for the row DCT-III
+// pass, which reads p for the next direction: 12 bytes per pixel less here
+// for 8 more there.)
 template <class CT, class T, class TO, int H>
 __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
-    T* __restrict__ r, T* __restrict__ d, const T* __restrict__ p, const T* __restrict__ q,
-    int64_t ld, TO* __restrict__ out, const void* twp, DevState st, int iter, int f16,
-    int nparts_out) {
+    T* __restrict__ r, const T* __restrict__ q, int64_t ld, TO* __restrict__ out,
+    const void* twp, DevState st, int iter, int f16, int nparts_out) {
   if (st.fl[FL_DONE]) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
@@ -594,15 +420,13 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
     constexpr int UN = RC::NCH < 2 ? RC::NCH : 2;
 #pragma unroll
     for (int i0 = 0; i0 < RC::NCH; i0 += UN) {
-      V pv[UN], qv[UN], rv[UN], dv[UN];
+      V qv[UN], rv[UN];
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
         const int e0 = (tid + (i0 + u) * kThreads) * W;
         const int64_t o = (row0 + e0 / N) * ld + e0 % N;
-        pv[u] = ld_nt<V>(p + o);
         qv[u] = ld_nt<V>(q + o);
         rv[u] = ld_nt<V>(r + o);
-        dv[u] = ld_nt<V>(d + o);
       }
 #pragma unroll
       for (int u = 0; u < UN; ++u) {
@@ -611,12 +435,10 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           rv[u][t] = rv[u][t] - al * qv[u][t];
-          dv[u][t] = dv[u][t] + al * pv[u][t];
           acc[0] += (double)rv[u][t] * (double)rv[u][t];
           acc[1] += (double)rv[u][t];
         }
         __builtin_nontemporal_store(rv[u], reinterpret_cast<V*>(r + o));
-        __builtin_nontemporal_store(dv[u], reinterpret_cast<V*>(d + o));
         ch.d[i0 + u] = rv[u];
       }
     }
@@ -697,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
       Cx<CT> ck, cp;
       post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
       // X~ at k, n-k, h-k, h+k; c_k (inverse) = X~_k - i X~_{n-k}
-      const CT dk = d(k), dnk = d(N - k), dp = d(H - k), dnp = d(H + k);
+      const CT dk = d(k), dnk = k > 0 ? d(N - k) : (CT)0, dp = d(H - k), dnp = d(H + k);
       const CT xk = ck.x * dk;
       const CT xnk = k > 0 ? -ck.y * dnk : (CT)0;
       const CT xp = cp.x * dp;
@@ -760,6 +582,7 @@ __global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int i
       st.sc[SC_RR] = rr;
       if (rr <= st.sc[SC_TOL2] * st.sc[SC_BB]) {
         st.fl[FL_DONE] = 1;
+        st.fl[FL_DPEND] = 1;   // d += alpha p of this iteration is still owed
         return;
       }
     }
@@ -778,29 +601,52 @@ __global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int i
 // place with no barrier between its reads and writes.
 // OUT: 0 z and the dots z.r, sum z; 1 also z.q (flexible beta); 2 the new
 // direction p = z + beta p_in into z (p_in, passed as q, unread at iter 0),
-// no dots.
+// no dots, and with dacc non-null the iterate update of the iteration
+// before, dacc += alpha_{iter-1} p_in -- alone if the rho pass stopped the
+// solve on convergence (FL_DPEND).
 template <class CT, class SI, class TO, int H, int OUT>
 __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
     const SI* __restrict__ in, int64_t ld, TO* __restrict__ z, const TO* __restrict__ r,
-    const TO* __restrict__ q, const void* twp, DevState st, int use_scale, int iter) {
+    const TO* __restrict__ q, TO* __restrict__ dacc, const void* twp, DevState st,
+    int use_scale, int iter) {
   constexpr bool FLEX = OUT == 1;
-  if (st.fl[FL_DONE]) return;
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
+  using V = typename Vec16<TO>::type;
+  constexpr int W = Vec16<TO>::W;
+  constexpr int NCH = ROWS * N / W / kThreads;
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  const bool dupd = OUT == 2 && dacc != nullptr && iter != 0;
+  const TO al = dupd ? (TO)st.sc[SC_ALPHA + ((iter - 1) & 1)] : (TO)0;
+  // chunk b of this thread: dacc += alpha p_in
+  auto add_dir = [&](int b, const V& pb) {
+    const int e0 = (tid + b * kThreads) * W;
+    TO* dp = dacc + (row0 + e0 / N) * ld + e0 % N;
+    V dv = ld_nt<V>(dp);
+#pragma unroll
+    for (int t = 0; t < W; ++t) dv[t] = dv[t] + al * pb[t];
+    st_nt<V>(dp, dv);
+  };
+  if (st.fl[FL_DONE]) {
+    if (dupd && st.fl[FL_DPEND]) {
+#pragma unroll
+      for (int b = 0; b < NCH; ++b) {
+        const int e0 = (tid + b * kThreads) * W;
+        add_dir(b, ld_nt<V>(q + (row0 + e0 / N) * ld + e0 % N));
+      }
+    }
+    return;
+  }
   constexpr int NP = H / 2 + 1;
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
   __shared__ Cx<CT> buf[padded<ROWS * H>()];
   const Tw<CT> tw = tw_of<CT, H>(twp);
-  const int tid = threadIdx.x;
   CT* v = reinterpret_cast<CT*>(buf);
   // output scale: 1/h of the inverse FFT and the 1/2 that pre_pair leaves
   // out, undoing the input scale of the first pass when the intermediates
   // are FP16
   const CT inv_h = (CT)(0.5 / H) / (use_scale ? (CT)st.sc[SC_SCALE] : (CT)1);
   const CT is0 = (CT)sqrt((double)N), is1 = (CT)sqrt(0.5 * N);   // 1 / s_k
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
-  using V = typename Vec16<TO>::type;
-  constexpr int W = Vec16<TO>::W;
-  constexpr int NCH = ROWS * N / W / kThreads;
   // OUT 2: the previous direction, loaded with the stored coefficients so
   // that its latency hides behind the transform (NCH 16-byte chunks per
   // thread, 8 at h = 4096 in FP32; rows longer than that load it after the
@@ -817,6 +663,10 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
         for (int b = 0; b < NCH; ++b) {
           const int e0 = (tid + b * kThreads) * W;
           pv[b] = ld_nt<V>(q + (row0 + e0 / N) * ld + e0 % N);
+        }
+        if (dupd) {
+#pragma unroll
+          for (int b = 0; b < NCH; ++b) add_dir(b, pv[b]);
         }
       }
     }
@@ -850,6 +700,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
       const int row = e0 / N, c = e0 % N;
       if constexpr (!PRE) {
         if (!first) pv[b] = ld_nt<V>(q + (row0 + row) * ld + c);
+        if (dupd) add_dir(b, pv[b]);
       }
       TO zo[W];
       if constexpr (W >= 4) {
@@ -971,6 +822,32 @@ static void launch_transpose(const T* in, int64_t rows, int64_t cols, T* out,
                      dim3(kThreads), 0, s, in, cols, out, rows, done);
 }
 
+template <class T>
+void launch_transpose_any(const T* in, int64_t rows, int64_t cols, T* out, const int32_t* done,
+                          hipStream_t s) {
+  launch_transpose<T>(in, rows, cols, out, done, s);
+}
+template void launch_transpose_any<double>(const double*, int64_t, int64_t, double*,
+                                           const int32_t*, hipStream_t);
+template void launch_transpose_any<float>(const float*, int64_t, int64_t, float*, const int32_t*,
+                                          hipStream_t);
+template void launch_transpose_any<_Float16>(const _Float16*, int64_t, int64_t, _Float16*,
+                                             const int32_t*, hipStream_t);
+template void launch_transpose_any<__bf16>(const __bf16*, int64_t, int64_t, __bf16*,
+                                           const int32_t*, hipStream_t);
+
+void launch_fct_rho(DevState st, int n, int iter, int f16, int nparts_rr, hipStream_t s) {
+  hipLaunchKernelGGL(fct_rho_kernel, dim3(1), dim3(1024), 0, s, st, n, iter, f16, nparts_rr);
+}
+
+void launch_fct_fold_partials(DevState st, int n, hipStream_t s) {
+  hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, st, n);
+}
+
+void launch_cg_alpha(DevState st, int nparts_pq, int iter, int f16, double npix, hipStream_t s) {
+  hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(1024), 0, s, st, nparts_pq, iter, f16, npix);
+}
+
 // ---- tables -----------------------------------------------------------------
 // Thread j: stage-twiddle entry j (j < h - 1), post/pre twiddles j (j <= h),
 // eigenvalue j (j < n), all from FP64.
@@ -1016,7 +893,11 @@ size_t fct_table_bytes(int64_t n, int elem) {
   return (size_t)(3 * (n / 2) + 2) * 2 * (size_t)elem + (size_t)n * (size_t)elem;
 }
 
-void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s) {
+void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s, bool general) {
+  if (general) {
+    launch_fctg_tables(elem, n, tw, eig, s);
+    return;
+  }
   const int nb = (int)((n + kThreads - 1) / kThreads);
   if (elem == 8)
     hipLaunchKernelGGL(fct_tables_kernel<double>, dim3(nb), dim3(kThreads), 0, s, n,
@@ -1104,13 +985,14 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
     if (a.spectral)
       hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, 2>), dim3((unsigned)nb),
                          dim3(kThreads), 0, s, T1, M, static_cast<T*>(a.p_out), r,
-                         static_cast<const T*>(a.p_in), a.twM, a.st, f16, a.iter);
+                         static_cast<const T*>(a.p_in), static_cast<T*>(a.d), a.twM, a.st,
+                         f16, a.iter);
     else if (q)
       hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, 1>), dim3((unsigned)nb),
-                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16, 0);
+                         dim3(kThreads), 0, s, T1, M, z, r, q, nullptr, a.twM, a.st, f16, 0);
     else
       hipLaunchKernelGGL((fct_rows_inv_kernel<CT, ST, T, H, 0>), dim3((unsigned)nb),
-                         dim3(kThreads), 0, s, T1, M, z, r, q, a.twM, a.st, f16, 0);
+                         dim3(kThreads), 0, s, T1, M, z, r, q, nullptr, a.twM, a.st, f16, 0);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT3, s);
   if (!a.spectral) {
@@ -1121,6 +1003,7 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
 }
 
 int fct_row_blocks(int64_t N, int64_t M) {
+  if (!fct_supported(N) || !fct_supported(M)) return fctg_row_blocks(N, M);
   int nb = 0;
   with_h(M / 2, [&](auto hc) {
     constexpr int H = decltype(hc)::value;
@@ -1130,8 +1013,8 @@ int fct_row_blocks(int64_t N, int64_t M) {
 }
 
 template <class CT, class T, class ST>
-static int cg_update_impl(const PrecondArgs& a, T* r, T* d, const T* p, const T* q, int nparts_pq,
-                          int iter, int nparts_out, hipStream_t s) {
+static int cg_update_impl(const PrecondArgs& a, T* r, const T* q, int nparts_pq, int iter,
+                          int nparts_out, hipStream_t s) {
   const int64_t N = a.N, M = a.M;
   const int f16 = std::is_same<ST, _Float16>::value ? 1 : 0;
   LaunchLog* L = a.log;
@@ -1143,36 +1026,39 @@ static int cg_update_impl(const PrecondArgs& a, T* r, T* d, const T* p, const T*
     constexpr int H = decltype(hc)::value;
     nb = (int)(N / rows_per_block<H>());
     hipLaunchKernelGGL((fct_rows_fwd_cg_kernel<CT, T, ST, H>), dim3((unsigned)nb),
-                       dim3(kThreads), 0, s, r, d, p, q, M, static_cast<ST*>(a.T1), a.twM, a.st,
-                       iter, f16, nparts_out);
+                       dim3(kThreads), 0, s, r, q, M, static_cast<ST*>(a.T1), a.twM, a.st, iter,
+                       f16, nparts_out);
   });
   log_mark(L, IRLSU_LK_UPDATE_DCT2, s);
   return nb;
 }
 
 template <class T>
-int launch_cg_update_fast(const PrecondArgs& a, T* r, T* d, const T* p, const T* q,
-                          int nparts_pq, int iter, int nparts_out, hipStream_t s) {
+int launch_cg_update_fast(const PrecondArgs& a, T* r, const T* q, int nparts_pq, int iter,
+                          int nparts_out, hipStream_t s) {
+  if (!fct_supported(a.N) || !fct_supported(a.M))
+    return launch_cg_update_fastg<T>(a, r, q, nparts_pq, iter, nparts_out, s);
   if constexpr (std::is_same<T, double>::value) {
-    return cg_update_impl<double, double, double>(a, r, d, p, q, nparts_pq, iter, nparts_out, s);
+    return cg_update_impl<double, double, double>(a, r, q, nparts_pq, iter, nparts_out, s);
   } else {
     switch (a.kind) {
-      case OK_F32: return cg_update_impl<float, float, float>(a, r, d, p, q, nparts_pq, iter,
-                                                              nparts_out, s);
-      case OK_BF16: return cg_update_impl<float, float, __bf16>(a, r, d, p, q, nparts_pq, iter,
-                                                                nparts_out, s);
-      case OK_F16: return cg_update_impl<float, float, _Float16>(a, r, d, p, q, nparts_pq, iter,
-                                                                 nparts_out, s);
+      case OK_F32:
+        return cg_update_impl<float, float, float>(a, r, q, nparts_pq, iter, nparts_out, s);
+      case OK_BF16:
+        return cg_update_impl<float, float, __bf16>(a, r, q, nparts_pq, iter, nparts_out, s);
+      case OK_F16:
+        return cg_update_impl<float, float, _Float16>(a, r, q, nparts_pq, iter, nparts_out, s);
     }
     return 0;
   }
 }
-template int launch_cg_update_fast<float>(const PrecondArgs&, float*, float*, const float*,
-                                          const float*, int, int, int, hipStream_t);
-template int launch_cg_update_fast<double>(const PrecondArgs&, double*, double*, const double*,
-                                           const double*, int, int, int, hipStream_t);
+template int launch_cg_update_fast<float>(const PrecondArgs&, float*, const float*, int, int, int,
+                                          hipStream_t);
+template int launch_cg_update_fast<double>(const PrecondArgs&, double*, const double*, int, int,
+                                           int, hipStream_t);
 
 int launch_precond_fast(const PrecondArgs& a, hipStream_t s) {
+  if (!fct_supported(a.N) || !fct_supported(a.M)) return launch_precond_fastg(a, s);
   switch (a.kind) {
     case OK_F64: return fast_impl<double, double, double>(a, s);
     case OK_F32: return fast_impl<float, float, float>(a, s);

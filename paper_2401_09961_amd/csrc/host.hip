@@ -448,7 +448,8 @@ irlsu_status pcg_solve(irlsu_plan* pl, const Ws<T>& W, double* x, const T* rhs,
       fused.p_in = P[l & 1];
       fused.p_out = P[(l + 1) & 1];
       fused.fused_head = 1;
-      launch_cg_update_fast<T>(fused, W.v[V_R], d, P[l & 1], W.v[V_Q], npq, l, nrr, q);
+      fused.d = d;
+      launch_cg_update_fast<T>(fused, W.v[V_R], W.v[V_Q], npq, l, nrr, q);
       launch_precond(fused, q);
       return;
     }
@@ -1456,7 +1457,9 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
   const bool even = (N % 2 == 0) && (M % 2 == 0);
   if (form == IRLSU_PLAN_FOLDED && !even) return IRLSU_ERR_SHAPE;
   const bool pow2 = fct_supported(N) && fct_supported(M);
-  if (form == IRLSU_PLAN_FAST && !pow2) return IRLSU_ERR_SHAPE;
+  // sides with factors 2, 3 and 5 only (a multiple of 8, half at most 8192)
+  const bool general = !pow2 && fctg_supported(N) && fctg_supported(M);
+  if (form == IRLSU_PLAN_FAST && !pow2 && !general) return IRLSU_ERR_SHAPE;
   irlsu_plan* p = new (std::nothrow) irlsu_plan;
   if (!p) return IRLSU_ERR_OOM;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1473,7 +1476,7 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
   }
   // the fast form wherever it applies; else the folded form once the
   // products dominate its extra passes
-  p->fast = form == IRLSU_PLAN_FAST || (form == IRLSU_PLAN_AUTO && pow2);
+  p->fast = form == IRLSU_PLAN_FAST || (form == IRLSU_PLAN_AUTO && (pow2 || general));
   p->folded = !p->fast && (form == IRLSU_PLAN_FOLDED ||
                            (form == IRLSU_PLAN_AUTO && even && p->Np * p->Mp >= ((int64_t)1 << 20)));
   p->hNp = round_up(N / 2, kTilePad);
@@ -1548,8 +1551,8 @@ irlsu_status irlsu_plan_create_ex(irlsu_plan** out, int64_t N, int64_t M, irlsu_
     return IRLSU_ERR_OOM;
   }
   if (p->fast) {
-    launch_fct_tables(p->elem, N, p->twN, p->eigN, s);
-    if (p->twM != p->twN) launch_fct_tables(p->elem, M, p->twM, p->eigM, s);
+    launch_fct_tables(p->elem, N, p->twN, p->eigN, s, general);
+    if (p->twM != p->twN) launch_fct_tables(p->elem, M, p->twM, p->eigM, s, general);
   } else if (p->folded) {
     launch_fold_basis(p->kind, N, p->hNp, p->PeN, p->PeNt, p->PoN, p->PoNt, p->eigNf, s);
     if (p->PeM != p->PeN)

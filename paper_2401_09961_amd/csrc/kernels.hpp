@@ -266,6 +266,11 @@ struct PrecondArgs {
   int iter = 0;
   const void* p_in = nullptr;
   void* p_out = nullptr;
+  // with spectral and a fused head: the iterate correction (T); the last
+  // pass adds alpha_{iter-1} p_in to it while it reads p_in for the new
+  // direction, and, if the rho pass found convergence (FL_DPEND), does only
+  // that
+  void* d = nullptr;
   // the row DCT-II of r already ran, fused with the CG update that produced r
   // (launch_cg_update_fast); the prologue then only tests convergence
   int fused_head = 0;
@@ -278,11 +283,13 @@ int fct_row_blocks(int64_t N, int64_t M);
 // The CG update of iteration iter fused with the first pass of the next
 // preconditioner application: alpha (and the FP16 input scale from the bound
 // ||r|| + |alpha| ||q|| on the new residual) in one block, then per row
-// r -= alpha q, d += alpha p and the DCT-II of the new r into a.T1; partials
-// ||r||^2, sum r zero padded to nparts_out.  Returns the row-pass grid.
+// r -= alpha q and the DCT-II of the new r into a.T1; partials ||r||^2,
+// sum r zero padded to nparts_out.  The iterate update d += alpha p is left
+// to the application's last pass (PrecondArgs::d), which reads p anyway.
+// Returns the row-pass grid.
 template <class T>
-int launch_cg_update_fast(const PrecondArgs& a, T* r, T* d, const T* p, const T* q,
-                          int nparts_pq, int iter, int nparts_out, hipStream_t s);
+int launch_cg_update_fast(const PrecondArgs& a, T* r, const T* q, int nparts_pq, int iter,
+                          int nparts_out, hipStream_t s);
 
 // ---- augmented (U, V^v, V^h) solve ------------------------------------------
 template <class T>
@@ -318,7 +325,28 @@ int aug_launch(int op, const AugArgs<T>& a, const AugVec<T>& x, const AugVec<T>&
                hipStream_t s);
 bool fct_supported(int64_t n);
 size_t fct_table_bytes(int64_t n, int elem);
-void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s);
+// general: the layout of the sides that are not powers of two (fctg.hip),
+// also where one side of such a plan is a power of two
+void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s,
+                       bool general = false);
+// Fast form for plans whose sides are not both powers of two (fctg.hip):
+// each side n a multiple of 8 whose half has no prime factor above 5,
+// n / 2 <= 8192.  The plan's vectors keep their row stride Mp and T1 / T2
+// span the padded Np x Mp.
+bool fctg_supported(int64_t n);
+int fctg_row_blocks(int64_t N, int64_t M);
+void launch_fctg_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s);
+int launch_precond_fastg(const PrecondArgs& a, hipStream_t s);
+template <class T>
+int launch_cg_update_fastg(const PrecondArgs& a, T* r, const T* q, int nparts_pq, int iter,
+                           int nparts_out, hipStream_t s);
+// pieces of the power-of-two passes that the general sizes share
+template <class T>
+void launch_transpose_any(const T* in, int64_t rows, int64_t cols, T* out, const int32_t* done,
+                          hipStream_t s);
+void launch_fct_rho(DevState st, int n, int iter, int f16, int nparts_rr, hipStream_t s);
+void launch_fct_fold_partials(DevState st, int n, hipStream_t s);
+void launch_cg_alpha(DevState st, int nparts_pq, int iter, int f16, double npix, hipStream_t s);
 // Returns the number of partials written by the last product (z.r etc.).
 int launch_precond(const PrecondArgs& a, hipStream_t s);
 // Grouped preconditioner over the tiles of a batch (operand kind of the

@@ -163,6 +163,7 @@ __global__ __launch_bounds__(kThreads) void finalize_weights_kernel(
     st.sc[SC_BB] = bb;
     st.sc[SC_TOL2] = tol2;
     st.fl[FL_DONE] = 0;
+    st.fl[FL_DPEND] = 0;
     st.fl[FL_ITERS] = 0;
     if (out) {
       out[0] = l1;

@@ -80,7 +80,12 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, in
                                              int rows_per_block, int lb) {
   using IO = StencilIO<T, MODE>;
   using CT = typename IO::CT;
-  if (a.check_done && a.st.fl[FL_DONE]) return;
+  if (a.check_done && a.st.fl[FL_DONE]) {
+    // the row DCT-III pass before this launch paid the iterate update that
+    // the converged iteration owed
+    if (lb == 0 && threadIdx.x == 0 && a.st.fl[FL_DPEND]) a.st.fl[FL_DPEND] = 0;
+    return;
+  }
 
   CT beta = 0, zc = 0;
   if constexpr (MODE == ST_FUSED) {

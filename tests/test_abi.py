@@ -65,10 +65,13 @@ def test_host_validation_without_gpu(lib):
     assert lib.irlsu_plan_create(ctypes.byref(h), 8, 0, 1, None) == -2
     assert lib.irlsu_plan_create(ctypes.byref(h), 8, 8, 7, None) == -8
     assert lib.irlsu_plan_create(ctypes.byref(h), 32769, 8, 1, None) == -2
-    # form: 0 auto, 1 dense, 2 folded (even sides), 3 fast (powers of two >= 128)
+    # form: 0 auto, 1 dense, 2 folded (even sides), 3 fast (powers of two
+    # >= 128, or each side a multiple of 8 whose half is at most 8192 and has
+    # no prime factor above 5)
     assert lib.irlsu_plan_create_ex(ctypes.byref(h), 8, 8, 1, 4, None) == -1
-    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 96, 128, 1, 3, None) == -2
-    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 64, 64, 1, 3, None) == -2
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 112, 128, 1, 3, None) == -2   # 56 = 8 x 7
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 100, 128, 1, 3, None) == -2   # 100 % 8
+    assert lib.irlsu_plan_create_ex(ctypes.byref(h), 128, 20000, 1, 3, None) == -2  # 10000 > 8192
     assert lib.irlsu_plan_create_ex(ctypes.byref(h), 8, 8, 1, -1, None) == -1
     assert lib.irlsu_plan_create_ex(ctypes.byref(h), 9, 8, 1, 2, None) == -2
     assert lib.irlsu_plan_create_ex(ctypes.byref(h), 8, 7, 1, 2, None) == -2

@@ -41,6 +41,20 @@ def test_folded_form_rated_on_executed_flops():
     assert abs(roof["dense_equivalent_TFLOPs"] - 2 * roof["achieved"]) < 0.02
 
 
+def test_fused_head_moves_the_iterate_update_to_the_last_pass():
+    """With the CG update fused into the row DCT-II, d += alpha p is paid by
+    the row DCT-III pass: the fused update reads q, r and writes r, T1; the
+    last pass reads T, p_old, d and writes p, d."""
+    N = M = 8192
+    px = N * M
+    launches = [("stencil", 0.2), ("alpha", 0.005), ("update_dct2", 0.2), ("transpose", 0.05),
+                ("cols", 0.14), ("partials", 0.008), ("transpose", 0.05), ("rows_dct3", 0.17)]
+    kern = bench.kernel_table(launches, "f16", "fast", N, M, flexible=False)
+    assert kern["fct_rows_fwd_cg_kernel"]["bytes_per_launch"] == 14 * px
+    assert kern["fct_rows_inv_kernel"]["bytes_per_launch"] == 18 * px
+    assert kern["stencil_kernel"]["bytes_per_launch"] == 16 * px
+
+
 def test_f64_bytes_double():
     kern = bench.kernel_table([("stencil", 1.0), ("axpy", 1.0)], "f64", "folded", 256, 256, False)
     assert kern["stencil_kernel"]["bytes_per_launch"] == 48 * 256 * 256
@@ -62,3 +76,16 @@ def test_roofline_skips_the_issue_bound_column_pass():
                               "fast", 512, 512, False)
     roof = bench.roofline(kern, "f16")
     assert roof["kernel"] == "fct_rows_inv_kernel" and roof["bound"] == "hbm"
+
+
+def test_alu_roofline_of_the_column_pass():
+    """The column pass (bound by instruction issue) is rated in
+    lane-instructions per second against 256 CUs x 4 SIMDs x 16 lanes x
+    2.4 GHz."""
+    kern = {"fct_cols_kernel": {"bound": "alu", "launches": 1, "ms": 0.1, "bytes_per_launch": 1},
+            "stencil_kernel": {"bound": "hbm", "launches": 1, "ms": 0.2, "bytes_per_launch": 1}}
+    out = bench.alu_roofline(kern, {"fct_cols_kernel": 1e6})
+    assert list(out) == ["fct_cols_kernel"]
+    ach = 1e6 * 64 / 1e-4 / 1e12
+    assert abs(out["fct_cols_kernel"]["achieved"] - ach) < 0.01
+    assert abs(bench.VALU_PEAK_T - 39.3216) < 1e-3

@@ -278,6 +278,54 @@ def test_precond_fast_matches_dct_oracle(fprec, shape):
     plan.close()
 
 
+# sides that are not powers of two: the same passes with run-time sizes and
+# FFT stages of radix 2^k, 3 and 5 (h = n/2 = 60, 100, 300, 500, 48, 2000,
+# 8000); one side a power of two with the other general; one and several
+# rows per block and the largest half-length (16000 = 2 x 8000)
+GENERAL_SHAPES = [(120, 200), (600, 1000), (4000, 96), (240, 4000), (8192, 1000), (1000, 16000)]
+
+
+@pytest.mark.parametrize("shape", GENERAL_SHAPES)
+@pytest.mark.parametrize("fprec", ["f64", "f32", "bf16", "f16"])
+def test_precond_fast_general_sides_match_dct_oracle(fprec, shape):
+    """The fast form on sides whose halves factor into 2, 3 and 5 against
+    scipy's orthonormal DCT: the same bars and element-wise bound as the
+    power-of-two sides."""
+    N, M = shape
+    dt = npdt(fprec)
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal((N, M)).astype(dt)
+    plan = pkg.Plan(N, M, fprec, form="fast")
+    assert plan.form == "fast"
+    z, rz = plan.precond(internal(plan, r))
+    torch.cuda.synchronize()
+    z_o = R.apply_precond(r.astype(np.float64))
+    zg = z.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
+    print(f"precond fast (general sides) {fprec} {shape}: rel err {rel:.3e}")
+    assert rel <= FAST_RTOL[fprec]
+    assert_elementwise(zg[:N, :M], r, "fast", fprec)
+    # the padding of the plan's arrays stays zero
+    assert np.all(zg[N:, :] == 0) and np.all(zg[:, M:] == 0)
+    ref = float(np.sum(r.astype(np.float64) * z_o))
+    assert abs(rz.item() - ref) <= 2 * FAST_RTOL[fprec] * abs(ref)
+    plan.close()
+
+
+def test_precond_fast_general_is_pseudo_inverse_property_f64():
+    """L z = r - mean(r) for the general-size fast form (600 x 120)."""
+    N, M = 600, 120
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal((N, M))
+    plan = pkg.Plan(N, M, "f64", form="fast")
+    z, _ = plan.precond(internal(plan, r))
+    zg = z.cpu().numpy()[:N, :M]
+    Lz = R.apply_A(np.ones((N - 1, M)), np.ones((N, M - 1)), zg)
+    assert np.abs(Lz - (r - r.mean())).max() < 1e-10
+    assert abs(zg.mean()) < 1e-12
+    plan.close()
+
+
 def test_precond_fast_is_pseudo_inverse_property_f64():
     """The fast form solves the Neumann problem: L z = r - mean(r)."""
     N, M = 512, 256

@@ -1,6 +1,8 @@
 """The paper's scaling shape 4000 x M, M from 2000 to 16000 (the running-time
-study of Section 4): sides that are not powers of two run the MFMA forms
-with rectangular bases (P_N != P_M), folded when both sides are even.
+study of Section 4).  These sides are multiples of 8 whose halves have only
+the factors 2 and 5 (and 3 for 6000), so the default plan runs the fast form
+with mixed-radix FFTs; the MFMA forms with rectangular bases (P_N != P_M,
+folded when both sides are even) are checked at the same shapes.
 
 Bars: the preconditioner against the oracle's FP64 transform (scipy's
 orthonormal DCT) at full size, relative 2-norm error -- 16-bit operands
@@ -32,11 +34,14 @@ from oracle import reduced as R
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("form", ["auto", "folded"])
 @pytest.mark.parametrize("M,prec", [(2000, "f16"), (16000, "f16"), (6000, "f32")])
-def test_preconditioner_4000_by_m(M, prec):
+def test_preconditioner_4000_by_m(M, prec, form):
+    """The default plan (the fast form) and the folded MFMA form at full
+    size against the oracle's transform; the padding of z stays zero."""
     N = 4000
-    plan = pkg.Plan(N, M, prec)
-    assert plan.form == "folded"
+    plan = pkg.Plan(N, M, prec, form=form)
+    assert plan.form == ("fast" if form == "auto" else form)
     g = torch.Generator(device="cuda").manual_seed(8)
     r = torch.zeros((plan.Np, plan.ld), device="cuda", dtype=plan.dtype)
     r[:N, :M] = torch.randn((N, M), device="cuda", generator=g, dtype=plan.dtype)
@@ -46,23 +51,27 @@ def test_preconditioner_4000_by_m(M, prec):
     for pad in (z[N:, :], z[:, M:]):
         assert pad.numel() == 0 or float(pad.abs().max()) == 0
     rn = r[:N, :M].double().cpu().numpy()
+    plan_form = plan.form
     plan.close()
     del r, z
     zo = R.apply_precond(rn, workers=min(16, os.cpu_count() or 1))
     rel = np.linalg.norm(zn - zo) / np.linalg.norm(zo)
-    print(f"precond {prec} 4000x{M}: rel err {rel:.3e}")
+    print(f"precond {plan_form} {prec} 4000x{M}: rel err {rel:.3e}")
     assert rel <= {"f16": 3e-2, "f32": 2e-5}[prec]
 
 
+@pytest.mark.parametrize("form", ["auto", "dense"])
 @pytest.mark.parametrize("prec", ["f32", "f16"])
-def test_unwrap_tenth_scale_400_by_1600(prec):
-    """400 x 1600 (the 4000 x 16000 aspect): dense form, c2-type residue
-    field, converged solves, L1 against the oracle."""
+def test_unwrap_tenth_scale_400_by_1600(prec, form):
+    """400 x 1600 (the 4000 x 16000 aspect): the default plan (fast form)
+    and the dense form, c2-type residue field, converged solves, L1 against
+    the oracle."""
     f = synth.field_c2(9, 400, 1600)
     dt = np.float32
     X = f.X.astype(dt)
     w = f.w.astype(dt)
-    plan = pkg.Plan(400, 1600, prec)
+    plan = pkg.Plan(400, 1600, prec, form=form)
+    assert plan.form == ("fast" if form == "auto" else form)
     p = pkg.default_params(prec)
     p.irls_iters, p.pcg_max, p.pcg_rtol = 4, 3000, 1e-6
     _, st = plan.unwrap(torch.from_numpy(X).cuda(), torch.from_numpy(w).cuda(), params=p,
@@ -71,7 +80,7 @@ def test_unwrap_tenth_scale_400_by_1600(prec):
     Uo, hist = R.irls(X.astype(np.float64), w=w.astype(np.float64), iters=4, tol=1e-6,
                       maxit=3000, workers=min(16, os.cpu_count() or 1))
     gap = abs(st["L1_final"] - hist[-1]["L1"]) / hist[-1]["L1"]
-    print(f"{prec} 400x1600: GPU L1 {st['L1_final']:.8g} oracle {hist[-1]['L1']:.8g} gap {gap:.2e}")
+    print(f"{prec} {form} 400x1600: GPU L1 {st['L1_final']:.8g} oracle {hist[-1]['L1']:.8g} gap {gap:.2e}")
     assert gap <= {"f32": 1e-5, "f16": 1e-3}[prec]
 
 
@@ -89,16 +98,18 @@ def _field_4000(dt):
     return torch.from_numpy(X).cuda(), torch.from_numpy(w).cuda()
 
 
+@pytest.mark.parametrize("form", ["fast", "folded"])
 @pytest.mark.parametrize("prec", ["f64"])
-def test_full_size_4000_by_2000_one_step(prec):
+def test_full_size_4000_by_2000_one_step(prec, form):
     """One weight step and 30 PCG iterations on the 4000 x 2000 field (the
-    folded MFMA form with rectangular bases) against the oracle's record."""
+    mixed-radix fast form, and the folded MFMA form with rectangular bases)
+    against the oracle's record."""
     with open(REF_4000_30) as fh:
         ref = json.load(fh)
     assert ref["N"] == 4000 and ref["M"] == 2000 and ref["maxit"] == 30 and ref["tol"] == 0.0
     X, w = _field_4000(np.float64 if prec == "f64" else np.float32)
-    plan = pkg.Plan(4000, 2000, prec)
-    assert plan.form == "folded"
+    plan = pkg.Plan(4000, 2000, prec, form=form)
+    assert plan.form == form
     p = pkg.default_params(prec)
     p.irls_iters, p.pcg_max, p.pcg_rtol, p.eps, p.true_res_every = 1, 30, 0.0, ref["eps"], 0
     U, st = plan.unwrap(X, w, params=p, stats=True)
@@ -110,7 +121,7 @@ def test_full_size_4000_by_2000_one_step(prec):
     dL1 = abs(st["L1_final"] - ref["L1_final"]) / ref["L1_final"]
     dH = abs(st["H_final"] - ref["H_final"]) / ref["H_final"]
     dU = float(np.max(np.abs(Us - np.asarray(ref["samples"]["U"])))) / ref["U_maxabs"]
-    print(f"4000x2000 one step {prec}: L1 rel {dL1:.2e}, H rel {dH:.2e}, U {dU:.2e}")
+    print(f"4000x2000 one step {prec} {form}: L1 rel {dL1:.2e}, H rel {dH:.2e}, U {dU:.2e}")
     bar_obj, bar_u = ONESTEP_BARS[prec]
     assert st["pcg_total"] == 30
     assert dL1 <= bar_obj and dH <= bar_obj and dU <= bar_u
@@ -118,14 +129,16 @@ def test_full_size_4000_by_2000_one_step(prec):
 
 @pytest.mark.parametrize("prec", ["f16", "f32"])
 def test_full_size_4000_by_2000_reaches_the_target(prec):
-    """The capped 20 x 100 schedule end to end at full size: the first IRLS
-    iterate within 1e-3 of the oracle's final L1 is reached, and its L1 is
-    within 1e-3 of the oracle's."""
+    """The capped 20 x 100 schedule end to end at full size (the default
+    plan: the fast form): the first IRLS iterate within 1e-3 of the
+    oracle's final L1 is reached, and its L1 is within 1e-3 of the
+    oracle's."""
     with open(REF_4000) as fh:
         ref = json.load(fh)
     assert ref["complete"] and ref["maxit"] == 100
     X, w = _field_4000(np.float32)
     plan = pkg.Plan(4000, 2000, prec)
+    assert plan.form == "fast"
     p = pkg.default_params(prec)
     L1_ref = ref["L1_final"]
     p.irls_iters, p.pcg_max, p.eps = 40, ref["maxit"], ref["eps"]
