@@ -378,30 +378,36 @@ def paper_shapes(pkg, torch, synth, a, prec):
     unwrap with X and w resident in HBM, HIP events, after one warm-up."""
     torch.cuda.set_device(0)
     rows = []
+    # the default plan (the mixed-radix fast form at these sides) and the
+    # folded MFMA form, unless --form names one
+    forms = ["auto", "folded"] if a.form == "auto" else [a.form]
     for M in (2000, 4000, 8000, 12000, 16000):
         N = 4000
-        print(f"[bench] paper shape {N}x{M}", file=sys.stderr, flush=True)
         f = synth.field_c2(a.seed, N, M)
         X = torch.from_numpy(f.X).to(device="cuda", dtype=torch.float32)
         w = torch.from_numpy(f.w).to(device="cuda", dtype=torch.float32)
-        plan = pkg.Plan(N, M, prec)
-        p = pkg.default_params(prec)
-        p.irls_iters, p.pcg_max = 20, 100
-        U = torch.empty((N, M), dtype=torch.float32, device="cuda")
-        plan.unwrap(X, w, params=p, out=U)
-        s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(s)
-        _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
-        e1.record(s)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        rows.append({"N": N, "M": M, "form": plan.form, "ms_per_unwrap": round(ms, 2),
-                     "Mpixel_per_s": round(N * M / 1e6 / (ms * 1e-3), 3),
-                     "pcg_iters": st["pcg_total"], "L1_final": st["L1_final"]})
-        plan.close()
-        del X, w, U
+        for form in forms:
+            print(f"[bench] paper shape {N}x{M} {form}", file=sys.stderr, flush=True)
+            plan = pkg.Plan(N, M, prec, form=form)
+            p = pkg.default_params(prec)
+            p.irls_iters, p.pcg_max = 20, 100
+            U = torch.empty((N, M), dtype=torch.float32, device="cuda")
+            plan.unwrap(X, w, params=p, out=U)
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(s)
+            _, st = plan.unwrap(X, w, params=p, out=U, stats=True)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rows.append({"N": N, "M": M, "form": plan.form, "ms_per_unwrap": round(ms, 2),
+                         "Mpixel_per_s": round(N * M / 1e6 / (ms * 1e-3), 3),
+                         "ms_per_pcg_iter": round(ms / max(1, st["pcg_total"]), 4),
+                         "pcg_iters": st["pcg_total"], "L1_final": st["L1_final"]})
+            plan.close()
+            del U
+        del X, w
     line = {"metric": "seconds per unwrap of 4000 x M (20 IRLS x 100 PCG)", "unit": "ms",
             "precision": prec, "data": "synthetic (c2-type fields)", "paper_shapes": rows}
     print(json.dumps(line), flush=True)

@@ -62,8 +62,16 @@ bool make_plan(int64_t h, GPlan* p) {
   return rem == 1;
 }
 
+// Threads per block: 256, or 512 for rows longer than 4096 points, whose
+// 64 KiB of LDS (FP32) leave room for only two blocks per CU -- twice the
+// waves to hide the latencies of the stages.
+template <int CAP>
+constexpr int g_threads() {
+  return CAP > kGPts ? 512 : 256;
+}
+
 // blocks per CU that the LDS of one block leaves room for, as the register
-// budget the kernels are compiled to (4 blocks: 128 VGPRs, 2 or 1: 256)
+// budget the kernels are compiled to (waves per SIMD: blocks x threads / 256)
 template <class CT, int CAP>
 constexpr int g_min_blocks() {
   return CAP * (int)sizeof(Cx<CT>) <= 32768 ? 4 : CAP * (int)sizeof(Cx<CT>) <= 65536 ? 2 : 1;
@@ -134,7 +142,8 @@ template <class CT, int R, int CAP>
 __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
                                         const Cx<CT>* __restrict__ root, int tid0) {
   const int tid = opaque(tid0);
-  constexpr int NBM = (CAP / R + kThreads - 1) / kThreads;
+  constexpr int NT = g_threads<CAP>();
+  constexpr int NBM = (CAP / R + NT - 1) / NT;
   // unsigned: the divisions by the uniform bpr and ns then need no sign fix
   const unsigned bpr = (unsigned)h / R, total = (unsigned)rows * bpr;
   const unsigned step = (unsigned)h / ((unsigned)ns * R), uns = (unsigned)ns;
@@ -142,7 +151,7 @@ __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
   int dst[NBM];
 #pragma unroll
   for (int b = 0; b < NBM; ++b) {
-    const unsigned bi = (unsigned)tid + (unsigned)b * kThreads;
+    const unsigned bi = (unsigned)tid + (unsigned)b * NT;
     if (bi < total) {
       const unsigned row = bi / bpr, j = bi - row * bpr;
       const unsigned k = j % uns;
@@ -162,7 +171,7 @@ __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NBM; ++b) {
-    const unsigned bi = (unsigned)tid + (unsigned)b * kThreads;
+    const unsigned bi = (unsigned)tid + (unsigned)b * NT;
     if (bi < total) {
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[dst[b] + r * ns] = a[b][r];
@@ -227,17 +236,17 @@ __device__ __forceinline__ void g_pre_pair(Cx<CT> ck, Cx<CT> cp, int h, int k, c
 
 // Streams the block's rows (n elements each, 16-byte chunks) through f(row,
 // column, chunk), eight chunks per thread in flight at a time.
-template <class TI, class F>
+template <class TI, int NT, class F>
 __device__ __forceinline__ void g_rows_in(const TI* __restrict__ in, int64_t ld, int64_t row0,
                                           int rows, int n, int tid, F&& f) {
   using V = typename Vec16<TI>::type;
   constexpr int W = Vec16<TI>::W;
   const int cpr = n / W, total = rows * cpr;
-  for (int base = 0; base < total; base += 8 * kThreads) {
+  for (int base = 0; base < total; base += 8 * NT) {
     V d[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int ci = base + tid + u * kThreads;
+      const int ci = base + tid + u * NT;
       if (ci < total) {
         const int row = ci / cpr, c = (ci - row * cpr) * W;
         d[u] = ld_nt<V>(in + (row0 + row) * ld + c);
@@ -245,7 +254,7 @@ __device__ __forceinline__ void g_rows_in(const TI* __restrict__ in, int64_t ld,
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int ci = base + tid + u * kThreads;
+      const int ci = base + tid + u * NT;
       if (ci < total) {
         const int row = ci / cpr, c = (ci - row * cpr) * W;
         f(row, c, d[u]);
@@ -316,13 +325,13 @@ __device__ __forceinline__ void g_inv_chunk(const Cx<CT>* buf, int h, int row, i
 
 // DCT-II outputs of the block's rows from the FFT in LDS: X_k = s_k Re c_k,
 // X_{n-k} = -s_k Im c_k (twice c from the post-processing, so s/2)
-template <class CT, class TO>
+template <class CT, class TO, int NT>
 __device__ __forceinline__ void g_store_dct2(const Cx<CT>* buf, int h, int rows, const GTw<CT>& tw,
                                              TO* __restrict__ out, int64_t ldo, int64_t row0,
                                              int tid) {
   const int n = 2 * h, np = h / 2 + 1;
   const CT s0 = (CT)(0.5 * sqrt(1.0 / n)), s1 = (CT)(0.5 * sqrt(2.0 / n));
-  for (int p = tid; p < rows * np; p += kThreads) {
+  for (int p = tid; p < rows * np; p += NT) {
     const int row = p / np, k = p - row * np;
     Cx<CT> ck, cp;
     g_post_pair<CT>(buf + row * h, h, k, tw, ck, cp);
@@ -338,9 +347,10 @@ __device__ __forceinline__ void g_store_dct2(const Cx<CT>* buf, int h, int rows,
 
 // ---- pass 1: DCT-II along rows ---------------------------------------------
 template <class CT, class TI, class TO, int CAP>
-__global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fwd_kernel(
+__global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_rows_fwd_kernel(
     const TI* __restrict__ in, int64_t ld, TO* __restrict__ out, int64_t ldo, int64_t nrows,
     GPlan pl, const void* twp, const int32_t* done, const double* scale_p) {
+  constexpr int NT = g_threads<CAP>();
   if (*done) return;
   __shared__ Cx<CT> buf[CAP];
   const int h = pl.h, tid = threadIdx.x;
@@ -351,18 +361,19 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fw
   const CT scale = scale_p ? (CT)*scale_p : (CT)1;
   using V = typename Vec16<TI>::type;
   constexpr int W = Vec16<TI>::W;
-  g_rows_in<TI>(in, ld, row0, rows, 2 * h, tid,
+  g_rows_in<TI, NT>(in, ld, row0, rows, 2 * h, tid,
                 [&](int row, int c, const V& d) { g_put<CT, V, W>(buf, h, row, c, d, scale); });
   __syncthreads();
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
-  g_store_dct2<CT, TO>(buf, h, rows, tw, out, ldo, row0, opaque(tid));
+  g_store_dct2<CT, TO, NT>(buf, h, rows, tw, out, ldo, row0, opaque(tid));
 }
 
 // ---- CG update fused with pass 1 (fct_rows_fwd_cg_kernel) --------------------
 template <class CT, class T, class TO, int CAP>
-__global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fwd_cg_kernel(
+__global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_rows_fwd_cg_kernel(
     T* __restrict__ r, const T* __restrict__ q, int64_t ld, TO* __restrict__ out, int64_t ldo,
     int64_t nrows, GPlan pl, const void* twp, DevState st, int iter, int f16, int nparts_out) {
+  constexpr int NT = g_threads<CAP>();
   if (st.fl[FL_DONE]) return;
   __shared__ Cx<CT> buf[CAP];
   const int h = pl.h, n = 2 * h, tid = threadIdx.x;
@@ -376,11 +387,11 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fw
   constexpr int W = Vec16<T>::W;
   double acc[2] = {0.0, 0.0};
   const int cpr = n / W, total = rows * cpr;
-  for (int base = 0; base < total; base += 4 * kThreads) {
+  for (int base = 0; base < total; base += 4 * NT) {
     V qv[4], rv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int ci = base + tid + u * kThreads;
+      const int ci = base + tid + u * NT;
       if (ci < total) {
         const int row = ci / cpr, c = (ci - row * cpr) * W;
         const int64_t o = (row0 + row) * ld + c;
@@ -390,7 +401,7 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fw
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int ci = base + tid + u * kThreads;
+      const int ci = base + tid + u * NT;
       if (ci < total) {
         const int row = ci / cpr, c = (ci - row * cpr) * W;
 #pragma unroll
@@ -406,9 +417,9 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fw
   }
   __syncthreads();
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
-  g_store_dct2<CT, TO>(buf, h, rows, tw, out, ldo, row0, opaque(tid));
+  g_store_dct2<CT, TO, NT>(buf, h, rows, tw, out, ldo, row0, opaque(tid));
   const int slots[2] = {PR_RR, PR_RSUM};
-  write_partials<2>(st, slots, acc, (int)blockIdx.x);
+  write_partials<2, NT>(st, slots, acc, (int)blockIdx.x);
   if (threadIdx.x == 0) {
     for (int k = (int)blockIdx.x + (int)gridDim.x; k < nparts_out; k += (int)gridDim.x) {
       part_row(st, PR_RR)[k] = 0.0;
@@ -420,11 +431,12 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_fw
 // ---- pass 3: DCT-II, spectral division, DCT-III along the rows of the
 // transposed intermediate (fct_cols_kernel) ---------------------------------
 template <class CT, class ST, int CAP, bool RHO>
-__global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_cols_kernel(ST* __restrict__ io, int64_t ld,
+__global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_cols_kernel(ST* __restrict__ io, int64_t ld,
                                                           int64_t nrows, GPlan pl,
                                                           const void* twp,
                                                           const double* __restrict__ eig_l,
                                                           DevState st) {
+  constexpr int NT = g_threads<CAP>();
   if (st.fl[FL_DONE]) return;
   __shared__ Cx<CT> buf[CAP];
   const int h = pl.h, n = 2 * h, tid = threadIdx.x;
@@ -434,13 +446,13 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_cols_ke
   const GTw<CT> tw = gtw_of<CT>(twp, h);
   using V = typename Vec16<ST>::type;
   constexpr int W = Vec16<ST>::W;
-  g_rows_in<ST>(io, ld, row0, rows, n, tid,
+  g_rows_in<ST, NT>(io, ld, row0, rows, n, tid,
                 [&](int row, int c, const V& d) { g_put<CT, V, W>(buf, h, row, c, d, (CT)1); });
   __syncthreads();
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
   CT rho = (CT)0;
   const int np = h / 2 + 1;
-  for (int p = opaque(tid); p < rows * np; p += kThreads) {
+  for (int p = opaque(tid); p < rows * np; p += NT) {
     const int row = p / np, k = p - row * np;
     const int64_t l = row0 + row;
     const CT mu = (CT)eig_l[l];
@@ -464,7 +476,7 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_cols_ke
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
   const CT inv_h = (CT)(0.25 / h);
   const int cpr = n / W;
-  for (int ci = opaque(tid); ci < rows * cpr; ci += kThreads) {
+  for (int ci = opaque(tid); ci < rows * cpr; ci += NT) {
     const int row = ci / cpr, c = (ci - row * cpr) * W;
     ST ot[W];
     g_inv_chunk<CT, W, ST>(buf, h, row, c, inv_h, ot);
@@ -476,7 +488,7 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_cols_ke
   if constexpr (RHO) {
     double acc[1] = {(double)rho * (0.5 / (double)n)};
     const int slots[1] = {PR_ZR};
-    write_partials<1>(st, slots, acc, (int)blockIdx.x);
+    write_partials<1, NT>(st, slots, acc, (int)blockIdx.x);
   }
 }
 
@@ -486,10 +498,11 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_cols_ke
 // non-null dacc += alpha_{iter-1} p_in -- alone if the rho pass stopped the
 // solve on convergence (FL_DPEND).
 template <class CT, class SI, class TO, int CAP, int OUT>
-__global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_inv_kernel(
+__global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_rows_inv_kernel(
     const SI* __restrict__ in, int64_t ldi, TO* __restrict__ z, int64_t ld,
     const TO* __restrict__ r, const TO* __restrict__ q, TO* __restrict__ dacc, int64_t nrows,
     int64_t nrows_pad, GPlan pl, const void* twp, DevState st, int use_scale, int iter) {
+  constexpr int NT = g_threads<CAP>();
   const int h = pl.h, n = 2 * h, tid = threadIdx.x;
   const int rpb = rows_per_block_g(h);
   const int64_t row0 = (int64_t)blockIdx.x * rpb;
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_in
   };
   if (st.fl[FL_DONE]) {
     if (dupd && st.fl[FL_DPEND]) {
-      for (int ci = tid; ci < total; ci += kThreads) add_dir(ci);
+      for (int ci = tid; ci < total; ci += NT) add_dir(ci);
     }
     return;
   }
@@ -520,14 +533,14 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_in
   const CT is0 = (CT)sqrt((double)n), is1 = (CT)sqrt(0.5 * n);
   using VI = typename Vec16<SI>::type;
   constexpr int WI = Vec16<SI>::W;
-  g_rows_in<SI>(in, ldi, row0, rows, n, tid,
+  g_rows_in<SI, NT>(in, ldi, row0, rows, n, tid,
                 [&](int row, int c, const VI& d) { g_put_inv<CT, VI, WI>(buf, h, row, c, d); });
   if (dupd) {
-    for (int ci = tid; ci < total; ci += kThreads) add_dir(ci);
+    for (int ci = tid; ci < total; ci += NT) add_dir(ci);
   }
   __syncthreads();
   const int np = h / 2 + 1;
-  for (int p = opaque(tid); p < rows * np; p += kThreads) {
+  for (int p = opaque(tid); p < rows * np; p += NT) {
     const int row = p / np, k = p - row * np;
     const Cx<CT>* b = buf + row * h;
     const Cx<CT> A = b[k];
@@ -542,7 +555,7 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_in
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
   double acc[3] = {0.0, 0.0, 0.0};
   const TO beta = OUT == 2 ? (TO)st.sc[SC_BETA] : (TO)0;
-  for (int ci = opaque(tid); ci < total; ci += kThreads) {
+  for (int ci = opaque(tid); ci < total; ci += NT) {
     const int row = ci / cpr, c = (ci - row * cpr) * W;
     const int64_t o = (row0 + row) * ld + c;
     TO zo[W];
@@ -576,15 +589,15 @@ __global__ __launch_bounds__(kThreads, (g_min_blocks<CT, CAP>())) void g_rows_in
   // [n, ld) of the block's rows, and the rows [nrows, nrows_pad) spread over
   // the blocks
   const int padc = (int)(ld - n);
-  for (int i = opaque(tid); i < rows * padc; i += kThreads) {
+  for (int i = opaque(tid); i < rows * padc; i += NT) {
     const int row = i / padc;
     z[(row0 + row) * ld + n + (i - row * padc)] = (TO)0;
   }
   for (int64_t pr = nrows + blockIdx.x; pr < nrows_pad; pr += gridDim.x)
-    for (int64_t j = tid; j < ld; j += kThreads) z[pr * ld + j] = (TO)0;
+    for (int64_t j = tid; j < ld; j += NT) z[pr * ld + j] = (TO)0;
   if constexpr (OUT != 2) {
     const int slots[3] = {PR_ZR, PR_ZQ, PR_ZS};
-    write_partials<3>(st, slots, acc, (int)blockIdx.x);
+    write_partials<3, NT>(st, slots, acc, (int)blockIdx.x);
   }
 }
 
@@ -648,7 +661,7 @@ int fastg_impl(const PrecondArgs& a, hipStream_t s) {
     with_cap(M / 2, [&](auto cap) {
       constexpr int CAP = decltype(cap)::value;
       hipLaunchKernelGGL((g_rows_fwd_kernel<CT, T, ST, CAP>), dim3(blocks_g(N, M / 2)),
-                         dim3(kThreads), 0, s, r, Mp, T1, Mp, N, pM, a.twM, done,
+                         dim3(g_threads<CAP>()), 0, s, r, Mp, T1, Mp, N, pM, a.twM, done,
                          f16 ? a.st.sc + SC_SCALE : nullptr);
     });
     log_mark(L, IRLSU_LK_ROWS_DCT2, s);
@@ -659,10 +672,10 @@ int fastg_impl(const PrecondArgs& a, hipStream_t s) {
   with_cap(N / 2, [&](auto cap) {
     constexpr int CAP = decltype(cap)::value;
     if (a.spectral)
-      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, true>), dim3(ncols), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, true>), dim3(ncols), dim3(g_threads<CAP>()), 0, s,
                          T2, Np, M, pN, a.twN, static_cast<const double*>(a.eigM), a.st);
     else
-      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, false>), dim3(ncols), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, false>), dim3(ncols), dim3(g_threads<CAP>()), 0, s,
                          T2, Np, M, pN, a.twN, static_cast<const double*>(a.eigM), a.st);
   });
   log_mark(L, IRLSU_LK_COLS, s);
@@ -676,14 +689,14 @@ int fastg_impl(const PrecondArgs& a, hipStream_t s) {
   with_cap(M / 2, [&](auto cap) {
     constexpr int CAP = decltype(cap)::value;
     if (a.spectral)
-      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 2>), dim3(nb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 2>), dim3(nb), dim3(g_threads<CAP>()), 0, s,
                          T1, Mp, static_cast<T*>(a.p_out), Mp, r, static_cast<const T*>(a.p_in),
                          static_cast<T*>(a.d), N, Np, pM, a.twM, a.st, f16, a.iter);
     else if (q)
-      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 1>), dim3(nb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 1>), dim3(nb), dim3(g_threads<CAP>()), 0, s,
                          T1, Mp, z, Mp, r, q, nullptr, N, Np, pM, a.twM, a.st, f16, 0);
     else
-      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 0>), dim3(nb), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 0>), dim3(nb), dim3(g_threads<CAP>()), 0, s,
                          T1, Mp, z, Mp, r, q, nullptr, N, Np, pM, a.twM, a.st, f16, 0);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT3, s);
@@ -706,7 +719,7 @@ int cg_update_g(const PrecondArgs& a, T* r, const T* q, int nparts_pq, int iter,
   const int nb = blocks_g(N, M / 2);
   with_cap(M / 2, [&](auto cap) {
     constexpr int CAP = decltype(cap)::value;
-    hipLaunchKernelGGL((g_rows_fwd_cg_kernel<CT, T, ST, CAP>), dim3(nb), dim3(kThreads), 0, s, r,
+    hipLaunchKernelGGL((g_rows_fwd_cg_kernel<CT, T, ST, CAP>), dim3(nb), dim3(g_threads<CAP>()), 0, s, r,
                        q, Mp, static_cast<ST*>(a.T1), Mp, N, pM, a.twM, a.st, iter, f16,
                        nparts_out);
   });

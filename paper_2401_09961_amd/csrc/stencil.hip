@@ -11,7 +11,7 @@
 // cross-lane shuffles; only the wave's two edge lanes read their outside
 // neighbour from memory, so no wave waits for another (no barrier in the
 // row loop).  The weights and halo of row i+1 and the p row i+2 are loaded
-// before row i is computed.  The arrays streamed once per pass are read and
+// before row i is computed, up to the last row the band needs.  The arrays streamed once per pass are read and
 // written with non-temporal hints: on gfx950 that lifts a three-read /
 // one-write stream from about 5.2 to 5.7 TB/s at 8192^2.  HBM traffic per
 // pixel: p, Omega^v, Omega^h in, q out = 16 bytes (FP32; fused form z,
@@ -123,12 +123,16 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, in
   int64_t r1 = r0 + rows_per_block;
   if (r1 > a.Np) r1 = a.Np;
   const int64_t ld = a.ld;
+  // rows the band reads: p from r0 - 1 to r1, the weights from r0 - 1 to
+  // r1 - 1 (the loads one row ahead stop there instead of running past)
+  const int64_t plim = r1 < a.Np ? r1 + 1 : a.Np;
+  const int64_t wlim = r1;
 
   // weights of row i (zero outside the image rows)
   auto weights = [&](int64_t i, V4<CT>& ov, V4<CT>& oh) {
     ov = zero4<CT>();
     oh = zero4<CT>();
-    if (active && i < a.Np) {
+    if (active && i < wlim) {
       const V4<T> ovt = ld4_nt(a.Ov + i * ld + j0);
       const V4<T> oht = ld4_nt(a.Oh + i * ld + j0);
 #pragma unroll
@@ -143,7 +147,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, in
   auto halo = [&](int64_t i, CT& hp, CT& hoh) {
     hp = (CT)0;
     hoh = (CT)0;
-    if (i < a.Np && cw < ld) {
+    if (i < wlim && cw < ld) {
       if (lane == 0 && cw > 0) {
         hp = io.p1(i, cw - 1);
         hoh = (CT)a.Oh[i * ld + cw - 1];
@@ -152,7 +156,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T>& a, int bx, in
       }
     }
   };
-  auto prow = [&](int64_t i) { return active ? io.p4(i, j0) : zero4<CT>(); };
+  auto prow = [&](int64_t i) { return active && i < plim ? io.p4(i, j0) : zero4<CT>(); };
 
   V4<CT> pu = prow(r0 - 1), pc = prow(r0), pd = prow(r0 + 1), ovu = zero4<CT>();
   if (active && r0 > 0) {
