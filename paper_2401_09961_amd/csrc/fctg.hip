@@ -33,7 +33,16 @@ struct GPlan {
   int h;
   int nst;
   int radix[kGMaxStages];
+  // per stage, ceil(2^32 / d) for d = h / R (butterflies per row) and for
+  // d = ns (the span): x / d = umulhi(x, m) exactly while x d < 2^32, which
+  // holds here (x, d <= 8192); d = 1 is never divided by
+  unsigned mag_bpr[kGMaxStages];
+  unsigned mag_ns[kGMaxStages];
 };
+
+unsigned div_magic(int64_t d) {
+  return d <= 1 ? 0u : (unsigned)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
+}
 
 // radices of an h-point FFT, first stage to last (false if h has a prime
 // factor above 5)
@@ -58,6 +67,12 @@ bool make_plan(int64_t h, GPlan* p) {
       if (p->nst == kGMaxStages) return false;
       p->radix[p->nst++] = f;
     }
+  }
+  int64_t ns = 1;
+  for (int i = 0; i < p->nst; ++i) {
+    p->mag_bpr[i] = div_magic(h / p->radix[i]);
+    p->mag_ns[i] = div_magic(ns);
+    ns *= p->radix[i];
   }
   return rem == 1;
 }
@@ -140,7 +155,8 @@ __device__ __forceinline__ void g_twiddles(const Cx<CT>* __restrict__ root, int 
 // registers across the barrier; CAP bounds rows x h, hence their count.
 template <class CT, int R, int CAP>
 __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
-                                        const Cx<CT>* __restrict__ root, int tid0) {
+                                        const Cx<CT>* __restrict__ root, unsigned mag_bpr,
+                                        unsigned mag_ns, int tid0) {
   const int tid = opaque(tid0);
   constexpr int NT = g_threads<CAP>();
   constexpr int NBM = (CAP / R + NT - 1) / NT;
@@ -153,8 +169,9 @@ __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
   for (int b = 0; b < NBM; ++b) {
     const unsigned bi = (unsigned)tid + (unsigned)b * NT;
     if (bi < total) {
-      const unsigned row = bi / bpr, j = bi - row * bpr;
-      const unsigned k = j % uns;
+      const unsigned row = bpr == 1 ? bi : __umulhi(bi, mag_bpr);
+      const unsigned j = bi - row * bpr;
+      const unsigned k = uns == 1 ? 0u : j - __umulhi(j, mag_ns) * uns;
       const Cx<CT>* sp = buf + row * h + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) a[b][r] = sp[r * bpr];
@@ -187,13 +204,14 @@ __device__ __forceinline__ void g_fft(Cx<CT>* buf, const GPlan& pl, int rows,
 #pragma nounroll
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.radix[s];
+    const unsigned mb = pl.mag_bpr[s], mn = pl.mag_ns[s];
     switch (R) {
-      case 16: g_stage<CT, 16, CAP>(buf, pl.h, ns, rows, root, tid); break;
-      case 8: g_stage<CT, 8, CAP>(buf, pl.h, ns, rows, root, tid); break;
-      case 4: g_stage<CT, 4, CAP>(buf, pl.h, ns, rows, root, tid); break;
-      case 2: g_stage<CT, 2, CAP>(buf, pl.h, ns, rows, root, tid); break;
-      case 5: g_stage<CT, 5, CAP>(buf, pl.h, ns, rows, root, tid); break;
-      default: g_stage<CT, 3, CAP>(buf, pl.h, ns, rows, root, tid); break;
+      case 16: g_stage<CT, 16, CAP>(buf, pl.h, ns, rows, root, mb, mn, tid); break;
+      case 8: g_stage<CT, 8, CAP>(buf, pl.h, ns, rows, root, mb, mn, tid); break;
+      case 4: g_stage<CT, 4, CAP>(buf, pl.h, ns, rows, root, mb, mn, tid); break;
+      case 2: g_stage<CT, 2, CAP>(buf, pl.h, ns, rows, root, mb, mn, tid); break;
+      case 5: g_stage<CT, 5, CAP>(buf, pl.h, ns, rows, root, mb, mn, tid); break;
+      default: g_stage<CT, 3, CAP>(buf, pl.h, ns, rows, root, mb, mn, tid); break;
     }
     ns *= R;
   }
