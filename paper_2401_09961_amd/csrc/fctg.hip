@@ -38,6 +38,10 @@ struct GPlan {
   // holds here (x, d <= 8192); d = 1 is never divided by
   unsigned mag_bpr[kGMaxStages];
   unsigned mag_ns[kGMaxStages];
+  // the same for the pairs per row (h/2 + 1) and the 16-byte chunks per row
+  // (2h / W for W = 2, 4, 8 elements)
+  unsigned mag_np;
+  unsigned mag_c[3];
 };
 
 unsigned div_magic(int64_t d) {
@@ -68,6 +72,10 @@ bool make_plan(int64_t h, GPlan* p) {
       p->radix[p->nst++] = f;
     }
   }
+  p->mag_np = div_magic(h / 2 + 1);
+  p->mag_c[0] = div_magic(h);
+  p->mag_c[1] = div_magic(h / 2);
+  p->mag_c[2] = div_magic(h / 4);
   int64_t ns = 1;
   for (int i = 0; i < p->nst; ++i) {
     p->mag_bpr[i] = div_magic(h / p->radix[i]);
@@ -90,6 +98,16 @@ constexpr int g_threads() {
 template <class CT, int CAP>
 constexpr int g_min_blocks() {
   return CAP * (int)sizeof(Cx<CT>) <= 32768 ? 4 : CAP * (int)sizeof(Cx<CT>) <= 65536 ? 2 : 1;
+}
+
+// x / d for a uniform divisor d with m = ceil(2^32 / d) (GPlan: exact for the
+// index ranges that occur, x d < 2^32)
+__device__ __forceinline__ int udiv(int x, int d, unsigned m) {
+  return d == 1 ? x : (int)__umulhi((unsigned)x, m);
+}
+template <int W>
+__device__ __forceinline__ unsigned chunk_magic(const GPlan& pl) {
+  return pl.mag_c[W == 2 ? 0 : W == 4 ? 1 : 2];
 }
 
 __host__ __device__ inline int rows_per_block_g(int64_t h) { return h >= kGPts ? 1 : (int)(kGPts / h); }
@@ -127,22 +145,34 @@ __device__ __forceinline__ int opaque(int v) {
   return r;
 }
 
-// w[r] = root[r m] for r = 1..R-1 (r m < h): the powers 1, 2, 4 and 8 from
-// the table, the others as products of two of them (at most three
-// roundings), which keeps a radix-16 butterfly at four table loads.
+// Twiddles of a butterfly, w[r] = root[r m] for r = 1..R-1 (r m < h): the
+// powers 1, 2, 4 and 8 from the table (g_tw_load), the others as products
+// of two of them (g_tw_expand, at most three roundings), which keeps a
+// radix-16 butterfly at four table loads.
+template <int R>
+constexpr int g_tw_loads() {
+  return R == 2 ? 1 : R <= 4 ? 2 : R <= 8 ? 3 : 4;
+}
 template <class CT, int R>
-__device__ __forceinline__ void g_twiddles(const Cx<CT>* __restrict__ root, int m,
-                                           Cx<CT> (&w)[R]) {
-  w[1] = root[m];
-  if constexpr (R > 2) w[2] = root[2 * m];
+__device__ __forceinline__ void g_tw_load(const Cx<CT>* __restrict__ root, int m,
+                                          Cx<CT> (&t)[g_tw_loads<R>()]) {
+  t[0] = root[m];
+  if constexpr (R > 2) t[1] = root[2 * m];
+  if constexpr (R > 4) t[2] = root[4 * m];
+  if constexpr (R > 8) t[3] = root[8 * m];
+}
+template <class CT, int R>
+__device__ __forceinline__ void g_tw_expand(const Cx<CT> (&t)[g_tw_loads<R>()], Cx<CT> (&w)[R]) {
+  w[1] = t[0];
+  if constexpr (R > 2) w[2] = t[1];
   if constexpr (R > 3) w[3] = cmul(w[1], w[2]);
-  if constexpr (R > 4) w[4] = root[4 * m];
+  if constexpr (R > 4) w[4] = t[2];
   if constexpr (R > 5) {
 #pragma unroll
     for (int r = 5; r < 8; ++r) w[r] = cmul(w[4], w[r - 4]);
   }
   if constexpr (R > 8) {
-    w[8] = root[8 * m];
+    w[8] = t[3];
 #pragma unroll
     for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
   }
@@ -153,6 +183,10 @@ __device__ __forceinline__ void g_twiddles(const Cx<CT>* __restrict__ root, int 
 // root[r (j mod ns) h / (ns R)], and writes its R-point DFT to
 // (j - j mod ns) R + j mod ns + r ns.  A thread holds its butterflies in
 // registers across the barrier; CAP bounds rows x h, hence their count.
+// Straight-line loads: a butterfly index past the block's last one reads
+// butterfly 0's points and twiddles (in range) and skips only its writes, so
+// all of a thread's table and LDS loads are in flight before the first
+// product instead of one butterfly's at a time.
 template <class CT, int R, int CAP>
 __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
                                         const Cx<CT>* __restrict__ root, unsigned mag_bpr,
@@ -160,36 +194,45 @@ __device__ __forceinline__ void g_stage(Cx<CT>* buf, int h, int ns, int rows,
   const int tid = opaque(tid0);
   constexpr int NT = g_threads<CAP>();
   constexpr int NBM = (CAP / R + NT - 1) / NT;
+  constexpr int NL = g_tw_loads<R>();
   // unsigned: the divisions by the uniform bpr and ns then need no sign fix
   const unsigned bpr = (unsigned)h / R, total = (unsigned)rows * bpr;
   const unsigned step = (unsigned)h / ((unsigned)ns * R), uns = (unsigned)ns;
   Cx<CT> a[NBM][R];
-  int dst[NBM];
+  Cx<CT> t[NBM][NL];
+  int src[NBM], dst[NBM];
+  bool act[NBM];
 #pragma unroll
   for (int b = 0; b < NBM; ++b) {
-    const unsigned bi = (unsigned)tid + (unsigned)b * NT;
-    if (bi < total) {
-      const unsigned row = bpr == 1 ? bi : __umulhi(bi, mag_bpr);
-      const unsigned j = bi - row * bpr;
-      const unsigned k = uns == 1 ? 0u : j - __umulhi(j, mag_ns) * uns;
-      const Cx<CT>* sp = buf + row * h + j;
+    const unsigned bu = (unsigned)tid + (unsigned)b * NT;
+    act[b] = bu < total;
+    const unsigned bi = act[b] ? bu : 0u;
+    const unsigned row = bpr == 1 ? bi : __umulhi(bi, mag_bpr);
+    const unsigned j = bi - row * bpr;
+    const unsigned k = uns == 1 ? 0u : j - __umulhi(j, mag_ns) * uns;
+    src[b] = (int)(row * (unsigned)h + j);
+    dst[b] = (int)(row * (unsigned)h + (j - k) * R + k);
+    if (ns > 1) g_tw_load<CT, R>(root, (int)(k * step), t[b]);
+  }
 #pragma unroll
-      for (int r = 0; r < R; ++r) a[b][r] = sp[r * bpr];
-      if (ns > 1) {
-        Cx<CT> w[R];
-        g_twiddles<CT, R>(root, (int)(k * step), w);
+  for (int b = 0; b < NBM; ++b) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], w[r]);
-      }
-      gdft<CT, R>(a[b]);
-      dst[b] = (int)(row * (unsigned)h + (j - k) * R + k);
+    for (int r = 0; r < R; ++r) a[b][r] = buf[src[b] + r * (int)bpr];
+  }
+#pragma unroll
+  for (int b = 0; b < NBM; ++b) {
+    if (ns > 1) {
+      Cx<CT> w[R];
+      g_tw_expand<CT, R>(t[b], w);
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], w[r]);
     }
+    gdft<CT, R>(a[b]);
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NBM; ++b) {
-    const unsigned bi = (unsigned)tid + (unsigned)b * NT;
-    if (bi < total) {
+    if (act[b]) {
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[dst[b] + r * ns] = a[b][r];
     }
@@ -256,7 +299,7 @@ __device__ __forceinline__ void g_pre_pair(Cx<CT> ck, Cx<CT> cp, int h, int k, c
 // column, chunk), eight chunks per thread in flight at a time.
 template <class TI, int NT, class F>
 __device__ __forceinline__ void g_rows_in(const TI* __restrict__ in, int64_t ld, int64_t row0,
-                                          int rows, int n, int tid, F&& f) {
+                                          int rows, int n, unsigned mcpr, int tid, F&& f) {
   using V = typename Vec16<TI>::type;
   constexpr int W = Vec16<TI>::W;
   const int cpr = n / W, total = rows * cpr;
@@ -266,7 +309,7 @@ __device__ __forceinline__ void g_rows_in(const TI* __restrict__ in, int64_t ld,
     for (int u = 0; u < 8; ++u) {
       const int ci = base + tid + u * NT;
       if (ci < total) {
-        const int row = ci / cpr, c = (ci - row * cpr) * W;
+        const int row = udiv(ci, cpr, mcpr), c = (ci - row * cpr) * W;
         d[u] = ld_nt<V>(in + (row0 + row) * ld + c);
       }
     }
@@ -274,7 +317,7 @@ __device__ __forceinline__ void g_rows_in(const TI* __restrict__ in, int64_t ld,
     for (int u = 0; u < 8; ++u) {
       const int ci = base + tid + u * NT;
       if (ci < total) {
-        const int row = ci / cpr, c = (ci - row * cpr) * W;
+        const int row = udiv(ci, cpr, mcpr), c = (ci - row * cpr) * W;
         f(row, c, d[u]);
       }
     }
@@ -346,11 +389,11 @@ __device__ __forceinline__ void g_inv_chunk(const Cx<CT>* buf, int h, int row, i
 template <class CT, class TO, int NT>
 __device__ __forceinline__ void g_store_dct2(const Cx<CT>* buf, int h, int rows, const GTw<CT>& tw,
                                              TO* __restrict__ out, int64_t ldo, int64_t row0,
-                                             int tid) {
+                                             unsigned mnp, int tid) {
   const int n = 2 * h, np = h / 2 + 1;
   const CT s0 = (CT)(0.5 * sqrt(1.0 / n)), s1 = (CT)(0.5 * sqrt(2.0 / n));
   for (int p = tid; p < rows * np; p += NT) {
-    const int row = p / np, k = p - row * np;
+    const int row = udiv(p, np, mnp), k = p - row * np;
     Cx<CT> ck, cp;
     g_post_pair<CT>(buf + row * h, h, k, tw, ck, cp);
     TO* o = out + (row0 + row) * ldo;
@@ -379,11 +422,11 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   const CT scale = scale_p ? (CT)*scale_p : (CT)1;
   using V = typename Vec16<TI>::type;
   constexpr int W = Vec16<TI>::W;
-  g_rows_in<TI, NT>(in, ld, row0, rows, 2 * h, tid,
+  g_rows_in<TI, NT>(in, ld, row0, rows, 2 * h, chunk_magic<W>(pl), tid,
                 [&](int row, int c, const V& d) { g_put<CT, V, W>(buf, h, row, c, d, scale); });
   __syncthreads();
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
-  g_store_dct2<CT, TO, NT>(buf, h, rows, tw, out, ldo, row0, opaque(tid));
+  g_store_dct2<CT, TO, NT>(buf, h, rows, tw, out, ldo, row0, pl.mag_np, opaque(tid));
 }
 
 // ---- CG update fused with pass 1 (fct_rows_fwd_cg_kernel) --------------------
@@ -411,7 +454,7 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
     for (int u = 0; u < 4; ++u) {
       const int ci = base + tid + u * NT;
       if (ci < total) {
-        const int row = ci / cpr, c = (ci - row * cpr) * W;
+        const int row = udiv(ci, cpr, chunk_magic<W>(pl)), c = (ci - row * cpr) * W;
         const int64_t o = (row0 + row) * ld + c;
         qv[u] = ld_nt<V>(q + o);
         rv[u] = ld_nt<V>(r + o);
@@ -421,7 +464,7 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
     for (int u = 0; u < 4; ++u) {
       const int ci = base + tid + u * NT;
       if (ci < total) {
-        const int row = ci / cpr, c = (ci - row * cpr) * W;
+        const int row = udiv(ci, cpr, chunk_magic<W>(pl)), c = (ci - row * cpr) * W;
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           rv[u][t] = rv[u][t] - al * qv[u][t];
@@ -435,7 +478,7 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   }
   __syncthreads();
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
-  g_store_dct2<CT, TO, NT>(buf, h, rows, tw, out, ldo, row0, opaque(tid));
+  g_store_dct2<CT, TO, NT>(buf, h, rows, tw, out, ldo, row0, pl.mag_np, opaque(tid));
   const int slots[2] = {PR_RR, PR_RSUM};
   write_partials<2, NT>(st, slots, acc, (int)blockIdx.x);
   if (threadIdx.x == 0) {
@@ -464,14 +507,14 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   const GTw<CT> tw = gtw_of<CT>(twp, h);
   using V = typename Vec16<ST>::type;
   constexpr int W = Vec16<ST>::W;
-  g_rows_in<ST, NT>(io, ld, row0, rows, n, tid,
+  g_rows_in<ST, NT>(io, ld, row0, rows, n, chunk_magic<W>(pl), tid,
                 [&](int row, int c, const V& d) { g_put<CT, V, W>(buf, h, row, c, d, (CT)1); });
   __syncthreads();
   g_fft<CT, CAP>(buf, pl, rows, tw.root, tid);
   CT rho = (CT)0;
   const int np = h / 2 + 1;
   for (int p = opaque(tid); p < rows * np; p += NT) {
-    const int row = p / np, k = p - row * np;
+    const int row = udiv(p, np, pl.mag_np), k = p - row * np;
     const int64_t l = row0 + row;
     const CT mu = (CT)eig_l[l];
     auto d = [&](int kk) -> CT { return (l == 0 && kk == 0) ? (CT)0 : recip(tw.eig[kk] + mu); };
@@ -495,7 +538,7 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   const CT inv_h = (CT)(0.25 / h);
   const int cpr = n / W;
   for (int ci = opaque(tid); ci < rows * cpr; ci += NT) {
-    const int row = ci / cpr, c = (ci - row * cpr) * W;
+    const int row = udiv(ci, cpr, chunk_magic<W>(pl)), c = (ci - row * cpr) * W;
     ST ot[W];
     g_inv_chunk<CT, W, ST>(buf, h, row, c, inv_h, ot);
     V o;
@@ -531,7 +574,7 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   const bool dupd = OUT == 2 && dacc != nullptr && iter != 0;
   const TO al = dupd ? (TO)st.sc[SC_ALPHA + ((iter - 1) & 1)] : (TO)0;
   auto add_dir = [&](int ci) {
-    const int row = ci / cpr, c = (ci - row * cpr) * W;
+    const int row = udiv(ci, cpr, chunk_magic<W>(pl)), c = (ci - row * cpr) * W;
     const int64_t o = (row0 + row) * ld + c;
     const V pv = ld_nt<V>(q + o);
     V dv = ld_nt<V>(dacc + o);
@@ -551,15 +594,12 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   const CT is0 = (CT)sqrt((double)n), is1 = (CT)sqrt(0.5 * n);
   using VI = typename Vec16<SI>::type;
   constexpr int WI = Vec16<SI>::W;
-  g_rows_in<SI, NT>(in, ldi, row0, rows, n, tid,
+  g_rows_in<SI, NT>(in, ldi, row0, rows, n, chunk_magic<WI>(pl), tid,
                 [&](int row, int c, const VI& d) { g_put_inv<CT, VI, WI>(buf, h, row, c, d); });
-  if (dupd) {
-    for (int ci = tid; ci < total; ci += NT) add_dir(ci);
-  }
   __syncthreads();
   const int np = h / 2 + 1;
   for (int p = opaque(tid); p < rows * np; p += NT) {
-    const int row = p / np, k = p - row * np;
+    const int row = udiv(p, np, pl.mag_np), k = p - row * np;
     const Cx<CT>* b = buf + row * h;
     const Cx<CT> A = b[k];
     const Cx<CT> B = b[k == 0 ? 0 : h - k];
@@ -574,14 +614,21 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
   double acc[3] = {0.0, 0.0, 0.0};
   const TO beta = OUT == 2 ? (TO)st.sc[SC_BETA] : (TO)0;
   for (int ci = opaque(tid); ci < total; ci += NT) {
-    const int row = ci / cpr, c = (ci - row * cpr) * W;
+    const int row = udiv(ci, cpr, chunk_magic<W>(pl)), c = (ci - row * cpr) * W;
     const int64_t o = (row0 + row) * ld + c;
     TO zo[W];
     g_inv_chunk<CT, W, TO>(buf, h, row, c, inv_h, zo);
     V out;
     if constexpr (OUT == 2) {
       if (iter != 0) {
+        // p_in once, for the new direction and for the iterate update
         const V pv = ld_nt<V>(q + o);
+        if (dupd) {
+          V dv = ld_nt<V>(dacc + o);
+#pragma unroll
+          for (int t = 0; t < W; ++t) dv[t] = dv[t] + al * pv[t];
+          st_nt<V>(dacc + o, dv);
+        }
 #pragma unroll
         for (int t = 0; t < W; ++t) out[t] = zo[t] + beta * pv[t];
       } else {
