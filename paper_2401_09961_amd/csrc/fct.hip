@@ -571,12 +571,13 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
 // input scale), stored for iteration iter with beta = rho / rho_{iter-1}
 // (0 at iter 0).  nparts_rr > 0: also the convergence test on the ||r||^2
 // partials of the fused update (the prologue's job on the other path; a
-// converged solve then wasted only the passes before this one).
-__global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int iter, int f16,
-                                                      int nparts_rr) {
-  if (st.fl[FL_DONE]) return;
-  double rho = reduce_slot<1024>(st, PR_ZR, n);
-  const double rr = nparts_rr > 0 ? reduce_slot<1024>(st, PR_RR, nparts_rr) : 0.0;
+// converged solve then wasted only the passes before this one).  Run by the
+// first block of the transpose that follows the column pass.
+template <int NT>
+__device__ __forceinline__ void rho_body(const DevState& st, int n, int iter, int f16,
+                                         int nparts_rr) {
+  double rho = reduce_slot<NT>(st, PR_ZR, n);
+  const double rr = nparts_rr > 0 ? reduce_slot<NT>(st, PR_RR, nparts_rr) : 0.0;
   if (threadIdx.x == 0) {
     if (nparts_rr > 0) {
       st.sc[SC_RR] = rr;
@@ -595,6 +596,7 @@ __global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int i
   }
 }
 
+
 // ---- pass 5: DCT-III along rows, z.r, z.q, sum z -------------------------
 // The stored coefficients go to LDS by put_rows_inv, so that each pair's four
 // inputs sit in the two slots the pair overwrites: the pre-processing runs in
@@ -602,7 +604,7 @@ __global__ __launch_bounds__(1024) void fct_rho_kernel(DevState st, int n, int i
 // OUT: 0 z and the dots z.r, sum z; 1 also z.q (flexible beta); 2 the new
 // direction p = z + beta p_in into z (p_in, passed as q, unread at iter 0),
 // no dots, and with dacc non-null the iterate update of the iteration
-// before, dacc += alpha_{iter-1} p_in -- alone if the rho pass stopped the
+// before, dacc += alpha_{iter-1} p_in -- alone if the rho step stopped the
 // solve on convergence (FL_DPEND).
 template <class CT, class SI, class TO, int H, int OUT>
 __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
@@ -779,10 +781,8 @@ constexpr int transpose_tile() {
 }
 
 template <class T>
-__global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, int64_t ldin,
-                                                            T* __restrict__ out, int64_t ldout,
-                                                            const int32_t* done) {
-  if (*done) return;
+__device__ __forceinline__ void transpose_tile(const T* __restrict__ in, int64_t ldin,
+                                               T* __restrict__ out, int64_t ldout) {
   using V = typename Vec16<T>::type;
   constexpr int TL = transpose_tile<T>();
   constexpr int W = Vec16<T>::W;
@@ -815,6 +815,27 @@ __global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict
 }
 
 template <class T>
+__global__ __launch_bounds__(kThreads) void transpose_kernel(const T* __restrict__ in, int64_t ldin,
+                                                            T* __restrict__ out, int64_t ldout,
+                                                            const int32_t* done) {
+  if (*done) return;
+  transpose_tile<T>(in, ldin, out, ldout);
+}
+
+// The transpose back after the column pass with the rho step (rho_body,
+// 256 threads) in its first block: one launch and one dependent gap
+// less per iteration.  A convergence found there makes the blocks that
+// start later skip their tiles, which the last pass then does not read.
+template <class T>
+__global__ __launch_bounds__(kThreads) void transpose_rho_kernel(
+    const T* __restrict__ in, int64_t ldin, T* __restrict__ out, int64_t ldout, DevState st,
+    int n, int iter, int f16, int nparts_rr) {
+  if (st.fl[FL_DONE]) return;
+  if (blockIdx.x == 0 && blockIdx.y == 0) rho_body<kThreads>(st, n, iter, f16, nparts_rr);
+  transpose_tile<T>(in, ldin, out, ldout);
+}
+
+template <class T>
 static void launch_transpose(const T* in, int64_t rows, int64_t cols, T* out,
                              const int32_t* done, hipStream_t s) {
   constexpr int TL = transpose_tile<T>();
@@ -827,6 +848,22 @@ void launch_transpose_any(const T* in, int64_t rows, int64_t cols, T* out, const
                           hipStream_t s) {
   launch_transpose<T>(in, rows, cols, out, done, s);
 }
+
+template <class T>
+void launch_transpose_rho(const T* in, int64_t rows, int64_t cols, T* out, DevState st, int n,
+                          int iter, int f16, int nparts_rr, hipStream_t s) {
+  constexpr int TL = transpose_tile<T>();
+  hipLaunchKernelGGL(transpose_rho_kernel<T>, dim3((unsigned)(cols / TL), (unsigned)(rows / TL)),
+                     dim3(kThreads), 0, s, in, cols, out, rows, st, n, iter, f16, nparts_rr);
+}
+template void launch_transpose_rho<double>(const double*, int64_t, int64_t, double*, DevState,
+                                           int, int, int, int, hipStream_t);
+template void launch_transpose_rho<float>(const float*, int64_t, int64_t, float*, DevState, int,
+                                          int, int, int, hipStream_t);
+template void launch_transpose_rho<_Float16>(const _Float16*, int64_t, int64_t, _Float16*,
+                                             DevState, int, int, int, int, hipStream_t);
+template void launch_transpose_rho<__bf16>(const __bf16*, int64_t, int64_t, __bf16*, DevState,
+                                           int, int, int, int, hipStream_t);
 template void launch_transpose_any<double>(const double*, int64_t, int64_t, double*,
                                            const int32_t*, hipStream_t);
 template void launch_transpose_any<float>(const float*, int64_t, int64_t, float*, const int32_t*,
@@ -836,9 +873,6 @@ template void launch_transpose_any<_Float16>(const _Float16*, int64_t, int64_t, 
 template void launch_transpose_any<__bf16>(const __bf16*, int64_t, int64_t, __bf16*,
                                            const int32_t*, hipStream_t);
 
-void launch_fct_rho(DevState st, int n, int iter, int f16, int nparts_rr, hipStream_t s) {
-  hipLaunchKernelGGL(fct_rho_kernel, dim3(1), dim3(1024), 0, s, st, n, iter, f16, nparts_rr);
-}
 
 void launch_fct_fold_partials(DevState st, int n, hipStream_t s) {
   hipLaunchKernelGGL(fct_fold_partials_kernel, dim3(1), dim3(kFoldThreads), 0, s, st, n);
@@ -943,7 +977,7 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
   LaunchLog* L = a.log;
   log_start(L, s);
   // fused head: pass 1 ran with the CG update and set the input scale; the
-  // convergence test moves into the rho kernel
+  // convergence test moves into the rho step
   if (!a.fused_head) {
     launch_fold_prologue(a.st, a.nparts_rr, a.check_conv, f16, N * M, s);
     log_mark(L, IRLSU_LK_PROLOGUE, s);
@@ -971,12 +1005,11 @@ static int fast_impl(const PrecondArgs& a, hipStream_t s) {
                          static_cast<const double*>(a.eigM), a.st);
   });
   log_mark(L, IRLSU_LK_COLS, s);
-  if (a.spectral) {
-    hipLaunchKernelGGL(fct_rho_kernel, dim3(1), dim3(1024), 0, s, a.st, ncols, a.iter, f16,
-                       a.fused_head && a.check_conv ? a.nparts_rr : 0);
-    log_mark(L, IRLSU_LK_PARTIALS, s);
-  }
-  launch_transpose<ST>(T2, M, N, T1, done, s);
+  if (a.spectral)
+    launch_transpose_rho<ST>(T2, M, N, T1, a.st, ncols, a.iter, f16,
+                             a.fused_head && a.check_conv ? a.nparts_rr : 0, s);
+  else
+    launch_transpose<ST>(T2, M, N, T1, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
   int nb = 0;
   with_h(M / 2, [&](auto hc) {

@@ -556,7 +556,7 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
 // ---- pass 5: DCT-III along rows (fct_rows_inv_kernel) -------------------------
 // OUT 0: z and the dots z.r, sum z; 1: also z.q; 2: the direction p = z +
 // beta p_in into z (p_in passed as q, unread at iter 0), and with dacc
-// non-null dacc += alpha_{iter-1} p_in -- alone if the rho pass stopped the
+// non-null dacc += alpha_{iter-1} p_in -- alone if the rho step stopped the
 // solve on convergence (FL_DPEND).
 template <class CT, class SI, class TO, int CAP, int OUT>
 __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_rows_inv_kernel(
@@ -744,11 +744,11 @@ int fastg_impl(const PrecondArgs& a, hipStream_t s) {
                          T2, Np, M, pN, a.twN, static_cast<const double*>(a.eigM), a.st);
   });
   log_mark(L, IRLSU_LK_COLS, s);
-  if (a.spectral) {
-    launch_fct_rho(a.st, ncols, a.iter, f16, a.fused_head && a.check_conv ? a.nparts_rr : 0, s);
-    log_mark(L, IRLSU_LK_PARTIALS, s);
-  }
-  launch_transpose_any<ST>(T2, Mp, Np, T1, done, s);
+  if (a.spectral)
+    launch_transpose_rho<ST>(T2, Mp, Np, T1, a.st, ncols, a.iter, f16,
+                             a.fused_head && a.check_conv ? a.nparts_rr : 0, s);
+  else
+    launch_transpose_any<ST>(T2, Mp, Np, T1, done, s);
   log_mark(L, IRLSU_LK_TRANSPOSE, s);
   const int nb = blocks_g(N, M / 2);
   with_cap(M / 2, [&](auto cap) {

@@ -268,7 +268,7 @@ struct PrecondArgs {
   void* p_out = nullptr;
   // with spectral and a fused head: the iterate correction (T); the last
   // pass adds alpha_{iter-1} p_in to it while it reads p_in for the new
-  // direction, and, if the rho pass found convergence (FL_DPEND), does only
+  // direction, and, if the rho step found convergence (FL_DPEND), does only
   // that
   void* d = nullptr;
   // the row DCT-II of r already ran, fused with the CG update that produced r
@@ -344,7 +344,10 @@ int launch_cg_update_fastg(const PrecondArgs& a, T* r, const T* q, int nparts_pq
 template <class T>
 void launch_transpose_any(const T* in, int64_t rows, int64_t cols, T* out, const int32_t* done,
                           hipStream_t s);
-void launch_fct_rho(DevState st, int n, int iter, int f16, int nparts_rr, hipStream_t s);
+// the transpose back with rho, beta and the convergence test in its first block
+template <class T>
+void launch_transpose_rho(const T* in, int64_t rows, int64_t cols, T* out, DevState st, int n,
+                          int iter, int f16, int nparts_rr, hipStream_t s);
 void launch_fct_fold_partials(DevState st, int n, hipStream_t s);
 void launch_cg_alpha(DevState st, int nparts_pq, int iter, int f16, double npix, hipStream_t s);
 // Returns the number of partials written by the last product (z.r etc.).

@@ -206,12 +206,13 @@ def test_profile_records_one_pcg_iteration(form):
     torch.cuda.synchronize()
     kinds = [k for k, _ in rec]
     # fast form, plain beta: the CG update runs fused with the first row
-    # pass (alpha first), rho and the convergence test come after the column
-    # pass (its spectral sum), and the last pass writes the new direction
+    # pass (alpha first), rho and the convergence test run in the first
+    # block of the transpose after the column pass (its spectral sum), and
+    # the last pass writes the new direction
     head = ["stencil", "alpha", "update_dct2"] if form == "fast" else ["stencil", "axpy"]
     assert kinds[:len(head)] == head
     kinds = kinds[len(head) - 2:]
-    expect = {"fast": ["transpose", "cols", "partials", "transpose", "rows_dct3"],
+    expect = {"fast": ["transpose", "cols", "transpose", "rows_dct3"],
               "folded": ["prologue", "butterfly"] + ["product"] * 2 + ["butterfly"]
               + ["product"] * 4 + ["butterfly"] + ["product"] * 2 + ["dots"],
               "dense": ["product"] * 4}[form]
