@@ -40,8 +40,9 @@ def rel(a, b):
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-8), ("f32", 2e-3)])
 # (128, 256): power-of-two sides, the fast preconditioner with the spectral
-# rho and the fused CG update in the adjoint solve
-@pytest.mark.parametrize("shape", [(40, 33), (130, 140), (128, 256)])
+# rho and the fused CG update in the adjoint solve; (120, 200): the same with
+# the mixed-radix passes (halves 60 = 4 x 3 x 5, 100 = 4 x 5 x 5)
+@pytest.mark.parametrize("shape", [(40, 33), (130, 140), (128, 256), (120, 200)])
 def test_adjoint_matches_oracle(prec, tol, shape):
     N, M = shape
     phi, X = residue_field(1, N, M)
