@@ -312,6 +312,33 @@ def test_precond_fast_general_sides_match_dct_oracle(fprec, shape):
     plan.close()
 
 
+# the smallest general sides: one stage (h = 4), one block holding every
+# row, radix-3 and radix-5 stages on tiny rows, padding far larger than the
+# image
+SMALL_GENERAL = [(8, 8), (8, 24), (24, 40), (48, 72), (96, 120), (40, 200)]
+
+
+@pytest.mark.parametrize("shape", SMALL_GENERAL)
+@pytest.mark.parametrize("fprec", ["f64", "f32"])
+def test_precond_fast_small_general_sides(fprec, shape):
+    N, M = shape
+    dt = npdt(fprec)
+    rng = np.random.default_rng(13)
+    r = rng.standard_normal((N, M)).astype(dt)
+    plan = pkg.Plan(N, M, fprec, form="fast")
+    assert plan.form == "fast"
+    z, _ = plan.precond(internal(plan, r))
+    torch.cuda.synchronize()
+    z_o = R.apply_precond(r.astype(np.float64))
+    zg = z.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(zg[:N, :M] - z_o) / np.linalg.norm(z_o)
+    print(f"precond fast (small general sides) {fprec} {shape}: rel err {rel:.3e}")
+    assert rel <= FAST_RTOL[fprec]
+    assert_elementwise(zg[:N, :M], r, "fast", fprec)
+    assert np.all(zg[N:, :] == 0) and np.all(zg[:, M:] == 0)
+    plan.close()
+
+
 def test_precond_fast_general_is_pseudo_inverse_property_f64():
     """L z = r - mean(r) for the general-size fast form (600 x 120)."""
     N, M = 600, 120
