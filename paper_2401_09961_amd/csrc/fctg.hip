@@ -8,8 +8,9 @@
 // Stockham stages of radix 16, 8, 4, 2, 5 and 3 whose plan (the radix list)
 // is a launch argument, and every size a run-time value.
 //
-// Rows of a pass: ceil(4096 / h) rows per block when h <= 4096, else one
-// (4096 or 8192 complex points of LDS).  Stage twiddles come from one table
+// Rows of a pass: floor(4096 / h) rows per block of 256 threads when
+// h <= 4096, else one row per block of 512 threads (at most 4096 or 8192
+// complex points of LDS).  Stage twiddles come from one table
 // of the h-th roots of unity: the twiddle of point r of butterfly j in the
 // stage of span NS and radix R is root[r (j mod NS) h / (NS R)].
 //
@@ -110,7 +111,9 @@ __device__ __forceinline__ unsigned chunk_magic(const GPlan& pl) {
   return pl.mag_c[W == 2 ? 0 : W == 4 ? 1 : 2];
 }
 
-__host__ __device__ inline int rows_per_block_g(int64_t h) { return h >= kGPts ? 1 : (int)(kGPts / h); }
+__host__ __device__ inline int rows_per_block_g(int64_t h) {
+  return h >= kGPts ? 1 : (int)(kGPts / h);
+}
 
 template <class CT>
 struct GTw {
@@ -492,11 +495,9 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
 // ---- pass 3: DCT-II, spectral division, DCT-III along the rows of the
 // transposed intermediate (fct_cols_kernel) ---------------------------------
 template <class CT, class ST, int CAP, bool RHO>
-__global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_cols_kernel(ST* __restrict__ io, int64_t ld,
-                                                          int64_t nrows, GPlan pl,
-                                                          const void* twp,
-                                                          const double* __restrict__ eig_l,
-                                                          DevState st) {
+__global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g_cols_kernel(
+    ST* __restrict__ io, int64_t ld, int64_t nrows, GPlan pl, const void* twp,
+    const double* __restrict__ eig_l, DevState st) {
   constexpr int NT = g_threads<CAP>();
   if (st.fl[FL_DONE]) return;
   __shared__ Cx<CT> buf[CAP];
@@ -737,10 +738,12 @@ int fastg_impl(const PrecondArgs& a, hipStream_t s) {
   with_cap(N / 2, [&](auto cap) {
     constexpr int CAP = decltype(cap)::value;
     if (a.spectral)
-      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, true>), dim3(ncols), dim3(g_threads<CAP>()), 0, s,
+      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, true>), dim3(ncols),
+                         dim3(g_threads<CAP>()), 0, s,
                          T2, Np, M, pN, a.twN, static_cast<const double*>(a.eigM), a.st);
     else
-      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, false>), dim3(ncols), dim3(g_threads<CAP>()), 0, s,
+      hipLaunchKernelGGL((g_cols_kernel<CT, ST, CAP, false>), dim3(ncols),
+                         dim3(g_threads<CAP>()), 0, s,
                          T2, Np, M, pN, a.twN, static_cast<const double*>(a.eigM), a.st);
   });
   log_mark(L, IRLSU_LK_COLS, s);
@@ -754,14 +757,17 @@ int fastg_impl(const PrecondArgs& a, hipStream_t s) {
   with_cap(M / 2, [&](auto cap) {
     constexpr int CAP = decltype(cap)::value;
     if (a.spectral)
-      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 2>), dim3(nb), dim3(g_threads<CAP>()), 0, s,
+      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 2>), dim3(nb),
+                         dim3(g_threads<CAP>()), 0, s,
                          T1, Mp, static_cast<T*>(a.p_out), Mp, r, static_cast<const T*>(a.p_in),
                          static_cast<T*>(a.d), N, Np, pM, a.twM, a.st, f16, a.iter);
     else if (q)
-      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 1>), dim3(nb), dim3(g_threads<CAP>()), 0, s,
+      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 1>), dim3(nb),
+                         dim3(g_threads<CAP>()), 0, s,
                          T1, Mp, z, Mp, r, q, nullptr, N, Np, pM, a.twM, a.st, f16, 0);
     else
-      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 0>), dim3(nb), dim3(g_threads<CAP>()), 0, s,
+      hipLaunchKernelGGL((g_rows_inv_kernel<CT, ST, T, CAP, 0>), dim3(nb),
+                         dim3(g_threads<CAP>()), 0, s,
                          T1, Mp, z, Mp, r, q, nullptr, N, Np, pM, a.twM, a.st, f16, 0);
   });
   log_mark(L, IRLSU_LK_ROWS_DCT3, s);
@@ -784,9 +790,9 @@ int cg_update_g(const PrecondArgs& a, T* r, const T* q, int nparts_pq, int iter,
   const int nb = blocks_g(N, M / 2);
   with_cap(M / 2, [&](auto cap) {
     constexpr int CAP = decltype(cap)::value;
-    hipLaunchKernelGGL((g_rows_fwd_cg_kernel<CT, T, ST, CAP>), dim3(nb), dim3(g_threads<CAP>()), 0, s, r,
-                       q, Mp, static_cast<ST*>(a.T1), Mp, N, pM, a.twM, a.st, iter, f16,
-                       nparts_out);
+    hipLaunchKernelGGL((g_rows_fwd_cg_kernel<CT, T, ST, CAP>), dim3(nb),
+                       dim3(g_threads<CAP>()), 0, s, r, q, Mp, static_cast<ST*>(a.T1), Mp, N,
+                       pM, a.twM, a.st, iter, f16, nparts_out);
   });
   log_mark(a.log, IRLSU_LK_UPDATE_DCT2, s);
   return nb;
