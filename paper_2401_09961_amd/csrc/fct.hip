@@ -187,35 +187,37 @@ __device__ __forceinline__ int perm(int e) {
 // Forward post-processing of pair k (0 <= k <= h/2): 2 c_k and 2 c_{h-k}
 // from W_k and W_{h-k}.  The even/odd split's factor 1/2 is left to the
 // caller's own scale (a power of two, so every rounding is unchanged).
+// With E = W_k + conj W_{h-k} and O = -i (W_k - conj W_{h-k}), index h-k has
+// conj E and conj O, and e^{-2 pi i (h-k)/n} = -conj e^{-2 pi i k/n}: one
+// product P = e^{-2 pi i k/n} O gives both V_k = E + P and V_{h-k} =
+// conj(E - P).
 template <class CT, int H>
 __device__ __forceinline__ void post_pair(const Cx<CT>* buf, int base, int k, const Tw<CT>& tw,
                                           Cx<CT>& ck, Cx<CT>& cp) {
   const Cx<CT> wa = buf[pc(base + (k & (H - 1)))], wb = buf[pc(base + ((H - k) & (H - 1)))];
-  auto c_of = [&](int kk, Cx<CT> x, Cx<CT> y) {
-    const Cx<CT> E = cadd(x, conjg(y));
-    const Cx<CT> O = mul_mi(csub(x, conjg(y)));
-    return cmul(tw.tq[kk], cadd(E, cmul(tw.tn[kk], O)));
-  };
-  ck = c_of(k, wa, wb);
-  cp = c_of(H - k, wb, wa);
+  const Cx<CT> E = {wa.x + wb.x, wa.y - wb.y};
+  const Cx<CT> O = {wa.y + wb.y, wb.x - wa.x};
+  const Cx<CT> P = cmul(tw.tn[k], O);
+  ck = cmul(tw.tq[k], cadd(E, P));
+  cp = cmul(tw.tq[H - k], {E.x - P.x, P.y - E.y});
 }
 
 // Inverse pre-processing of pair k: from c_k = Xt_k - i Xt_{n-k} and
 // c_{h-k}, the FFT inputs 2 W_k, 2 W_{h-k} (conjugated for the forward FFT;
 // the factor 1/2 is left to the caller's output scale, as in post_pair).
+// With v = e^{+i pi k/(2n)} c at k and at h-k, E = v_k + conj v_{h-k} and
+// O = (v_k - conj v_{h-k}) e^{+2 pi i k/n}; index h-k has conj E and conj O
+// (the same identities as in post_pair), so slot k takes conj(E + i O) and
+// slot h-k takes E - i O.
 template <class CT, int H>
 __device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<CT>& tw, Cx<CT>* buf,
                                          int base) {
-  const Cx<CT> vk = cmulc(ck, tw.tq[k]);      // e^{+i pi k/(2n)} c_k
+  const Cx<CT> vk = cmulc(ck, tw.tq[k]);
   const Cx<CT> vp = cmulc(cp, tw.tq[H - k]);
-  const Cx<CT> Ek = cadd(vk, conjg(vp));
-  const Cx<CT> Ok = cmulc(csub(vk, conjg(vp)), tw.tn[k]);
-  buf[pc(base + (k & (H - 1)))] = conjg(cadd(Ek, mul_i(Ok)));
-  if (k != H - k && k > 0) {
-    const Cx<CT> Ep = cadd(vp, conjg(vk));
-    const Cx<CT> Op = cmulc(csub(vp, conjg(vk)), tw.tn[H - k]);
-    buf[pc(base + H - k)] = conjg(cadd(Ep, mul_i(Op)));
-  }
+  const Cx<CT> E = {vk.x + vp.x, vk.y - vp.y};
+  const Cx<CT> O = cmulc({vk.x - vp.x, vk.y + vp.y}, tw.tn[k]);
+  buf[pc(base + (k & (H - 1)))] = {E.x - O.y, -(E.y + O.x)};
+  if (k != H - k && k > 0) buf[pc(base + H - k)] = {E.x + O.y, E.y - O.x};
 }
 
 // ---- row staging ----------------------------------------------------------

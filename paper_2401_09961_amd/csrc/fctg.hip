@@ -272,13 +272,11 @@ template <class CT>
 __device__ __forceinline__ void g_post_pair(const Cx<CT>* row, int h, int k, const GTw<CT>& tw,
                                             Cx<CT>& ck, Cx<CT>& cp) {
   const Cx<CT> wa = row[k], wb = row[k == 0 ? 0 : h - k];
-  auto c_of = [&](int kk, Cx<CT> x, Cx<CT> y) {
-    const Cx<CT> E = cadd(x, conjg(y));
-    const Cx<CT> O = mul_mi(csub(x, conjg(y)));
-    return cmul(tw.tq[kk], cadd(E, cmul(tw.tn[kk], O)));
-  };
-  ck = c_of(k, wa, wb);
-  cp = c_of(h - k, wb, wa);
+  const Cx<CT> E = {wa.x + wb.x, wa.y - wb.y};
+  const Cx<CT> O = {wa.y + wb.y, wb.x - wa.x};
+  const Cx<CT> P = cmul(tw.tn[k], O);
+  ck = cmul(tw.tq[k], cadd(E, P));
+  cp = cmul(tw.tq[h - k], {E.x - P.x, P.y - E.y});
 }
 
 // Inverse pre-processing of pair k, as pre_pair in fct.hip: the FFT inputs
@@ -288,14 +286,10 @@ __device__ __forceinline__ void g_pre_pair(Cx<CT> ck, Cx<CT> cp, int h, int k, c
                                            Cx<CT>* row) {
   const Cx<CT> vk = cmulc(ck, tw.tq[k]);
   const Cx<CT> vp = cmulc(cp, tw.tq[h - k]);
-  const Cx<CT> Ek = cadd(vk, conjg(vp));
-  const Cx<CT> Ok = cmulc(csub(vk, conjg(vp)), tw.tn[k]);
-  row[k] = conjg(cadd(Ek, mul_i(Ok)));
-  if (k != h - k && k > 0) {
-    const Cx<CT> Ep = cadd(vp, conjg(vk));
-    const Cx<CT> Op = cmulc(csub(vp, conjg(vk)), tw.tn[h - k]);
-    row[h - k] = conjg(cadd(Ep, mul_i(Op)));
-  }
+  const Cx<CT> E = {vk.x + vp.x, vk.y - vp.y};
+  const Cx<CT> O = cmulc({vk.x - vp.x, vk.y + vp.y}, tw.tn[k]);
+  row[k] = {E.x - O.y, -(E.y + O.x)};
+  if (k != h - k && k > 0) row[h - k] = {E.x + O.y, E.y - O.x};
 }
 
 // Streams the block's rows (n elements each, 16-byte chunks) through f(row,
