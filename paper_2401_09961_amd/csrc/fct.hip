@@ -54,36 +54,39 @@ __device__ __forceinline__ int pr(int e) { return 2 * pc(e >> 1) + (e & 1); }
 // value is rounded once from FP64, and a load replaces the products that
 // would form it.
 //
-// LOAD_ALL: every power from the table (fewest instructions).  Otherwise w,
-// w^2, w^4, w^8 from the table and the others as products of two of them
-// (at most three roundings; fewer loads, whose waits also wait for the
-// pass's own earlier loads) -- measured faster in all three passes at
-// 8192^2, so the passes use it.
-template <class CT, int R, int NS, bool LOAD_ALL>
+// w, w^2, w^4, w^8 come from the table and the others as products of two of
+// them (at most three roundings).  Loading every power from the global table
+// instead was measured slower in all three passes at 8192^2 (more loads per
+// stage, whose waits also wait for the pass's own earlier loads).  The
+// column pass, bound by instruction issue, reads every power of its span-16
+// stage from a block-local copy of that stage's table in LDS (LT16 below).
+template <class CT, int R, int NS>
 __device__ __forceinline__ void stage_twiddles(const Cx<CT>* __restrict__ tw, int k,
                                                Cx<CT> (&w)[R]) {
   const Cx<CT>* t = tw + (NS - 1) + k;
-  if constexpr (LOAD_ALL) {
-#pragma unroll
-    for (int r = 1; r < R; ++r) w[r] = t[(r - 1) * NS];
-  } else {
-    w[1] = t[0];
-    if constexpr (R > 2) {
-      w[2] = t[NS];
-      w[3] = cmul(w[1], w[2]);
-    }
-    if constexpr (R > 4) {
-      w[4] = t[3 * NS];
-      w[5] = cmul(w[4], w[1]);
-      w[6] = cmul(w[4], w[2]);
-      w[7] = cmul(w[4], w[3]);
-    }
-    if constexpr (R > 8) {
-      w[8] = t[7 * NS];
-#pragma unroll
-      for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
-    }
+  w[1] = t[0];
+  if constexpr (R > 2) {
+    w[2] = t[NS];
+    w[3] = cmul(w[1], w[2]);
   }
+  if constexpr (R > 4) {
+    w[4] = t[3 * NS];
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+  }
+  if constexpr (R > 8) {
+    w[8] = t[7 * NS];
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+  }
+}
+
+// Entries of the span-16 stage's table (radix min(16, H / 16)); 0 when the
+// transform has no such stage.
+template <int H>
+constexpr int lt16_size() {
+  return H >= 32 ? ((H / 16 >= 16 ? 16 : H / 16) - 1) * 16 : 0;
 }
 
 // Stage with span NS and radix R: butterfly j of a row reads points
@@ -93,8 +96,11 @@ __device__ __forceinline__ void stage_twiddles(const Cx<CT>* __restrict__ tw, in
 // pad per 16 points, the R points of a butterfly sit at constant offsets
 // from the first one (H/R and NS multiples of 16, or NS = 1 with R = 16
 // and the first point on a multiple of 16), so one address serves all R.
-template <class CT, int H, int ROWS, int R, int NS, bool LOAD_ALL>
-__device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict__ tw, int tid) {
+// LT16: the span-16 stage reads its twiddles from lt16, the LDS copy of
+// its table (entry (r - 1) 16 + k).
+template <class CT, int H, int ROWS, int R, int NS, bool LT16>
+__device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict__ tw,
+                                          const Cx<CT>* lt16, int tid) {
   constexpr int BPR = H / R;
   constexpr int NB = ROWS * BPR / kThreads;
   static_assert(NB >= 1 && NB * kThreads == ROWS * BPR, "butterflies per thread");
@@ -119,7 +125,12 @@ __device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict_
     }
     if constexpr (NS > 1) {
       Cx<CT> w[R];
-      stage_twiddles<CT, R, NS, LOAD_ALL>(tw, k, w);
+      if constexpr (LT16 && NS == 16) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[r] = lt16[(r - 1) * 16 + k];
+      } else {
+        stage_twiddles<CT, R, NS>(tw, k, w);
+      }
 #pragma unroll
       for (int r = 1; r < R; ++r) a[b][r] = cmul(a[b][r], w[r]);
     }
@@ -144,13 +155,14 @@ __device__ __forceinline__ void fft_stage(Cx<CT>* buf, const Cx<CT>* __restrict_
   __syncthreads();
 }
 
-template <class CT, int H, int ROWS, bool LOAD_ALL, int NS = 1>
-__device__ __forceinline__ void fft_rows(Cx<CT>* buf, const Cx<CT>* __restrict__ tw, int tid) {
+template <class CT, int H, int ROWS, bool LT16, int NS = 1>
+__device__ __forceinline__ void fft_rows(Cx<CT>* buf, const Cx<CT>* __restrict__ tw, int tid,
+                                         const Cx<CT>* lt16 = nullptr) {
   if constexpr (NS < H) {
     constexpr int REM = H / NS;
     constexpr int R = REM >= 16 ? 16 : REM;
-    fft_stage<CT, H, ROWS, R, NS, LOAD_ALL>(buf, tw, tid);
-    fft_rows<CT, H, ROWS, LOAD_ALL, NS * R>(buf, tw, tid);
+    fft_stage<CT, H, ROWS, R, NS, LT16>(buf, tw, lt16, tid);
+    fft_rows<CT, H, ROWS, LT16, NS * R>(buf, tw, tid, lt16);
   }
 }
 
@@ -164,18 +176,23 @@ constexpr int rows_per_block() {
 // Tables of one side n = 2h (CT): complex [0, h - 1) the FFT stages'
 // twiddles (stage_twiddles), entry h - 1 unused; [h, 2h] e^{-2 pi i k/n},
 // k = 0..h; [2h+1, 3h+1] e^{-i pi k/(2n)}, k = 0..h; then n reals, the
-// eigenvalues 4 sin^2(pi k / 2n) of the side's Neumann second difference.
+// eigenvalues 4 sin^2(pi k / 2n) of the side's Neumann second difference;
+// then the h/2 + 1 records of the column pass's pair steps (PairTw), which
+// start 16-byte aligned (8h + 4 reals in).
 template <class CT>
 struct Tw {
   const Cx<CT>* fft;
   const Cx<CT>* tn;
   const Cx<CT>* tq;
   const CT* eig;
+  const PairTw<CT>* pair;
 };
 template <class CT, int H>
 __device__ __forceinline__ Tw<CT> tw_of(const void* p) {
   const Cx<CT>* t = static_cast<const Cx<CT>*>(p);
-  return {t, t + H, t + 2 * H + 1, reinterpret_cast<const CT*>(t + 3 * H + 2)};
+  return {t, t + H, t + 2 * H + 1, reinterpret_cast<const CT*>(t + 3 * H + 2),
+          reinterpret_cast<const PairTw<CT>*>(static_cast<const CT*>(p) +
+                                               pair_table_offset(H))};
 }
 
 // position of row element e in the even-up / odd-down sequence v
@@ -184,40 +201,24 @@ __device__ __forceinline__ int perm(int e) {
   return (e & 1) ? N - 1 - (e >> 1) : (e >> 1);
 }
 
-// Forward post-processing of pair k (0 <= k <= h/2): 2 c_k and 2 c_{h-k}
-// from W_k and W_{h-k}.  The even/odd split's factor 1/2 is left to the
-// caller's own scale (a power of two, so every rounding is unchanged).
-// With E = W_k + conj W_{h-k} and O = -i (W_k - conj W_{h-k}), index h-k has
-// conj E and conj O, and e^{-2 pi i (h-k)/n} = -conj e^{-2 pi i k/n}: one
-// product P = e^{-2 pi i k/n} O gives both V_k = E + P and V_{h-k} =
-// conj(E - P).
+// Pair steps of one row held in LDS (post_core and pre_core), the twiddles
+// from the side's tables.  post_pair returns twice the coefficients: the
+// even/odd split's factor 1/2 is left to the caller's own scale (a power of
+// two, so every rounding is unchanged); so does pre_pair.
 template <class CT, int H>
 __device__ __forceinline__ void post_pair(const Cx<CT>* buf, int base, int k, const Tw<CT>& tw,
                                           Cx<CT>& ck, Cx<CT>& cp) {
-  const Cx<CT> wa = buf[pc(base + (k & (H - 1)))], wb = buf[pc(base + ((H - k) & (H - 1)))];
-  const Cx<CT> E = {wa.x + wb.x, wa.y - wb.y};
-  const Cx<CT> O = {wa.y + wb.y, wb.x - wa.x};
-  const Cx<CT> P = cmul(tw.tn[k], O);
-  ck = cmul(tw.tq[k], cadd(E, P));
-  cp = cmul(tw.tq[H - k], {E.x - P.x, P.y - E.y});
+  post_core(buf[pc(base + (k & (H - 1)))], buf[pc(base + ((H - k) & (H - 1)))], tw.tq[k],
+            tw.tq[H - k], tw.tn[k], ck, cp);
 }
 
-// Inverse pre-processing of pair k: from c_k = Xt_k - i Xt_{n-k} and
-// c_{h-k}, the FFT inputs 2 W_k, 2 W_{h-k} (conjugated for the forward FFT;
-// the factor 1/2 is left to the caller's output scale, as in post_pair).
-// With v = e^{+i pi k/(2n)} c at k and at h-k, E = v_k + conj v_{h-k} and
-// O = (v_k - conj v_{h-k}) e^{+2 pi i k/n}; index h-k has conj E and conj O
-// (the same identities as in post_pair), so slot k takes conj(E + i O) and
-// slot h-k takes E - i O.
 template <class CT, int H>
 __device__ __forceinline__ void pre_pair(Cx<CT> ck, Cx<CT> cp, int k, const Tw<CT>& tw, Cx<CT>* buf,
                                          int base) {
-  const Cx<CT> vk = cmulc(ck, tw.tq[k]);
-  const Cx<CT> vp = cmulc(cp, tw.tq[H - k]);
-  const Cx<CT> E = {vk.x + vp.x, vk.y - vp.y};
-  const Cx<CT> O = cmulc({vk.x - vp.x, vk.y + vp.y}, tw.tn[k]);
-  buf[pc(base + (k & (H - 1)))] = {E.x - O.y, -(E.y + O.x)};
-  if (k != H - k && k > 0) buf[pc(base + H - k)] = {E.x + O.y, E.y - O.x};
+  Cx<CT> sk, sp;
+  pre_core(ck, cp, tw.tq[k], tw.tq[H - k], tw.tn[k], sk, sp);
+  buf[pc(base + (k & (H - 1)))] = sk;
+  if (k != H - k && k > 0) buf[pc(base + H - k)] = sp;
 }
 
 // ---- row staging ----------------------------------------------------------
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_kernel(const TI* __rest
   for (int qq = 0; qq < PP; ++qq) {
     const int p = tid + qq * kThreads;
     if (p < ROWS * NP) {
-      const int row = p / NP, k = p % NP;
+      const int row = ROWS == 1 ? 0 : p / NP, k = ROWS == 1 ? p : p % NP;
       Cx<CT> ck, cp;
       post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
       TO* o = out + (row0 + row) * ld;
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_fwd_cg_kernel(
   for (int qq = 0; qq < PP; ++qq) {
     const int pp = tid + qq * kThreads;
     if (pp < ROWS * NP) {
-      const int row = pp / NP, k = pp % NP;
+      const int row = ROWS == 1 ? 0 : pp / NP, k = ROWS == 1 ? pp : pp % NP;
       Cx<CT> ck, cp;
       post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
       TO* o = out + (row0 + row) * ld;
@@ -487,9 +488,16 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
   constexpr int N = 2 * H, ROWS = rows_per_block<H>();
   constexpr int NP = H / 2 + 1;
   constexpr int PP = (ROWS * NP + kThreads - 1) / kThreads;
+  constexpr int NT16 = lt16_size<H>();
+  constexpr bool LT16 = NT16 > 0;
   __shared__ Cx<CT> buf[padded<ROWS * H>()];
+  __shared__ Cx<CT> lt16[LT16 ? NT16 : 1];
   const Tw<CT> tw = tw_of<CT, H>(twp);
   const int tid = threadIdx.x;
+  if constexpr (LT16) {
+    static_assert(NT16 <= kThreads, "one table entry per thread");
+    if (tid < NT16) lt16[tid] = tw.fft[15 + tid];
+  }
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   CT* v = reinterpret_cast<CT*>(buf);
   // RHO: this thread's share of sum rhat^2 / (lambda + mu), in units of
@@ -501,7 +509,8 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     put_rows<CT, ST, H>(ch, v, (CT)1, tid);
   }
   __syncthreads();
-  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
+  fft_rows<CT, H, ROWS, LT16>(buf, tw.fft, tid, lt16);
+  const CT mu0 = (CT)eig_l[row0];
   // forward post-processing, division and inverse pre-processing of pair
   // (k, h-k), in place: the pair's two slots are read and written by the
   // same thread only.  With d = 1 / (lambda_k + mu_l), the scaled
@@ -512,21 +521,28 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
   for (int qq = 0; qq < PP; ++qq) {
     const int p = tid + qq * kThreads;
     if (p < ROWS * NP) {
-      const int row = p / NP, k = p % NP;
+      const int row = ROWS == 1 ? 0 : p / NP, k = ROWS == 1 ? p : p % NP;
       const int64_t l = row0 + row;
-      const CT mu = (CT)eig_l[l];
-      auto d = [&](int kk) -> CT {
-        return (l == 0 && kk == 0) ? (CT)0 : recip(tw.eig[kk] + mu);
-      };
+      const CT mu = ROWS == 1 ? mu0 : (CT)eig_l[l];
+      // one aligned record holds the pair's twiddles and eigenvalues
+      const PairTw<CT> pt = tw.pair[k];
+      Cx<CT>* slot_k = buf + pc(row * H + (k & (H - 1)));
+      Cx<CT>* slot_p = buf + pc(row * H + ((H - k) & (H - 1)));
       Cx<CT> ck, cp;
-      post_pair<CT, H>(buf, row * H, k, tw, ck, cp);
+      post_core(*slot_k, *slot_p, pt.q, pt.qp, pt.n, ck, cp);
+      // d = 1 / (lambda + mu) at k, n-k, h-k, h+k (mode (0, 0) set to zero)
+      const CT dk = (l == 0 && k == 0) ? (CT)0 : recip(pt.e[0] + mu);
+      const CT dnk = k > 0 ? recip(pt.e[1] + mu) : (CT)0;
+      const CT dp = recip(pt.e[2] + mu), dnp = recip(pt.e[3] + mu);
       // X~ at k, n-k, h-k, h+k; c_k (inverse) = X~_k - i X~_{n-k}
-      const CT dk = d(k), dnk = k > 0 ? d(N - k) : (CT)0, dp = d(H - k), dnp = d(H + k);
       const CT xk = ck.x * dk;
       const CT xnk = k > 0 ? -ck.y * dnk : (CT)0;
       const CT xp = cp.x * dp;
       const CT xnp = -cp.y * dnp;   // k = 0: index h, equal to xp
-      pre_pair<CT, H>({xk, -xnk}, {xp, -xnp}, k, tw, buf, row * H);
+      Cx<CT> sk, sp;
+      pre_core<CT>({xk, -xnk}, {xp, -xnp}, pt.q, pt.qp, pt.n, sk, sp);
+      *slot_k = sk;
+      if (k != H - k && k > 0) *slot_p = sp;
       if constexpr (RHO) {
         // squared orthonormal coefficients (s_k Re c_k etc.) over the
         // eigenvalue sum; each index of the column once (k = 0 and k = h/2
@@ -540,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void fct_cols_kernel(ST* __restrict__ io,
     }
   }
   __syncthreads();
-  fft_rows<CT, H, ROWS, false>(buf, tw.fft, tid);
+  fft_rows<CT, H, ROWS, LT16>(buf, tw.fft, tid, lt16);
   const CT inv_h = (CT)(0.25 / H);
   using V = typename Vec16<ST>::type;
   constexpr int W = Vec16<ST>::W;
@@ -681,7 +697,7 @@ __global__ __launch_bounds__(kThreads) void fct_rows_inv_kernel(
   for (int qq = 0; qq < PP; ++qq) {
     const int p = tid + qq * kThreads;
     if (p < ROWS * NP) {
-      const int row = p / NP, k = p % NP;
+      const int row = ROWS == 1 ? 0 : p / NP, k = ROWS == 1 ? p : p % NP;
       const Cx<CT> A = buf[pc(row * H + k)];
       const Cx<CT> B = buf[pc(row * H + ((H - k) & (H - 1)))];
       const CT xk = A.x * (k == 0 ? is0 : is1);
@@ -923,10 +939,15 @@ __global__ __launch_bounds__(kThreads) void fct_tables_kernel(int64_t n, Cx<CT>*
     eig[j] = 4.0 * sv * sv;
     reinterpret_cast<CT*>(tw + 3 * h + 2)[j] = (CT)(4.0 * sv * sv);
   }
+  if (j <= h / 2)
+    pair_tw_fill(reinterpret_cast<PairTw<CT>*>(reinterpret_cast<CT*>(tw) + pair_table_offset(h)) + j,
+                 j, h);
 }
 
 size_t fct_table_bytes(int64_t n, int elem) {
-  return (size_t)(3 * (n / 2) + 2) * 2 * (size_t)elem + (size_t)n * (size_t)elem;
+  const int64_t h = n / 2;
+  return (size_t)pair_table_offset(h) * (size_t)elem +
+         (size_t)(h / 2 + 1) * (elem == 8 ? sizeof(PairTw<double>) : sizeof(PairTw<float>));
 }
 
 void launch_fct_tables(int elem, int64_t n, void* tw, double* eig, hipStream_t s, bool general) {

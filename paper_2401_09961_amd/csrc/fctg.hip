@@ -121,11 +121,13 @@ struct GTw {
   const Cx<CT>* tn;     // e^{-2 pi i k / n}, k = 0..h
   const Cx<CT>* tq;     // e^{-i pi k / (2n)}, k = 0..h
   const CT* eig;        // 4 sin^2(pi k / 2n), k < n
+  const PairTw<CT>* pair;  // the column pass's pair records, k = 0..h/2
 };
 template <class CT>
 __device__ __forceinline__ GTw<CT> gtw_of(const void* p, int h) {
   const Cx<CT>* t = static_cast<const Cx<CT>*>(p);
-  return {t, t + h, t + 2 * h + 1, reinterpret_cast<const CT*>(t + 3 * h + 2)};
+  return {t, t + h, t + 2 * h + 1, reinterpret_cast<const CT*>(t + 3 * h + 2),
+          reinterpret_cast<const PairTw<CT>*>(static_cast<const CT*>(p) + pair_table_offset(h))};
 }
 
 template <class CT, int R>
@@ -266,30 +268,21 @@ __device__ __forceinline__ void g_fft(Cx<CT>* buf, const GPlan& pl, int rows,
 // position of row element e in the even-up / odd-down sequence (length n)
 __device__ __forceinline__ int gperm(int e, int n) { return (e & 1) ? n - 1 - (e >> 1) : (e >> 1); }
 
-// Forward post-processing of pair k (0 <= k <= h/2), as post_pair in fct.hip:
-// twice c_k and c_{h-k} from W_k and W_{h-k}.
+// Pair steps of one row held in LDS (post_core and pre_core), the twiddles
+// from the side's tables, as post_pair and pre_pair in fct.hip.
 template <class CT>
 __device__ __forceinline__ void g_post_pair(const Cx<CT>* row, int h, int k, const GTw<CT>& tw,
                                             Cx<CT>& ck, Cx<CT>& cp) {
-  const Cx<CT> wa = row[k], wb = row[k == 0 ? 0 : h - k];
-  const Cx<CT> E = {wa.x + wb.x, wa.y - wb.y};
-  const Cx<CT> O = {wa.y + wb.y, wb.x - wa.x};
-  const Cx<CT> P = cmul(tw.tn[k], O);
-  ck = cmul(tw.tq[k], cadd(E, P));
-  cp = cmul(tw.tq[h - k], {E.x - P.x, P.y - E.y});
+  post_core(row[k], row[k == 0 ? 0 : h - k], tw.tq[k], tw.tq[h - k], tw.tn[k], ck, cp);
 }
 
-// Inverse pre-processing of pair k, as pre_pair in fct.hip: the FFT inputs
-// (conjugated) twice W_k and W_{h-k} from c_k and c_{h-k}.
 template <class CT>
 __device__ __forceinline__ void g_pre_pair(Cx<CT> ck, Cx<CT> cp, int h, int k, const GTw<CT>& tw,
                                            Cx<CT>* row) {
-  const Cx<CT> vk = cmulc(ck, tw.tq[k]);
-  const Cx<CT> vp = cmulc(cp, tw.tq[h - k]);
-  const Cx<CT> E = {vk.x + vp.x, vk.y - vp.y};
-  const Cx<CT> O = cmulc({vk.x - vp.x, vk.y + vp.y}, tw.tn[k]);
-  row[k] = {E.x - O.y, -(E.y + O.x)};
-  if (k != h - k && k > 0) row[h - k] = {E.x + O.y, E.y - O.x};
+  Cx<CT> sk, sp;
+  pre_core(ck, cp, tw.tq[k], tw.tq[h - k], tw.tn[k], sk, sp);
+  row[k] = sk;
+  if (k != h - k && k > 0) row[h - k] = sp;
 }
 
 // Streams the block's rows (n elements each, 16-byte chunks) through f(row,
@@ -512,15 +505,22 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
     const int row = udiv(p, np, pl.mag_np), k = p - row * np;
     const int64_t l = row0 + row;
     const CT mu = (CT)eig_l[l];
-    auto d = [&](int kk) -> CT { return (l == 0 && kk == 0) ? (CT)0 : recip(tw.eig[kk] + mu); };
+    const PairTw<CT> pt = tw.pair[k];
+    Cx<CT>* slot_k = buf + row * h + k;
+    Cx<CT>* slot_p = buf + row * h + (k == 0 ? 0 : h - k);
     Cx<CT> ck, cp;
-    g_post_pair<CT>(buf + row * h, h, k, tw, ck, cp);
-    const CT dk = d(k), dnk = k > 0 ? d(n - k) : (CT)0, dp = d(h - k), dnp = d(h + k);
+    post_core(*slot_k, *slot_p, pt.q, pt.qp, pt.n, ck, cp);
+    const CT dk = (l == 0 && k == 0) ? (CT)0 : recip(pt.e[0] + mu);
+    const CT dnk = k > 0 ? recip(pt.e[1] + mu) : (CT)0;
+    const CT dp = recip(pt.e[2] + mu), dnp = recip(pt.e[3] + mu);
     const CT xk = ck.x * dk;
     const CT xnk = k > 0 ? -ck.y * dnk : (CT)0;
     const CT xp = cp.x * dp;
     const CT xnp = -cp.y * dnp;
-    g_pre_pair<CT>({xk, -xnk}, {xp, -xnp}, h, k, tw, buf + row * h);
+    Cx<CT> sk, sp;
+    pre_core<CT>({xk, -xnk}, {xp, -xnp}, pt.q, pt.qp, pt.n, sk, sp);
+    *slot_k = sk;
+    if (k != h - k && k > 0) *slot_p = sp;
     if constexpr (RHO) {
       rho += (k == 0 ? (CT)0.5 : (CT)1) * ck.x * ck.x * dk;
       if (k > 0) rho += ck.y * ck.y * dnk;
@@ -664,8 +664,8 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
 // ---- tables -------------------------------------------------------------------
 // Layout of fct_tables_kernel (fct.hip) with the h roots of unity in place of
 // the power-of-two stage twiddles: [0, h) e^{-2 pi i m/h}; [h, 2h]
-// e^{-2 pi i k/n}; [2h+1, 3h+1] e^{-i pi k/(2n)}; n eigenvalues (CT), and
-// the FP64 eigenvalues in eig.
+// e^{-2 pi i k/n}; [2h+1, 3h+1] e^{-i pi k/(2n)}; n eigenvalues (CT); the
+// h/2 + 1 pair records (PairTw); and the FP64 eigenvalues in eig.
 template <class CT>
 __global__ __launch_bounds__(kThreads) void g_tables_kernel(int64_t n, Cx<CT>* tw, double* eig) {
   const int64_t h = n / 2;
@@ -686,6 +686,9 @@ __global__ __launch_bounds__(kThreads) void g_tables_kernel(int64_t n, Cx<CT>* t
     eig[j] = 4.0 * sv * sv;
     reinterpret_cast<CT*>(tw + 3 * h + 2)[j] = (CT)(4.0 * sv * sv);
   }
+  if (j <= h / 2)
+    pair_tw_fill(reinterpret_cast<PairTw<CT>*>(reinterpret_cast<CT*>(tw) + pair_table_offset(h)) + j,
+                 j, h);
 }
 
 template <class F>

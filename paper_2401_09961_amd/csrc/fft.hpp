@@ -2,6 +2,7 @@
 // accesses shared by the fast-form passes (power-of-two sides in fct.hip,
 // sides with factors 2, 3 and 5 in fctg.hip).
 #pragma once
+#include <cstdint>
 #include <type_traits>
 
 #include <hip/hip_runtime.h>
@@ -201,6 +202,73 @@ __device__ __forceinline__ void dft5(Cx<CT> (&a)[5]) {
   a[4] = csub(m1, t1);
   a[2] = cadd(m2, t2);
   a[3] = csub(m2, t2);
+}
+
+// Everything the column pass's pair step k (0 <= k <= h/2) of a side of
+// length n = 2h reads, in one 16-byte aligned record: e^{-i pi k/(2n)},
+// e^{-i pi (h-k)/(2n)}, e^{-2 pi i k/n} and the eigenvalues 4 sin^2(pi j/2n)
+// at j = k, n-k (0 for k = 0), h-k, h+k; each value rounded once from FP64.
+template <class CT>
+struct alignas(16) PairTw {
+  Cx<CT> q, qp, n;
+  CT e[6];
+};
+
+// Start of the pair records in a side's table, in CT elements: after 3h + 2
+// complex entries and n = 2h reals (8h + 4 CT, so 16-byte aligned).
+__host__ __device__ inline int64_t pair_table_offset(int64_t h) { return 2 * (3 * h + 2) + 2 * h; }
+
+template <class CT>
+__device__ __forceinline__ void pair_tw_fill(PairTw<CT>* out, int64_t k, int64_t h) {
+  const double n = 2.0 * (double)h;
+  double s, c;
+  PairTw<CT> t;
+  sincospi(0.5 * (double)k / n, &s, &c);
+  t.q = {(CT)c, (CT)(-s)};
+  sincospi(0.5 * (double)(h - k) / n, &s, &c);
+  t.qp = {(CT)c, (CT)(-s)};
+  sincospi(2.0 * (double)k / n, &s, &c);
+  t.n = {(CT)c, (CT)(-s)};
+  const int64_t j[4] = {k, 2 * h - k, h - k, h + k};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double sv = sinpi(0.5 * (double)j[i] / n);
+    t.e[i] = (i == 1 && k == 0) ? (CT)0 : (CT)(4.0 * sv * sv);
+  }
+  t.e[4] = t.e[5] = (CT)0;
+  *out = t;
+}
+
+// ---- DCT pair steps (one length-n DCT through an FFT of h = n/2 points) --
+// Forward post-processing of pair k (0 <= k <= h/2): twice c_k and c_{h-k}
+// from W_k and W_{h-k}, with tq = e^{-i pi k/(2n)}, tqp = e^{-i pi (h-k)/(2n)}
+// and tn = e^{-2 pi i k/n}.  With E = W_k + conj W_{h-k} and O = -i (W_k -
+// conj W_{h-k}), index h-k has conj E and conj O, and e^{-2 pi i (h-k)/n} =
+// -conj tn: one product P = tn O gives V_k = E + P and V_{h-k} = conj(E - P).
+template <class CT>
+__device__ __forceinline__ void post_core(Cx<CT> wa, Cx<CT> wb, Cx<CT> tq, Cx<CT> tqp, Cx<CT> tn,
+                                          Cx<CT>& ck, Cx<CT>& cp) {
+  const Cx<CT> E = {wa.x + wb.x, wa.y - wb.y};
+  const Cx<CT> O = {wa.y + wb.y, wb.x - wa.x};
+  const Cx<CT> P = cmul(tn, O);
+  ck = cmul(tq, cadd(E, P));
+  cp = cmul(tqp, {E.x - P.x, P.y - E.y});
+}
+
+// Inverse pre-processing of pair k: from c_k = Xt_k - i Xt_{n-k} and
+// c_{h-k}, the (conjugated) FFT inputs twice W_k (sk) and W_{h-k} (sp).
+// With v = conj(tq) c at k and at h-k, E = v_k + conj v_{h-k} and O = (v_k -
+// conj v_{h-k}) conj tn; index h-k has conj E and conj O (the identities of
+// post_core), so sk = conj(E + i O) and sp = E - i O.
+template <class CT>
+__device__ __forceinline__ void pre_core(Cx<CT> ck, Cx<CT> cp, Cx<CT> tq, Cx<CT> tqp, Cx<CT> tn,
+                                         Cx<CT>& sk, Cx<CT>& sp) {
+  const Cx<CT> vk = cmulc(ck, tq);
+  const Cx<CT> vp = cmulc(cp, tqp);
+  const Cx<CT> E = {vk.x + vp.x, vk.y - vp.y};
+  const Cx<CT> O = cmulc({vk.x - vp.x, vk.y + vp.y}, tn);
+  sk = {E.x - O.y, -E.y - O.x};
+  sp = {E.x + O.y, E.y - O.x};
 }
 
 template <class T>
