@@ -120,13 +120,12 @@ struct GTw {
   const Cx<CT>* root;   // e^{-2 pi i m / h}, m < h
   const Cx<CT>* tn;     // e^{-2 pi i k / n}, k = 0..h
   const Cx<CT>* tq;     // e^{-i pi k / (2n)}, k = 0..h
-  const CT* eig;        // 4 sin^2(pi k / 2n), k < n
   const PairTw<CT>* pair;  // the column pass's pair records, k = 0..h/2
 };
 template <class CT>
 __device__ __forceinline__ GTw<CT> gtw_of(const void* p, int h) {
   const Cx<CT>* t = static_cast<const Cx<CT>*>(p);
-  return {t, t + h, t + 2 * h + 1, reinterpret_cast<const CT*>(t + 3 * h + 2),
+  return {t, t + h, t + 2 * h + 1,
           reinterpret_cast<const PairTw<CT>*>(static_cast<const CT*>(p) + pair_table_offset(h))};
 }
 
@@ -643,7 +642,10 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
         acc[2] += zd;
       }
     }
-    st_nt<V>(z + o, out);
+    if constexpr (OUT == 2)
+      *reinterpret_cast<V*>(z + o) = out;   // read by the operator next (as in fct.hip)
+    else
+      st_nt<V>(z + o, out);
   }
   // zeros in the output's padding, as the product forms leave it: columns
   // [n, ld) of the block's rows, and the rows [nrows, nrows_pad) spread over
@@ -664,8 +666,9 @@ __global__ __launch_bounds__(g_threads<CAP>(), (g_min_blocks<CT, CAP>())) void g
 // ---- tables -------------------------------------------------------------------
 // Layout of fct_tables_kernel (fct.hip) with the h roots of unity in place of
 // the power-of-two stage twiddles: [0, h) e^{-2 pi i m/h}; [h, 2h]
-// e^{-2 pi i k/n}; [2h+1, 3h+1] e^{-i pi k/(2n)}; n eigenvalues (CT); the
-// h/2 + 1 pair records (PairTw); and the FP64 eigenvalues in eig.
+// e^{-2 pi i k/n}; [2h+1, 3h+1] e^{-i pi k/(2n)}; the h/2 + 1 pair records
+// (PairTw, eigenvalues unscaled: the output pass applies 1/(4h)); and the
+// FP64 eigenvalues in eig.
 template <class CT>
 __global__ __launch_bounds__(kThreads) void g_tables_kernel(int64_t n, Cx<CT>* tw, double* eig) {
   const int64_t h = n / 2;
@@ -684,11 +687,10 @@ __global__ __launch_bounds__(kThreads) void g_tables_kernel(int64_t n, Cx<CT>* t
   if (j < n) {
     const double sv = sinpi(0.5 * (double)j / (double)n);
     eig[j] = 4.0 * sv * sv;
-    reinterpret_cast<CT*>(tw + 3 * h + 2)[j] = (CT)(4.0 * sv * sv);
   }
   if (j <= h / 2)
     pair_tw_fill(reinterpret_cast<PairTw<CT>*>(reinterpret_cast<CT*>(tw) + pair_table_offset(h)) + j,
-                 j, h);
+                 j, h, 1.0);
 }
 
 template <class F>

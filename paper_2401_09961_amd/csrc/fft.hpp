@@ -207,7 +207,8 @@ __device__ __forceinline__ void dft5(Cx<CT> (&a)[5]) {
 // Everything the column pass's pair step k (0 <= k <= h/2) of a side of
 // length n = 2h reads, in one 16-byte aligned record: e^{-i pi k/(2n)},
 // e^{-i pi (h-k)/(2n)}, e^{-2 pi i k/n} and the eigenvalues 4 sin^2(pi j/2n)
-// at j = k, n-k (0 for k = 0), h-k, h+k; each value rounded once from FP64.
+// at j = k, n-k (0 for k = 0), h-k, h+k times escale; each value rounded
+// once from FP64.
 template <class CT>
 struct alignas(16) PairTw {
   Cx<CT> q, qp, n;
@@ -215,11 +216,12 @@ struct alignas(16) PairTw {
 };
 
 // Start of the pair records in a side's table, in CT elements: after 3h + 2
-// complex entries and n = 2h reals (8h + 4 CT, so 16-byte aligned).
-__host__ __device__ inline int64_t pair_table_offset(int64_t h) { return 2 * (3 * h + 2) + 2 * h; }
+// complex entries (6h + 4 CT, so 16-byte aligned).
+__host__ __device__ inline int64_t pair_table_offset(int64_t h) { return 2 * (3 * h + 2); }
 
 template <class CT>
-__device__ __forceinline__ void pair_tw_fill(PairTw<CT>* out, int64_t k, int64_t h) {
+__device__ __forceinline__ void pair_tw_fill(PairTw<CT>* out, int64_t k, int64_t h,
+                                             double escale) {
   const double n = 2.0 * (double)h;
   double s, c;
   PairTw<CT> t;
@@ -233,7 +235,7 @@ __device__ __forceinline__ void pair_tw_fill(PairTw<CT>* out, int64_t k, int64_t
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const double sv = sinpi(0.5 * (double)j[i] / n);
-    t.e[i] = (i == 1 && k == 0) ? (CT)0 : (CT)(4.0 * sv * sv);
+    t.e[i] = (i == 1 && k == 0) ? (CT)0 : (CT)(4.0 * sv * sv * escale);
   }
   t.e[4] = t.e[5] = (CT)0;
   *out = t;

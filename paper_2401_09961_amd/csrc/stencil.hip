@@ -11,9 +11,13 @@
 // cross-lane shuffles; only the wave's two edge lanes read their outside
 // neighbour from memory, so no wave waits for another (no barrier in the
 // row loop).  The weights and halo of row i+1 and the p row i+2 are loaded
-// before row i is computed, up to the last row the band needs.  The arrays streamed once per pass are read and
-// written with non-temporal hints: on gfx950 that lifts a three-read /
-// one-write stream from about 5.2 to 5.7 TB/s at 8192^2.  HBM traffic per
+// before row i is computed, up to the last row the band needs.  The weights
+// and q are streamed with non-temporal hints (on gfx950 that lifts a
+// three-read / one-write stream from about 5.2 to 5.7 TB/s at 8192^2); p,
+// which the preconditioner's last pass wrote just before with plain stores,
+// is read with plain loads so that the last-level cache serves part of it
+// (6% less time per PCG iteration at 8192^2, with the plain stores of the
+// transposes and of p).  HBM traffic per
 // pixel: p, Omega^v, Omega^h in, q out = 16 bytes (FP32; fused form z,
 // p_old in and p out as well), plus the two halo rows per band.
 #include "kernels.hpp"
@@ -60,7 +64,9 @@ struct StencilIO {
         r.v[e] = valid ? ((CT)z.v[e] - zc) + beta * (CT)p.v[e] : (CT)0;
       }
     } else if constexpr (MODE == ST_APPLY) {
-      const V4<T> p = ld4_nt(a.p_in + o);
+      // a plain load: the direction was written just before by the
+      // preconditioner's last pass and is partly in the last-level cache
+      const V4<T> p = ld4(a.p_in + o);
 #pragma unroll
       for (int e = 0; e < 4; ++e) r.v[e] = (CT)p.v[e];
     } else {
