@@ -198,8 +198,9 @@ irlsu_status irlsu_params_default(irlsu_params* p, irlsu_precision prec);
  * current HIP device the plan allocates and fills
  *   fast form: the FFT twiddle tables of each side (about 3n/2 complex
  *     values per side -- the stage twiddles for power-of-two plans, the
- *     n/2-th roots of unity otherwise -- shared when N = M) and the
- *     Laplacian eigenvalues
+ *     n/2-th roots of unity otherwise -- and n/4 + 1 records of the
+ *     column pass's pair twiddles and eigenvalues, shared when N = M) and
+ *     the Laplacian eigenvalues
  *     2 - 2 cos(pi k / n) in FP64;
  *   dense form: the orthonormal DCT-II bases P_N, P_M and their transposes
  *     in the operand type, and the eigenvalues;
